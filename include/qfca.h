@@ -1,0 +1,167 @@
+/*
+ * qfca.h -- C ABI of libqfca, the MI355X (gfx950) implementation of the
+ * Quantized FCA score-map path: "Quantized FCA: Efficient Zero-Shot Texture
+ * Anomaly Detection" (Ardelean, Rueckbeil, Weyrich).
+ *
+ * Problem (Sec. 3, Eq. 1): one C-channel feature map F in R^{C x H x W} in,
+ * one per-pixel anomaly map A(x, y) out, zero-shot: every statistic comes
+ * from the image itself (Sec. 3.3) or, for served texture classes, from a
+ * class exemplar fitted once.
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments named X, bins, score, amap, w1, achan, resid are DEVICE
+ *     pointers owned by the caller (for instance torch tensors on cuda:N).
+ *     Arrays passed to qfca_model_create / read by qfca_model_read are HOST
+ *     pointers owned by the caller.  The library owns models and scratch.
+ *   - Feature maps are float32, channel-planar [C][H][W], row-major, densely
+ *     packed.  Bin maps are uint8 [C][H][W].  Score-like maps are float32
+ *     [H][W].
+ *   - Calls are stream-ordered on the context's HIP stream and return before
+ *     the GPU finishes, like HIP itself; outputs are valid once the stream is
+ *     synchronised.  qfca_fit_pca and qfca_fit_reference are synchronous.
+ *   - Arguments are validated before any launch; no exception or abort
+ *     crosses the ABI.  Every call returns a qfca_status; qfca_last_error()
+ *     gives a message for the calling thread's last failure.
+ *   - A context is used by one host thread at a time; models may be shared
+ *     by contexts on the same device.
+ *   - Score-side inputs are not checked for non-finite values; NaN or Inf in
+ *     X passed to qfca_quantize gives undefined bins.
+ */
+#ifndef QFCA_H
+#define QFCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QFCA_OK = 0,
+    QFCA_E_ARG = 1,          /* null pointer or out-of-range parameter */
+    QFCA_E_SHAPE = 2,        /* H, W inconsistent with the parameters (e.g. smaller than T) */
+    QFCA_E_NOMEM = 3,        /* device or host allocation failed */
+    QFCA_E_DEVICE = 4,       /* a HIP call failed; recreate the context */
+    QFCA_E_STATE = 5,        /* model not ready for this call (e.g. no reference yet) */
+    QFCA_E_NONFINITE = 6,    /* NaN or Inf met where the fit needs finite values */
+    QFCA_E_UNSUPPORTED = 7   /* parameters outside what this build implements */
+} qfca_status;
+
+enum { QFCA_PRE_NONE = 0,       /* plain QFCA: histogram the features as given */
+       QFCA_PRE_RESIDUAL = 1 }; /* QFCA+: histogram W - PCA^-1(PCA(W)), Sec. 3.3 */
+
+enum { QFCA_PREC_FP32 = 0,      /* projection in FP32 */
+       QFCA_PREC_BF16 = 1 };    /* projection on BF16 MFMA, FP32 accumulate */
+
+/* Method parameters.  Paper defaults: B = 16 bins (Sec. 4.5.1), k = 10
+ * principal components (Sec. 4.5.2), sigma_p = infinity (box association,
+ * the only one implemented), sigma_s = 1 (Sec. 4.5.4).
+ *   C        channels, 1..2048
+ *   k        principal components removed, 0..C-1 (ignored for PRE_NONE)
+ *   B        bins N of Sec. 3.1, 1..64
+ *   T        patch side, odd, 1..63
+ *   q_lo/hi  quantisation range as per-channel quantiles, 0 <= q_lo < q_hi <= 1
+ *   sigma_s  final Gaussian blur, 0 (none) .. 5 px
+ *   preproc  QFCA_PRE_*
+ *   proj_prec QFCA_PREC_* */
+typedef struct {
+    int32_t C, k, B, T;
+    float q_lo, q_hi, sigma_s;
+    int32_t preproc, proj_prec;
+} qfca_params;
+
+typedef struct qfca_ctx_s* qfca_ctx;
+typedef struct qfca_model_s* qfca_model;
+
+const char* qfca_status_str(qfca_status s);
+/* Message describing the calling thread's last failed call ("" if none). */
+const char* qfca_last_error(void);
+/* Library version, as 10000*major + 100*minor + patch. */
+int32_t qfca_version(void);
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream` (a
+ * hipStream_t, borrowed; NULL means the default stream).  The context owns a
+ * grow-only scratch arena and the tile-configuration cache. */
+qfca_status qfca_ctx_create(int32_t device, void* hip_stream, qfca_ctx* out);
+qfca_status qfca_ctx_set_stream(qfca_ctx ctx, void* hip_stream);
+qfca_status qfca_ctx_destroy(qfca_ctx ctx);
+
+/* Zero-shot fit on one image (Sec. 3.2, Sec. 3.3).  Synchronous.
+ * X: device [C][H][W] float32 with H, W >= T.  Computes, in order:
+ *   mean mu and covariance (FP64 on the GPU); the top-k eigenvectors V of the
+ *   covariance (host FP64 symmetric eigensolver, since a C x C problem is too
+ *   small for the GPU); the residual r = (x - mu) - V V^T (x - mu) with the
+ *   projection of params->proj_prec; per-channel type-7 quantiles q_lo, q_hi
+ *   of r (exact order statistics on the GPU) giving lo, hi, delta = (hi-lo)/B
+ *   and float32 edges lo + m delta; the bins; and the median reference: for
+ *   every bin i, cR(i) is the ceil(P/2)-th largest full-window cumulative
+ *   count among the P full T x T windows (the rank-wise lower median of the
+ *   patches, quantised after the median).
+ * On success *out is a new model (free it with qfca_model_destroy). */
+qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* params, const float* X,
+                         int32_t H, int32_t W, qfca_model* out);
+
+/* Build a model from host arrays, for instance one fitted elsewhere.
+ * mu [C], V [C][k] (row-major, column j = j-th principal axis), edges
+ * [C][B-1] float32 nondecreasing per channel (a channel of +inf edges is
+ * degenerate), delta [C] (bin width, feature units, >= 0), cR [C][B]
+ * cumulative reference histogram with cR[c][B-1] == T*T, nondecreasing, or
+ * NULL to leave the reference unset (then call qfca_fit_reference).  mu and V
+ * may be NULL when preproc == QFCA_PRE_NONE or k == 0. */
+qfca_status qfca_model_create(qfca_ctx ctx, const qfca_params* params, const float* mu,
+                              const float* V, const float* edges, const double* delta,
+                              const int32_t* cR, qfca_model* out);
+
+/* (Re)compute the model's median reference from device bins [C][H][W]
+ * (H, W >= T), exactly in integers (Sec. 3.2).  Synchronous. */
+qfca_status qfca_fit_reference(qfca_ctx ctx, qfca_model model, const uint8_t* bins,
+                               int32_t H, int32_t W);
+
+/* Quantisation (Sec. 3.1, Sec. 3.3).  X: device [C][H][W] float32.
+ * bins: device [C][H][W] uint8 out, bins = #{m : r >= edge_m} with r the
+ * residual (PRE_RESIDUAL) or the feature (PRE_NONE) in float32, compared
+ * against the float32 edges (a value equal to an edge goes to the upper bin).
+ * resid: optional device [C][H][W] float32 out (NULL to skip). */
+qfca_status qfca_quantize(qfca_ctx ctx, qfca_model model, const float* X, int32_t H,
+                          int32_t W, uint8_t* bins, float* resid);
+
+/* Patch statistics comparison, association, aggregation and blur
+ * (Sec. 3.1, Alg. 1, Sec. 4.5.4).  bins: device [C][H][W] uint8, every value
+ * < B.  For every pixel p the T x T window (clipped to the image) is
+ * histogrammed and compared with the reference by Algorithm 1 after scaling
+ * both to equal mass; each bin's error (bin units) is averaged over the
+ * windows that contain a pixel of that bin (sigma_p = infinity) and gathered
+ * at the pixel's own bin; channels are averaged with weight delta_c; the map
+ * is blurred with sigma_s (renormalised at the border).
+ *   score: device [H][W] float32 out (required)
+ *   amap:  device [H][W] float32 out, the map before the blur (nullable)
+ *   w1:    device [H][W] float32 out, channel mean of delta_c times the window
+ *          1-Wasserstein distance sum_k |cP_k - cR_k| / (n_p n_R) (nullable)
+ *   achan: device [C][H][W] float32 out, per-channel delta_c-weighted maps
+ *          before the channel mean (nullable)
+ * Requires a model with a reference (QFCA_E_STATE otherwise). */
+qfca_status qfca_score_map(qfca_ctx ctx, qfca_model model, const uint8_t* bins, int32_t H,
+                           int32_t W, float* score, float* amap, float* w1, float* achan);
+
+/* Model queries.  qfca_model_read copies one field to host memory:
+ *   field 0 mu [C] float32, 1 V [C][k] float32, 2 edges [C][B-1] float32,
+ *   3 delta [C] float64, 4 cR [C][B] int32, 5 eigenvalues [C] float64
+ *   (descending; fit only), 6 lo [C] float64, 7 hi [C] float64.
+ * bytes must equal the field size; QFCA_E_STATE if the field is not set. */
+qfca_status qfca_model_params(qfca_model model, qfca_params* out);
+qfca_status qfca_model_read(qfca_model model, int32_t field, void* host_dst, size_t bytes);
+qfca_status qfca_model_destroy(qfca_model model);
+
+/* The host FP64 symmetric eigensolver used by qfca_fit_pca (Householder
+ * tridiagonalisation, then implicit QL), exposed for testing.  A: host
+ * [n][n] row-major symmetric (destroyed); evals: host [n] out, descending;
+ * vecs: host [n][n] out, row-major, column j the unit eigenvector of
+ * evals[j] with its largest-magnitude entry positive.  Returns 0, or -1 if
+ * the iteration fails to converge or n < 1.  Needs no GPU. */
+int qfca_host_sym_eig(double* A, int32_t n, double* evals, double* vecs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QFCA_H */

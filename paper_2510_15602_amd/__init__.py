@@ -1,0 +1,291 @@
+"""Python binding of libqfca, the gfx950 implementation of the Quantized FCA
+score-map path (Ardelean, Rueckbeil, Weyrich, "Quantized FCA: Efficient
+Zero-Shot Texture Anomaly Detection").
+
+Argument marshalling only: every step runs in the HIP library.  The entry
+points keep the C names (qfca_fit_pca, qfca_quantize, qfca_score_map, ...);
+tensors are torch tensors on a HIP device, passed by pointer on the context's
+stream (by default torch's current stream).  There is no CPU fallback: if the
+library is not built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqfca.so")
+
+QFCA_PRE_NONE, QFCA_PRE_RESIDUAL = 0, 1
+QFCA_PREC_FP32, QFCA_PREC_BF16 = 0, 1
+
+STATUS = {0: "QFCA_OK", 1: "QFCA_E_ARG", 2: "QFCA_E_SHAPE", 3: "QFCA_E_NOMEM", 4: "QFCA_E_DEVICE",
+          5: "QFCA_E_STATE", 6: "QFCA_E_NONFINITE", 7: "QFCA_E_UNSUPPORTED"}
+
+# Symbols declared in include/qfca.h
+EXPORTS = ("qfca_status_str", "qfca_last_error", "qfca_version", "qfca_ctx_create",
+           "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca", "qfca_model_create",
+           "qfca_fit_reference", "qfca_quantize", "qfca_score_map", "qfca_model_params",
+           "qfca_model_read", "qfca_model_destroy", "qfca_host_sym_eig")
+
+
+class QfcaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_int32), ("k", ctypes.c_int32), ("B", ctypes.c_int32),
+                ("T", ctypes.c_int32), ("q_lo", ctypes.c_float), ("q_hi", ctypes.c_float),
+                ("sigma_s", ctypes.c_float), ("preproc", ctypes.c_int32),
+                ("proj_prec", ctypes.c_int32)]
+
+    @classmethod
+    def make(cls, C, k=10, B=16, T=9, q_lo=0.01, q_hi=0.99, sigma_s=1.0,
+             preproc=QFCA_PRE_RESIDUAL, proj_prec=QFCA_PREC_FP32):
+        return cls(int(C), int(k), int(B), int(T), float(q_lo), float(q_hi), float(sigma_s),
+                   int(preproc), int(proj_prec))
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libqfca.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        L.qfca_status_str.restype = ctypes.c_char_p
+        L.qfca_status_str.argtypes = [i32]
+        L.qfca_last_error.restype = ctypes.c_char_p
+        L.qfca_version.restype = i32
+        L.qfca_ctx_create.argtypes = [i32, P, ctypes.POINTER(P)]
+        L.qfca_ctx_set_stream.argtypes = [P, P]
+        L.qfca_ctx_destroy.argtypes = [P]
+        L.qfca_fit_pca.argtypes = [P, ctypes.POINTER(Params), P, i32, i32, ctypes.POINTER(P)]
+        L.qfca_model_create.argtypes = [P, ctypes.POINTER(Params), P, P, P, P, P, ctypes.POINTER(P)]
+        L.qfca_fit_reference.argtypes = [P, P, P, i32, i32]
+        L.qfca_quantize.argtypes = [P, P, P, i32, i32, P, P]
+        L.qfca_score_map.argtypes = [P, P, P, i32, i32, P, P, P, P]
+        L.qfca_model_params.argtypes = [P, ctypes.POINTER(Params)]
+        L.qfca_model_read.argtypes = [P, i32, P, sz]
+        L.qfca_model_destroy.argtypes = [P]
+        L.qfca_host_sym_eig.argtypes = [P, i32, P, P]
+        L.qfca_host_sym_eig.restype = i32
+        for name in ("qfca_ctx_create", "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca",
+                     "qfca_model_create", "qfca_fit_reference", "qfca_quantize", "qfca_score_map",
+                     "qfca_model_params", "qfca_model_read", "qfca_model_destroy"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise QfcaError(rc, lib().qfca_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev_tensor(t, dtype, name, ndim=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a HIP device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions")
+    return t
+
+
+class Context:
+    """A libqfca context on one device, issuing work on a HIP stream (torch's
+    current stream of that device unless given)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().qfca_ctx_create(self.device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().qfca_ctx_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().qfca_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+FIELDS = {"mu": (0, np.float32), "V": (1, np.float32), "edges": (2, np.float32),
+          "delta": (3, np.float64), "cR": (4, np.int32), "evals": (5, np.float64),
+          "lo": (6, np.float64), "hi": (7, np.float64)}
+
+
+class Model:
+    def __init__(self, handle):
+        self.handle = handle
+        p = Params()
+        _check(lib().qfca_model_params(handle, ctypes.byref(p)))
+        self.params = p
+
+    def read(self, field: str) -> np.ndarray:
+        fid, dt = FIELDS[field]
+        p = self.params
+        shape = {"mu": (p.C,), "V": (p.C, p.k), "edges": (p.C, max(p.B - 1, 0)), "delta": (p.C,),
+                 "cR": (p.C, p.B), "evals": (p.C,), "lo": (p.C,), "hi": (p.C,)}[field]
+        out = np.zeros(shape, dt)
+        _check(lib().qfca_model_read(self.handle, fid, out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().qfca_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+
+def qfca_fit_pca(ctx: Context, params: Params, X) -> Model:
+    import torch
+    X = _dev_tensor(X, torch.float32, "X", 3)
+    C, H, W = X.shape
+    if C != params.C:
+        raise ValueError("X.shape[0] != params.C")
+    h = ctypes.c_void_p()
+    _check(lib().qfca_fit_pca(ctx.handle, ctypes.byref(params), _ptr(X), H, W, ctypes.byref(h)))
+    return Model(h)
+
+
+def qfca_model_create(ctx: Context, params: Params, mu, V, edges, delta, cR=None) -> Model:
+    def host(a, dt):
+        return None if a is None else np.ascontiguousarray(a, dtype=dt)
+    mu, V, edges = host(mu, np.float32), host(V, np.float32), host(edges, np.float32)
+    delta, cR = host(delta, np.float64), host(cR, np.int32)
+    C, B, k = params.C, params.B, params.k
+    if edges is not None and edges.size != C * max(B - 1, 0):
+        raise ValueError("edges must be [C, B-1]")
+    if delta is None or delta.size != C:
+        raise ValueError("delta must be [C]")
+    if cR is not None and cR.size != C * B:
+        raise ValueError("cR must be [C, B]")
+    if params.preproc == QFCA_PRE_RESIDUAL and k > 0:
+        if mu is None or V is None or mu.size != C or V.size != C * k:
+            raise ValueError("mu [C] and V [C, k] are required")
+
+    def p(a):
+        return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    h = ctypes.c_void_p()
+    _check(lib().qfca_model_create(ctx.handle, ctypes.byref(params), p(mu), p(V), p(edges), p(delta),
+                                   p(cR), ctypes.byref(h)))
+    return Model(h)
+
+
+def qfca_fit_reference(ctx: Context, model: Model, bins):
+    import torch
+    bins = _dev_tensor(bins, torch.uint8, "bins", 3)
+    _check(lib().qfca_fit_reference(ctx.handle, model.handle, _ptr(bins), bins.shape[1], bins.shape[2]))
+
+
+def qfca_quantize(ctx: Context, model: Model, X, bins=None, resid=None, want_bins=True):
+    """Returns (bins uint8 [C,H,W] or None, resid float32 [C,H,W] or None).
+    Pass resid=True to allocate the residual output."""
+    import torch
+    X = _dev_tensor(X, torch.float32, "X", 3)
+    C, H, W = X.shape
+    if C != model.params.C:
+        raise ValueError("X.shape[0] != model C")
+    if bins is None and want_bins:
+        bins = torch.empty((C, H, W), dtype=torch.uint8, device=X.device)
+    if resid is True:
+        resid = torch.empty((C, H, W), dtype=torch.float32, device=X.device)
+    elif resid is False:
+        resid = None
+    if bins is not None:
+        _dev_tensor(bins, torch.uint8, "bins", 3)
+    if resid is not None:
+        _dev_tensor(resid, torch.float32, "resid", 3)
+    _check(lib().qfca_quantize(ctx.handle, model.handle, _ptr(X), H, W, _ptr(bins), _ptr(resid)))
+    return bins, resid
+
+
+@dataclass
+class ScoreMaps:
+    score: object
+    amap: object = None
+    w1: object = None
+    achan: object = None
+
+
+def qfca_score_map(ctx: Context, model: Model, bins, amap=False, w1=False, achan=False,
+                   out: ScoreMaps | None = None) -> ScoreMaps:
+    import torch
+    bins = _dev_tensor(bins, torch.uint8, "bins", 3)
+    C, H, W = bins.shape
+    if C != model.params.C:
+        raise ValueError("bins.shape[0] != model C")
+    dev = bins.device
+    if out is None:
+        out = ScoreMaps(torch.empty((H, W), dtype=torch.float32, device=dev))
+        if amap:
+            out.amap = torch.empty((H, W), dtype=torch.float32, device=dev)
+        if w1:
+            out.w1 = torch.empty((H, W), dtype=torch.float32, device=dev)
+        if achan:
+            out.achan = torch.empty((C, H, W), dtype=torch.float32, device=dev)
+    _check(lib().qfca_score_map(ctx.handle, model.handle, _ptr(bins), H, W, _ptr(out.score),
+                                _ptr(out.amap), _ptr(out.w1), _ptr(out.achan)))
+    return out
+
+
+def host_sym_eig(A: np.ndarray):
+    """The library's host eigensolver (no GPU needed): (evals desc, vecs)."""
+    A = np.array(A, dtype=np.float64, order="C", copy=True)
+    n = A.shape[0]
+    ev = np.zeros(n)
+    V = np.zeros((n, n))
+    rc = lib().qfca_host_sym_eig(A.ctypes.data_as(ctypes.c_void_p), n, ev.ctypes.data_as(ctypes.c_void_p),
+                                 V.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise QfcaError(4, "eigensolver failed")
+    return ev, V
+
+
+# short aliases
+fit_pca = qfca_fit_pca
+model_create = qfca_model_create
+fit_reference = qfca_fit_reference
+quantize = qfca_quantize
+score_map = qfca_score_map

@@ -1,0 +1,573 @@
+// C ABI of libqfca: argument validation, contexts, models and the order of
+// kernel launches for the fit, quantisation and score-map calls.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "qfca_internal.h"
+
+namespace qfca {
+namespace {
+thread_local std::string g_err;
+}
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace qfca
+
+using namespace qfca;
+
+enum Slot {
+    SL_ACHAN = 0, SL_W1CHAN, SL_AMAP, SL_W1TMP, SL_RESID, SL_BINS, SL_COUNTS, SL_SEL,
+    SL_COV, SL_MU, SL_RANKS, SL_CR, SL_COUNT
+};
+
+struct qfca_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DevBuf scratch[SL_COUNT];
+    std::map<long long, ScoreTile> tiles;  // tile-configuration cache
+};
+
+struct qfca_model_s {
+    qfca_params p{};
+    int device = 0;
+    int KP = 0;  // projection width (k padded to 8/16/32/64)
+    int Bp = 8;  // lanes per channel in the score kernel
+    int m = 1;   // T*T
+    std::vector<double> mu, V, evals, lo, hi, delta;
+    std::vector<float> edges;
+    std::vector<int32_t> cR;
+    bool has_ref = false, has_evals = false, has_lohi = false;
+    float* d_mu = nullptr;
+    float* d_V = nullptr;
+    uint16_t* d_Vbf = nullptr;
+    float* d_edges = nullptr;
+    float* d_lo = nullptr;
+    float* d_invd = nullptr;
+    double* d_delta = nullptr;
+    int32_t* d_cR = nullptr;
+    ScoreTables tab;
+    std::vector<void*> owned;
+    ~qfca_model_s() {
+        for (void* q : owned) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+qfca_status fail(qfca_status s, const std::string& msg) {
+    set_error(msg);
+    return s;
+}
+
+qfca_status hip_fail(hipError_t e, const char* where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(e == hipErrorOutOfMemory ? QFCA_E_NOMEM : QFCA_E_DEVICE, m);
+}
+
+#define HIP_TRY(expr)                                       \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);   \
+    } while (0)
+
+qfca_status check_params(const qfca_params* p) {
+    if (!p) return fail(QFCA_E_ARG, "params is NULL");
+    if (p->C < 1 || p->C > 2048) return fail(QFCA_E_ARG, "C must be in [1, 2048]");
+    if (p->B < 1 || p->B > 64) return fail(QFCA_E_UNSUPPORTED, "B must be in [1, 64]");
+    if (p->T < 1 || p->T > 63 || (p->T % 2) == 0) return fail(QFCA_E_UNSUPPORTED, "T must be odd, 1..63");
+    if (p->preproc != QFCA_PRE_NONE && p->preproc != QFCA_PRE_RESIDUAL)
+        return fail(QFCA_E_ARG, "unknown preproc");
+    if (p->proj_prec != QFCA_PREC_FP32 && p->proj_prec != QFCA_PREC_BF16)
+        return fail(QFCA_E_ARG, "unknown proj_prec");
+    if (p->preproc == QFCA_PRE_RESIDUAL && (p->k < 0 || p->k > 64 || p->k > p->C - 1))
+        return fail(QFCA_E_UNSUPPORTED, "k must be in [0, min(64, C-1)]");
+    if (!(p->q_lo >= 0.f && p->q_lo < p->q_hi && p->q_hi <= 1.f))
+        return fail(QFCA_E_ARG, "need 0 <= q_lo < q_hi <= 1");
+    if (!(p->sigma_s >= 0.f && p->sigma_s <= 5.f)) return fail(QFCA_E_ARG, "sigma_s must be in [0, 5]");
+    return QFCA_OK;
+}
+
+qfca_status check_shape(int H, int W, int C) {
+    if (H < 1 || W < 1) return fail(QFCA_E_SHAPE, "H and W must be >= 1");
+    if ((long long)H * W > (1LL << 30)) return fail(QFCA_E_SHAPE, "H*W too large");
+    if ((long long)H * W * C > (1LL << 40)) return fail(QFCA_E_SHAPE, "C*H*W too large");
+    return QFCA_OK;
+}
+
+template <class Tp>
+hipError_t scratch(qfca_ctx ctx, Slot s, size_t bytes, Tp** out) {
+    DevBuf& b = ctx->scratch[s];
+    if (b.bytes < bytes) {
+        if (b.p) {
+            hipError_t e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) return e;
+            (void)hipFree(b.p);
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        hipError_t e = hipMalloc(&b.p, bytes);
+        if (e != hipSuccess) return e;
+        b.bytes = bytes;
+    }
+    *out = (Tp*)b.p;
+    return hipSuccess;
+}
+
+template <class Tp>
+hipError_t upload(qfca_model m, Tp** dst, const Tp* src, size_t n) {
+    if (!*dst) {
+        hipError_t e = hipMalloc((void**)dst, std::max<size_t>(n, 1) * sizeof(Tp));
+        if (e != hipSuccess) return e;
+        m->owned.push_back(*dst);
+    }
+    if (n) return hipMemcpy(*dst, src, n * sizeof(Tp), hipMemcpyHostToDevice);
+    return hipSuccess;
+}
+
+uint16_t f32_to_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);  // inf / nan
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+int pow2_at_least(int v, int lo) {
+    int p = lo;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Upload mu and V (float32, V padded to KP columns, plus a bf16 copy).
+qfca_status upload_projection(qfca_model m) {
+    const int C = m->p.C, k = m->p.k;
+    const bool pre = m->p.preproc == QFCA_PRE_RESIDUAL;
+    m->KP = (!pre || k == 0) ? 0 : (k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64);
+    std::vector<float> muf(C, 0.f), Vf((size_t)C * std::max(m->KP, 1), 0.f);
+    std::vector<uint16_t> Vb(Vf.size(), 0);
+    if (pre) {
+        for (int c = 0; c < C; ++c) muf[c] = (float)m->mu[c];
+        for (int c = 0; c < C; ++c)
+            for (int j = 0; j < k; ++j) {
+                Vf[(size_t)c * m->KP + j] = (float)m->V[(size_t)c * k + j];
+                Vb[(size_t)c * m->KP + j] = f32_to_bf16(Vf[(size_t)c * m->KP + j]);
+            }
+    }
+    HIP_TRY(upload(m, &m->d_mu, muf.data(), muf.size()));
+    HIP_TRY(upload(m, &m->d_V, Vf.data(), Vf.size()));
+    HIP_TRY(upload(m, &m->d_Vbf, Vb.data(), Vb.size()));
+    return QFCA_OK;
+}
+
+// Upload edges, lo, 1/delta and delta.
+qfca_status upload_quant(qfca_model m) {
+    const int C = m->p.C, B = m->p.B;
+    std::vector<float> lof(C), invd(C);
+    for (int c = 0; c < C; ++c) {
+        lof[c] = (float)m->lo[c];
+        invd[c] = m->delta[c] > 0.0 ? (float)(1.0 / m->delta[c]) : 0.f;
+    }
+    std::vector<float> e = m->edges;
+    if (e.empty()) e.push_back(0.f);
+    HIP_TRY(upload(m, &m->d_edges, e.data(), e.size()));
+    HIP_TRY(upload(m, &m->d_lo, lof.data(), lof.size()));
+    HIP_TRY(upload(m, &m->d_invd, invd.data(), invd.size()));
+    HIP_TRY(upload(m, &m->d_delta, m->delta.data(), m->delta.size()));
+    (void)B;
+    return QFCA_OK;
+}
+
+// Reference-dependent tables of the score kernel (see ScoreTables).
+qfca_status upload_tables(qfca_model m) {
+    const int C = m->p.C, B = m->p.B, T = m->p.T;
+    const int mm = T * T, Bp = m->Bp;
+    std::vector<int2> psig((size_t)C * (mm + 1));
+    std::vector<int32_t> cRm1((size_t)C * Bp, 0), Dm1((size_t)C * Bp, 0), cRl((size_t)C * Bp, 0);
+    for (int c = 0; c < C; ++c) {
+        const int32_t* cr = &m->cR[(size_t)c * B];
+        int2* ps = &psig[(size_t)c * (mm + 1)];
+        int kk = 0;  // #{k < B-1 : cR_k <= t}
+        long long psi = 0;
+        for (int t = 0; t <= mm; ++t) {
+            while (kk < B - 1 && cr[kk] <= t) ++kk;
+            ps[t] = make_int2((int)psi, kk);
+            psi += kk;
+        }
+        for (int i = 0; i < Bp; ++i) {
+            if (i >= 1 && i < B) {
+                cRm1[(size_t)c * Bp + i] = cr[i - 1];
+                Dm1[(size_t)c * Bp + i] = ps[cr[i - 1]].x;
+            }
+            if (i < B - 1) cRl[(size_t)c * Bp + i] = cr[i];
+        }
+    }
+    std::vector<float> rcp(mm + 1);
+    rcp[0] = 0.f;
+    for (int t = 1; t <= mm; ++t) rcp[t] = (float)(1.0 / (double)t);
+    HIP_TRY(upload(m, &m->tab.psig, psig.data(), psig.size()));
+    HIP_TRY(upload(m, &m->tab.cRm1, cRm1.data(), cRm1.size()));
+    HIP_TRY(upload(m, &m->tab.Dm1, Dm1.data(), Dm1.size()));
+    HIP_TRY(upload(m, &m->tab.cRl, cRl.data(), cRl.size()));
+    HIP_TRY(upload(m, &m->tab.rcp, rcp.data(), rcp.size()));
+    HIP_TRY(upload(m, &m->d_cR, m->cR.data(), m->cR.size()));
+    m->tab.delta = m->d_delta;
+    m->tab.Bp = Bp;
+    m->has_ref = true;
+    return QFCA_OK;
+}
+
+qfca_model new_model(qfca_ctx ctx, const qfca_params* p) {
+    qfca_model m = new (std::nothrow) qfca_model_s();
+    if (!m) return nullptr;
+    m->p = *p;
+    m->device = ctx->device;
+    m->m = p->T * p->T;
+    m->Bp = pow2_at_least(p->B, 8);
+    return m;
+}
+
+ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
+    const long long key = (((long long)T * 128 + B) * 4096 + std::min(W, 4095)) * 4096 + std::min(H, 4095);
+    auto it = ctx->tiles.find(key);
+    if (it != ctx->tiles.end()) return it->second;
+    ScoreTile t;
+    t.S = 64 / Bp;
+    t.Ws = 64;
+    t.Hb = 64;
+    while (score_lds_bytes(T, Bp, t.S, t.Ws) > 65536 && t.S > 1) t.S >>= 1;
+    while (score_lds_bytes(T, Bp, t.S, t.Ws) > 65536 && t.Ws > 8) t.Ws >>= 1;
+    (void)C;
+    ctx->tiles[key] = t;
+    return t;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* qfca_status_str(qfca_status s) {
+    switch (s) {
+        case QFCA_OK: return "ok";
+        case QFCA_E_ARG: return "invalid argument";
+        case QFCA_E_SHAPE: return "invalid shape";
+        case QFCA_E_NOMEM: return "out of memory";
+        case QFCA_E_DEVICE: return "device error";
+        case QFCA_E_STATE: return "invalid state";
+        case QFCA_E_NONFINITE: return "non-finite input";
+        case QFCA_E_UNSUPPORTED: return "unsupported parameters";
+    }
+    return "unknown status";
+}
+
+const char* qfca_last_error(void) { return g_err.c_str(); }
+
+int32_t qfca_version(void) { return 100; }
+
+qfca_status qfca_ctx_create(int32_t device, void* hip_stream, qfca_ctx* out) {
+    if (!out) return fail(QFCA_E_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(QFCA_E_ARG, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    qfca_ctx c = new (std::nothrow) qfca_ctx_s();
+    if (!c) return fail(QFCA_E_NOMEM, "context allocation failed");
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return QFCA_OK;
+}
+
+qfca_status qfca_ctx_set_stream(qfca_ctx ctx, void* hip_stream) {
+    if (!ctx) return fail(QFCA_E_ARG, "ctx is NULL");
+    ctx->stream = (hipStream_t)hip_stream;
+    return QFCA_OK;
+}
+
+qfca_status qfca_ctx_destroy(qfca_ctx ctx) {
+    if (!ctx) return QFCA_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& b : ctx->scratch)
+        if (b.p) (void)hipFree(b.p);
+    delete ctx;
+    return QFCA_OK;
+}
+
+qfca_status qfca_model_destroy(qfca_model m) {
+    if (!m) return QFCA_OK;
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    delete m;
+    return QFCA_OK;
+}
+
+qfca_status qfca_model_params(qfca_model m, qfca_params* out) {
+    if (!m || !out) return fail(QFCA_E_ARG, "NULL argument");
+    *out = m->p;
+    return QFCA_OK;
+}
+
+qfca_status qfca_model_read(qfca_model m, int32_t field, void* dst, size_t bytes) {
+    if (!m || !dst) return fail(QFCA_E_ARG, "NULL argument");
+    const int C = m->p.C, k = m->p.k, B = m->p.B;
+    std::vector<float> tmp;
+    const void* src = nullptr;
+    size_t need = 0;
+    bool ok = true;
+    switch (field) {
+        case 0:
+            tmp.resize(C);
+            for (int c = 0; c < C; ++c) tmp[c] = m->mu.empty() ? 0.f : (float)m->mu[c];
+            src = tmp.data(); need = (size_t)C * 4; break;
+        case 1:
+            tmp.resize((size_t)C * k);
+            ok = m->p.preproc == QFCA_PRE_RESIDUAL && m->V.size() == tmp.size();
+            for (size_t i = 0; ok && i < tmp.size(); ++i) tmp[i] = (float)m->V[i];
+            src = tmp.data(); need = tmp.size() * 4; break;
+        case 2: src = m->edges.data(); need = (size_t)C * (B - 1) * 4; break;
+        case 3: src = m->delta.data(); need = (size_t)C * 8; break;
+        case 4: ok = m->has_ref; src = m->cR.data(); need = (size_t)C * B * 4; break;
+        case 5: ok = m->has_evals; src = m->evals.data(); need = (size_t)C * 8; break;
+        case 6: ok = m->has_lohi; src = m->lo.data(); need = (size_t)C * 8; break;
+        case 7: ok = m->has_lohi; src = m->hi.data(); need = (size_t)C * 8; break;
+        default: return fail(QFCA_E_ARG, "unknown field");
+    }
+    if (!ok) return fail(QFCA_E_STATE, "field not set on this model");
+    if (bytes != need) return fail(QFCA_E_ARG, "byte count does not match the field size");
+    if (need) memcpy(dst, src, need);
+    return QFCA_OK;
+}
+
+qfca_status qfca_model_create(qfca_ctx ctx, const qfca_params* p, const float* mu, const float* V,
+                              const float* edges, const double* delta, const int32_t* cR,
+                              qfca_model* out) {
+    if (!ctx || !out) return fail(QFCA_E_ARG, "NULL argument");
+    *out = nullptr;
+    qfca_status st = check_params(p);
+    if (st != QFCA_OK) return st;
+    const int C = p->C, k = p->k, B = p->B, T = p->T;
+    const bool pre = p->preproc == QFCA_PRE_RESIDUAL;
+    if ((B > 1 && !edges) || !delta) return fail(QFCA_E_ARG, "edges and delta are required");
+    if (pre && k > 0 && (!mu || !V)) return fail(QFCA_E_ARG, "mu and V are required for k > 0");
+    for (int c = 0; c < C; ++c) {
+        if (!(delta[c] >= 0.0) || !isfinite(delta[c])) return fail(QFCA_E_ARG, "delta must be finite, >= 0");
+        for (int i = 1; i + 1 < B; ++i)
+            if (!(edges[(size_t)c * (B - 1) + i] >= edges[(size_t)c * (B - 1) + i - 1]))
+                return fail(QFCA_E_ARG, "edges must be nondecreasing per channel");
+    }
+    if (cR) {
+        for (int c = 0; c < C; ++c) {
+            if (cR[(size_t)c * B + B - 1] != T * T) return fail(QFCA_E_ARG, "cR[c][B-1] must equal T*T");
+            for (int i = 0; i < B; ++i) {
+                const int32_t v = cR[(size_t)c * B + i];
+                if (v < 0 || (i > 0 && v < cR[(size_t)c * B + i - 1]))
+                    return fail(QFCA_E_ARG, "cR must be nondecreasing and >= 0");
+            }
+        }
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::unique_ptr<qfca_model_s> m(new_model(ctx, p));
+    if (!m) return fail(QFCA_E_NOMEM, "model allocation failed");
+    m->mu.assign(C, 0.0);
+    if (pre) {
+        if (mu)
+            for (int c = 0; c < C; ++c) m->mu[c] = mu[c];
+        m->V.assign((size_t)C * k, 0.0);
+        for (size_t i = 0; i < m->V.size(); ++i) m->V[i] = V[i];
+    }
+    if (B > 1) m->edges.assign(edges, edges + (size_t)C * (B - 1));
+    m->delta.assign(delta, delta + C);
+    m->lo.assign(C, 0.0);
+    for (int c = 0; c < C; ++c)
+        m->lo[c] = (B > 1 && m->delta[c] > 0.0) ? (double)m->edges[(size_t)c * (B - 1)] - m->delta[c] : 0.0;
+    if ((st = upload_projection(m.get())) != QFCA_OK) return st;
+    if ((st = upload_quant(m.get())) != QFCA_OK) return st;
+    if (cR) {
+        m->cR.assign(cR, cR + (size_t)C * B);
+        if ((st = upload_tables(m.get())) != QFCA_OK) return st;
+    }
+    *out = m.release();
+    return QFCA_OK;
+}
+
+qfca_status qfca_quantize(qfca_ctx ctx, qfca_model m, const float* X, int32_t H, int32_t W,
+                          uint8_t* bins, float* resid) {
+    if (!ctx || !m || !X || (!bins && !resid)) return fail(QFCA_E_ARG, "NULL argument");
+    qfca_status st = check_shape(H, W, m->p.C);
+    if (st != QFCA_OK) return st;
+    if (m->device != ctx->device) return fail(QFCA_E_ARG, "model and context are on different devices");
+    HIP_TRY(hipSetDevice(ctx->device));
+    ProjLaunch L;
+    L.X = X; L.C = m->p.C; L.N = H * W; L.k = m->p.k; L.B = m->p.B;
+    L.preproc = m->p.preproc; L.prec = m->p.proj_prec;
+    L.mu = m->d_mu; L.V = m->d_V; L.Vbf = m->d_Vbf; L.edges = m->d_edges; L.lo = m->d_lo;
+    L.inv_delta = m->d_invd; L.bins = bins; L.resid = resid;
+    HIP_TRY(launch_proj(L, ctx->stream));
+    return QFCA_OK;
+}
+
+qfca_status qfca_fit_reference(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W) {
+    if (!ctx || !m || !bins) return fail(QFCA_E_ARG, "NULL argument");
+    qfca_status st = check_shape(H, W, m->p.C);
+    if (st != QFCA_OK) return st;
+    const int C = m->p.C, B = m->p.B, T = m->p.T, mm = T * T;
+    if (H < T || W < T) return fail(QFCA_E_SHAPE, "the reference needs H, W >= T");
+    HIP_TRY(hipSetDevice(ctx->device));
+    uint32_t* counts = nullptr;
+    int32_t* dcR = nullptr;
+    HIP_TRY(scratch(ctx, SL_COUNTS, (size_t)C * B * (mm + 1) * 4, &counts));
+    HIP_TRY(scratch(ctx, SL_CR, (size_t)C * B * 4, &dcR));
+    HIP_TRY(launch_refcount(bins, C, H, W, T, B, counts, ctx->stream));
+    const long long P = (long long)(H - T + 1) * (W - T + 1);
+    HIP_TRY(launch_refselect(counts, C, B, mm, (P + 1) / 2, dcR, ctx->stream));
+    m->cR.assign((size_t)C * B, 0);
+    HIP_TRY(hipMemcpyAsync(m->cR.data(), dcR, (size_t)C * B * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return upload_tables(m);
+}
+
+qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int32_t H, int32_t W,
+                         qfca_model* out) {
+    if (!ctx || !X || !out) return fail(QFCA_E_ARG, "NULL argument");
+    *out = nullptr;
+    qfca_status st = check_params(p);
+    if (st != QFCA_OK) return st;
+    if ((st = check_shape(H, W, p->C)) != QFCA_OK) return st;
+    if (H < p->T || W < p->T) return fail(QFCA_E_SHAPE, "the fit needs H, W >= T");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int C = p->C, k = p->k, B = p->B;
+    const long N = (long)H * W;
+    const bool pre = p->preproc == QFCA_PRE_RESIDUAL;
+    std::unique_ptr<qfca_model_s> m(new_model(ctx, p));
+    if (!m) return fail(QFCA_E_NOMEM, "model allocation failed");
+    hipStream_t s = ctx->stream;
+
+    // 1. mean (also the finiteness check) and covariance, FP64 on the GPU
+    double* dmu = nullptr;
+    HIP_TRY(scratch(ctx, SL_MU, (size_t)C * 8, &dmu));
+    HIP_TRY(launch_mean(X, C, N, dmu, s));
+    m->mu.assign(C, 0.0);
+    HIP_TRY(hipMemcpyAsync(m->mu.data(), dmu, (size_t)C * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int c = 0; c < C; ++c)
+        if (!isfinite(m->mu[c])) return fail(QFCA_E_NONFINITE, "non-finite value in the features");
+    if (pre) {
+        std::vector<double> cov((size_t)C * C), vecs((size_t)C * C);
+        double* dcov = nullptr;
+        HIP_TRY(scratch(ctx, SL_COV, (size_t)C * C * 8, &dcov));
+        HIP_TRY(launch_cov(X, C, N, dmu, dcov, s));
+        HIP_TRY(hipMemcpyAsync(cov.data(), dcov, cov.size() * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        m->evals.assign(C, 0.0);
+        // 2. eigenvectors of the k largest eigenvalues (host, FP64)
+        if (sym_eig(cov.data(), C, m->evals.data(), vecs.data()) != 0)
+            return fail(QFCA_E_DEVICE, "eigensolver did not converge");
+        m->has_evals = true;
+        m->V.assign((size_t)C * k, 0.0);
+        for (int c = 0; c < C; ++c)
+            for (int j = 0; j < k; ++j) m->V[(size_t)c * k + j] = vecs[(size_t)c * C + j];
+    } else {
+        std::fill(m->mu.begin(), m->mu.end(), 0.0);
+    }
+    if ((st = upload_projection(m.get())) != QFCA_OK) return st;
+
+    // 3. residual and its per-channel type-7 quantiles (exact order statistics)
+    float* resid = nullptr;
+    HIP_TRY(scratch(ctx, SL_RESID, (size_t)C * N * 4, &resid));
+    {
+        ProjLaunch L;
+        L.X = X; L.C = C; L.N = (int)N; L.k = k; L.B = B; L.preproc = p->preproc;
+        L.prec = p->proj_prec; L.mu = m->d_mu; L.V = m->d_V; L.Vbf = m->d_Vbf;
+        L.edges = nullptr; L.lo = nullptr; L.inv_delta = nullptr; L.bins = nullptr; L.resid = resid;
+        HIP_TRY(launch_proj(L, s));
+    }
+    const double hq[2] = {(double)(N - 1) * (double)p->q_lo, (double)(N - 1) * (double)p->q_hi};
+    long long ranks[4];
+    for (int q = 0; q < 2; ++q) {
+        const long long f = (long long)floor(hq[q]);
+        ranks[2 * q] = f;
+        ranks[2 * q + 1] = std::min<long long>(f + 1, N - 1);
+    }
+    long long* dranks = nullptr;
+    float* dsel = nullptr;
+    HIP_TRY(scratch(ctx, SL_RANKS, sizeof(ranks), &dranks));
+    HIP_TRY(scratch(ctx, SL_SEL, (size_t)C * 4 * 4, &dsel));
+    HIP_TRY(hipMemcpyAsync(dranks, ranks, sizeof(ranks), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_select(resid, C, N, dranks, 4, dsel, s));
+    std::vector<float> sel((size_t)C * 4);
+    HIP_TRY(hipMemcpyAsync(sel.data(), dsel, sel.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    m->lo.assign(C, 0.0);
+    m->hi.assign(C, 0.0);
+    m->delta.assign(C, 0.0);
+    m->edges.assign((size_t)C * (B - 1), 0.f);
+    for (int c = 0; c < C; ++c) {
+        double qv[2];
+        for (int q = 0; q < 2; ++q) {
+            const double a = sel[(size_t)c * 4 + 2 * q], b = sel[(size_t)c * 4 + 2 * q + 1];
+            const double f = floor(hq[q]);
+            qv[q] = (ranks[2 * q] + 1 < N) ? a + (hq[q] - f) * (b - a) : a;
+        }
+        if (!isfinite(qv[0]) || !isfinite(qv[1])) return fail(QFCA_E_NONFINITE, "non-finite residual");
+        m->lo[c] = qv[0];
+        m->hi[c] = qv[1];
+        if (!(qv[1] > qv[0])) {
+            m->delta[c] = 0.0;
+            for (int i = 1; i < B; ++i) m->edges[(size_t)c * (B - 1) + i - 1] = INFINITY;
+        } else {
+            const double d = (qv[1] - qv[0]) / (double)B;
+            m->delta[c] = d;
+            for (int i = 1; i < B; ++i) m->edges[(size_t)c * (B - 1) + i - 1] = (float)(qv[0] + (double)i * d);
+        }
+    }
+    m->has_lohi = true;
+    if ((st = upload_quant(m.get())) != QFCA_OK) return st;
+
+    // 4. bins with the final edges, then the median reference
+    uint8_t* bins = nullptr;
+    HIP_TRY(scratch(ctx, SL_BINS, (size_t)C * N, &bins));
+    if ((st = qfca_quantize(ctx, m.get(), X, H, W, bins, nullptr)) != QFCA_OK) return st;
+    if ((st = qfca_fit_reference(ctx, m.get(), bins, H, W)) != QFCA_OK) return st;
+    *out = m.release();
+    return QFCA_OK;
+}
+
+qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
+                           float* score, float* amap, float* w1, float* achan) {
+    if (!ctx || !m || !bins || !score) return fail(QFCA_E_ARG, "NULL argument");
+    qfca_status st = check_shape(H, W, m->p.C);
+    if (st != QFCA_OK) return st;
+    if (!m->has_ref) return fail(QFCA_E_STATE, "model has no reference");
+    if (m->device != ctx->device) return fail(QFCA_E_ARG, "model and context are on different devices");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int C = m->p.C;
+    const size_t N = (size_t)H * W;
+    hipStream_t s = ctx->stream;
+    float* ach = achan;
+    if (!ach) HIP_TRY(scratch(ctx, SL_ACHAN, (size_t)C * N * 4, &ach));
+    float* w1ch = nullptr;
+    float* w1o = w1;
+    if (w1) HIP_TRY(scratch(ctx, SL_W1CHAN, (size_t)C * N * 4, &w1ch));
+    float* am = amap;
+    if (!am) HIP_TRY(scratch(ctx, SL_AMAP, N * 4, &am));
+    ScoreLaunch L;
+    L.bins = bins; L.C = C; L.H = H; L.W = W; L.T = m->p.T; L.B = m->p.B;
+    L.tab = m->tab;
+    L.achan = ach; L.w1chan = w1ch;
+    L.tile = choose_tile(ctx, C, H, W, m->p.T, m->p.B, m->Bp);
+    HIP_TRY(launch_score(L, s));
+    HIP_TRY(launch_chanmean(ach, w1ch, C, (int)N, am, w1o, s));
+    HIP_TRY(launch_blur(am, H, W, m->p.sigma_s, score, s));
+    return QFCA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,379 @@
+// Fit-side kernels for gfx950: mean and covariance of the features (PCA of
+// Sec. 3.3, FP64 accumulation), exact per-channel order statistics for the
+// quantisation range (Sec. 3.1), the median reference of Sec. 3.2 as an
+// integer selection over full-window cumulative counts, and the projection +
+// quantisation kernel (residual W - PCA^-1(PCA(W)) then the bin index).
+#include <algorithm>
+
+#include "qfca_internal.h"
+
+namespace qfca {
+namespace {
+
+// ------------------------------------------------------------------------
+// Mean: one block per channel, FP64 tree reduction in a fixed order.
+__global__ __launch_bounds__(256) void k_mean(const float* __restrict__ X, long N,
+                                              double* __restrict__ mu) {
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    const float* x = X + (size_t)c * N;
+    double s = 0.0;
+    for (long i = threadIdx.x; i < N; i += 256) s += (double)x[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) mu[c] = red[0] / (double)N;
+}
+
+// Covariance partials: block (tile ta, tile tb >= ta, chunk) accumulates
+// sum_i (x_a - mu_a)(x_b - mu_b) over its pixel chunk for a 64 x 64 tile in
+// FP64 (each thread a 4 x 4 micro-tile).  Partials are reduced over chunks
+// in a fixed order by k_cov_reduce (deterministic).
+constexpr int CT = 64;   // tile side
+constexpr int CK = 16;   // pixels per LDS stage
+
+__global__ __launch_bounds__(256) void k_cov_partial(const float* __restrict__ X, int C, long N,
+                                                     const double* __restrict__ mu, int ntile,
+                                                     long chunk, double* __restrict__ part) {
+    __shared__ double As[CK][CT + 1];
+    __shared__ double Bs[CK][CT + 1];
+    // decode upper-triangular tile pair
+    int pair = blockIdx.x, ta = 0;
+    while (pair >= ntile - ta) { pair -= ntile - ta; ++ta; }
+    const int tb = ta + pair;
+    const long i0 = (long)blockIdx.y * chunk;
+    const long i1 = min(N, i0 + chunk);
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4];
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (long ib = i0; ib < i1; ib += CK) {
+        for (int t = threadIdx.x; t < CK * CT; t += 256) {
+            const int kk = t % CK, row = t / CK;
+            const long i = ib + kk;
+            const int ca = ta * CT + row, cb = tb * CT + row;
+            As[kk][row] = (i < i1 && ca < C) ? (double)X[(size_t)ca * N + i] - mu[ca] : 0.0;
+            Bs[kk][row] = (i < i1 && cb < C) ? (double)X[(size_t)cb * N + i] - mu[cb] : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < CK; ++kk) {
+            double av[4], bv[4];
+            for (int u = 0; u < 4; ++u) av[u] = As[kk][ty * 4 + u];
+            for (int v = 0; v < 4; ++v) bv[v] = Bs[kk][tx * 4 + v];
+            for (int u = 0; u < 4; ++u)
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+    double* out = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * CT * CT;
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) out[(ty * 4 + u) * CT + tx * 4 + v] = acc[u][v];
+}
+
+__global__ void k_cov_reduce(const double* __restrict__ part, int C, long N, int ntile, int npair,
+                             int nchunk, double* __restrict__ cov) {
+    const int pair0 = blockIdx.x;
+    int pair = pair0, ta = 0;
+    while (pair >= ntile - ta) { pair -= ntile - ta; ++ta; }
+    const int tb = ta + pair;
+    for (int t = threadIdx.x; t < CT * CT; t += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < nchunk; ++k) s += part[((size_t)k * npair + pair0) * CT * CT + t];
+        const int a = ta * CT + t / CT, b = tb * CT + t % CT;
+        if (a < C && b < C) {
+            cov[(size_t)a * C + b] = s / (double)N;
+            cov[(size_t)b * C + a] = s / (double)N;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Exact order statistics by MSB-first radix selection on order-preserving
+// 32-bit keys, 4 passes of 8 bits, all requested ranks of a channel at once.
+constexpr int MAXR = 8;
+
+__device__ __forceinline__ uint32_t fkey(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float funkey(uint32_t k) {
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    return __uint_as_float(u);
+}
+
+__global__ __launch_bounds__(256) void k_select(const float* __restrict__ vals, long N,
+                                                const long long* __restrict__ ranks, int nr,
+                                                float* __restrict__ out) {
+    __shared__ uint32_t hist[MAXR][256];
+    __shared__ uint32_t prefix[MAXR];
+    __shared__ long long remaining[MAXR];
+    const int c = blockIdx.x;
+    const float* v = vals + (size_t)c * N;
+    if (threadIdx.x < nr) {
+        prefix[threadIdx.x] = 0u;
+        remaining[threadIdx.x] = ranks[threadIdx.x];
+    }
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        const uint32_t mask = pass == 0 ? 0u : (0xFFFFFFFFu << (32 - 8 * pass));
+        for (int t = threadIdx.x; t < MAXR * 256; t += 256) (&hist[0][0])[t] = 0u;
+        __syncthreads();
+        for (long i = threadIdx.x; i < N; i += 256) {
+            const uint32_t k = fkey(v[i]);
+            for (int q = 0; q < nr; ++q)
+                if ((k & mask) == prefix[q]) atomicAdd(&hist[q][(k >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < nr) {
+            const int q = threadIdx.x;
+            long long rem = remaining[q];
+            int d = 0;
+            for (d = 0; d < 256; ++d) {
+                if (rem < (long long)hist[q][d]) break;
+                rem -= hist[q][d];
+            }
+            prefix[q] |= ((uint32_t)min(d, 255)) << shift;
+            remaining[q] = rem;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < nr) out[(size_t)c * nr + threadIdx.x] = funkey(prefix[threadIdx.x]);
+}
+
+// ------------------------------------------------------------------------
+// Reference: count table counts[c][i][t] = #{full windows p : cP_p(i) = t}.
+// Same lane layout and running sums as the score kernel (lane (s, j) owns bin
+// j of channel s); every lane keeps a private uint16 histogram in LDS for the
+// bins of its split, flushed with global atomics at the end of the tile.
+struct RArgs {
+    const uint8_t* bins;
+    int C, H, W, T, B, Bp, S, r, m, Ws, Hb, nsplit;
+    uint32_t* counts;
+};
+
+__global__ __launch_bounds__(64) void k_refcount(RArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x;
+    const int Bp = a.Bp, S = a.S, T = a.T, r = a.r, m = a.m, H = a.H, W = a.W;
+    const int s = lane / Bp, j = lane - s * Bp;
+    const int sa = s < S ? s : S - 1;
+    const int x0 = blockIdx.x * a.Ws, xe = min(W, x0 + a.Ws), ws = xe - x0;
+    const int y0 = blockIdx.y * a.Hb, ye = min(H, y0 + a.Hb);
+    const int split = blockIdx.z % a.nsplit;
+    const int cbase = (blockIdx.z / a.nsplit) * S;
+    const int c = cbase + s;
+    const bool cv = (s < S) && (c < a.C);
+    const int per = Bp / a.nsplit;
+    const int jlo = split * per;
+    const bool counting = cv && (j < a.B) && (j >= jlo) && (j < jlo + per);
+    const int WbMax = a.Ws + 2 * r, Wb = ws + 2 * r;  // bin columns [x0-r, xe+r)
+    const int xb0 = x0 - r;
+    const uint8_t* bc = a.bins + (size_t)(cv ? c : 0) * H * W;
+    uint8_t* vc = smem;                                          // [WbMax][64]
+    uint16_t* cnt = (uint16_t*)(smem + ((WbMax * 64 + 15) & ~15));  // [S][per][m+1]
+    for (int t = lane; t < WbMax * 16; t += 64) ((uint32_t*)vc)[t] = 0u;
+    for (int t = lane; t < S * per * (m + 1); t += 64) cnt[t] = 0;
+    __syncthreads();
+    uint16_t* mycnt = cnt + ((size_t)sa * per + (counting ? j - jlo : 0)) * (m + 1);
+    // Full-window centres owned by this tile: rows [ys, yend), columns
+    // [max(x0, r), min(xe, W - r)).
+    const int ys = max(y0, r), yend = min(ye, H - r);
+    const int pxlo = max(x0, r), pxhi = min(xe, W - r);
+    if (ys < yend && pxlo < pxhi) {
+        for (int yy = ys - r; yy < ys + r; ++yy)
+            for (int q = 0; q < Wb; ++q) {
+                const int xl = xb0 + q;
+                if (xl >= 0 && xl < W) vc[q * 64 + lane] += (bc[(size_t)yy * W + xl] <= j) ? 1 : 0;
+            }
+        for (int yc = ys; yc < yend; ++yc) {
+            const int ya = yc + r, yr = yc - r - 1;
+            const bool rem = yc > ys;
+            int cP = 0;
+            for (int q = 0; q < Wb; ++q) {
+                const int xl = xb0 + q;
+                int v = 0;
+                if (xl >= 0 && xl < W) {
+                    v = vc[q * 64 + lane] + ((bc[(size_t)ya * W + xl] <= j) ? 1 : 0);
+                    if (rem) v -= (bc[(size_t)yr * W + xl] <= j) ? 1 : 0;
+                    vc[q * 64 + lane] = (uint8_t)v;
+                }
+                const int vold = (q >= T) ? (int)vc[(q - T) * 64 + lane] : 0;
+                cP += v - vold;
+                const int px = xl - r;
+                if (counting && q >= T - 1 && px >= pxlo && px < pxhi) mycnt[cP] += 1;
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = lane; t < S * per * (m + 1); t += 64) {
+        const int ss = t / (per * (m + 1));
+        const int rest = t - ss * per * (m + 1);
+        const int jj = rest / (m + 1) + jlo, tt = rest - (rest / (m + 1)) * (m + 1);
+        const int cc = cbase + ss;
+        const uint32_t v = cnt[t];
+        if (v && cc < a.C && jj < a.B)
+            atomicAdd(&a.counts[((size_t)cc * a.B + jj) * (m + 1) + tt], v);
+    }
+}
+
+__global__ void k_refselect(const uint32_t* __restrict__ counts, int C, int B, int m, long long h,
+                            int32_t* __restrict__ cR) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * B) return;
+    const uint32_t* cnt = counts + (size_t)t * (m + 1);
+    long long seen = 0;
+    int v = m;
+    for (v = m; v > 0; --v) {
+        seen += cnt[v];
+        if (seen >= h) break;
+    }
+    cR[t] = v;
+}
+
+// ------------------------------------------------------------------------
+// Projection + quantisation, FP32 on the vector ALUs: one thread per pixel;
+// z = V^T (x - mu) (KP accumulators, V zero-padded to KP columns), then
+// r_c = (x_c - mu_c) - sum_j V[c][j] z_j, then the bin index.
+struct PArgs {
+    const float* X;
+    int C, N, k, B, preproc;
+    const float* mu;
+    const float* V;  // [C][KP]
+    const float* edges;
+    const float* lo;
+    const float* inv_delta;
+    uint8_t* bins;
+    float* resid;
+};
+
+__device__ __forceinline__ int bin_of(float rr, const float* __restrict__ e, float lo, float idl, int B) {
+    if (idl == 0.f) return 0;
+    int b = (int)floorf((rr - lo) * idl);
+    b = b < 0 ? 0 : (b > B - 1 ? B - 1 : b);
+    while (b > 0 && rr < e[b - 1]) --b;
+    while (b < B - 1 && rr >= e[b]) ++b;
+    return b;
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_proj_fp32(PArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const size_t N = (size_t)a.N;
+    float z[KP > 0 ? KP : 1];
+#pragma unroll
+    for (int q = 0; q < (KP > 0 ? KP : 1); ++q) z[q] = 0.f;
+    if (a.preproc && KP > 0) {
+        for (int c = 0; c < a.C; ++c) {
+            const float d = a.X[(size_t)c * N + i] - a.mu[c];
+            const float* vr = a.V + (size_t)c * KP;
+#pragma unroll
+            for (int q = 0; q < KP; ++q) z[q] = fmaf(vr[q], d, z[q]);
+        }
+    }
+    for (int c = 0; c < a.C; ++c) {
+        float rr = a.X[(size_t)c * N + i];
+        if (a.preproc) {
+            rr -= a.mu[c];
+            const float* vr = a.V + (size_t)c * KP;
+            float rec = 0.f;
+#pragma unroll
+            for (int q = 0; q < KP; ++q) rec = fmaf(vr[q], z[q], rec);
+            rr -= rec;
+        }
+        if (a.resid) a.resid[(size_t)c * N + i] = rr;
+        if (a.bins)
+            a.bins[(size_t)c * N + i] =
+                (uint8_t)bin_of(rr, a.edges + (size_t)c * (a.B - 1), a.lo[c], a.inv_delta[c], a.B);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mean(const float* X, int C, long N, double* mu, hipStream_t st) {
+    hipLaunchKernelGGL(k_mean, dim3(C), dim3(256), 0, st, X, N, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_cov(const float* X, int C, long N, const double* mu, double* cov, hipStream_t st) {
+    const int ntile = (C + CT - 1) / CT;
+    const int npair = ntile * (ntile + 1) / 2;
+    int nchunk = (int)std::max(1L, std::min(512L, 1024L / npair));
+    nchunk = (int)std::min<long>(nchunk, std::max(1L, N / CK));
+    const long chunk = ((N + nchunk - 1) / nchunk + CK - 1) / CK * CK;
+    nchunk = (int)((N + chunk - 1) / chunk);
+    double* part = nullptr;
+    hipError_t e = hipMallocAsync((void**)&part, (size_t)nchunk * npair * CT * CT * sizeof(double), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cov_partial, dim3(npair, nchunk), dim3(256), 0, st, X, C, N, mu, ntile,
+                       chunk, part);
+    hipLaunchKernelGGL(k_cov_reduce, dim3(npair), dim3(256), 0, st, part, C, N, ntile, npair,
+                       nchunk, cov);
+    e = hipGetLastError();
+    const hipError_t e2 = hipFreeAsync(part, st);
+    return e != hipSuccess ? e : e2;
+}
+
+hipError_t launch_select(const float* vals, int C, long N, const long long* ranks_dev, int nr,
+                         float* out, hipStream_t st) {
+    if (nr > MAXR) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_select, dim3(C), dim3(256), 0, st, vals, N, ranks_dev, nr, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_refcount(const uint8_t* bins, int C, int H, int W, int T, int B,
+                           uint32_t* counts, hipStream_t st) {
+    RArgs a;
+    a.bins = bins; a.C = C; a.H = H; a.W = W; a.T = T; a.B = B;
+    int Bp = 8;
+    while (Bp < B) Bp <<= 1;
+    a.Bp = Bp;
+    a.r = T / 2; a.m = T * T;
+    a.Ws = 64; a.Hb = 64;
+    a.counts = counts;
+    hipError_t e = hipMemsetAsync(counts, 0, (size_t)C * B * (a.m + 1) * sizeof(uint32_t), st);
+    if (e != hipSuccess) return e;
+    // channels per wave and bin splits so the private histograms fit in LDS
+    int S = 64 / Bp, nsplit = 1;
+    auto lds = [&](int S_, int ns_) {
+        const size_t WbMax = (size_t)a.Ws + 2 * a.r;
+        return ((WbMax * 64 + 15) & ~size_t(15)) + (size_t)S_ * (Bp / ns_) * (a.m + 1) * 2;
+    };
+    while (lds(S, nsplit) > 60000 && S > 1) S >>= 1;
+    while (lds(S, nsplit) > 60000 && nsplit < Bp) nsplit <<= 1;
+    if (lds(S, nsplit) > 65536) return hipErrorInvalidValue;
+    a.S = S; a.nsplit = nsplit;
+    dim3 grid((W + a.Ws - 1) / a.Ws, (H + a.Hb - 1) / a.Hb, ((C + S - 1) / S) * nsplit);
+    hipLaunchKernelGGL(k_refcount, grid, dim3(64), lds(S, nsplit), st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_refselect(const uint32_t* counts, int C, int B, int m, long long h, int32_t* cR,
+                            hipStream_t st) {
+    const int n = C * B;
+    hipLaunchKernelGGL(k_refselect, dim3((n + 255) / 256), dim3(256), 0, st, counts, C, B, m, h, cR);
+    return hipGetLastError();
+}
+
+hipError_t launch_proj(const ProjLaunch& L, hipStream_t st) {
+    PArgs a;
+    a.X = L.X; a.C = L.C; a.N = L.N; a.k = L.k; a.B = L.B; a.preproc = L.preproc;
+    a.mu = L.mu; a.V = L.V; a.edges = L.edges; a.lo = L.lo; a.inv_delta = L.inv_delta;
+    a.bins = L.bins; a.resid = L.resid;
+    const int KP = (!L.preproc || L.k == 0) ? 0 : (L.k <= 8 ? 8 : L.k <= 16 ? 16 : L.k <= 32 ? 32 : 64);
+    if (L.preproc && L.k > 64) return hipErrorInvalidValue;
+    dim3 grid((L.N + 255) / 256);
+    switch (KP) {
+        case 0: hipLaunchKernelGGL(k_proj_fp32<0>, grid, dim3(256), 0, st, a); break;
+        case 8: hipLaunchKernelGGL(k_proj_fp32<8>, grid, dim3(256), 0, st, a); break;
+        case 16: hipLaunchKernelGGL(k_proj_fp32<16>, grid, dim3(256), 0, st, a); break;
+        case 32: hipLaunchKernelGGL(k_proj_fp32<32>, grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_proj_fp32<64>, grid, dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qfca

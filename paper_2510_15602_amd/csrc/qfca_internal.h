@@ -1,0 +1,100 @@
+// Internal declarations shared by the libqfca translation units (not part of
+// the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qfca.h"
+
+namespace qfca {
+
+// Per-thread last error message, set by the API layer.
+void set_error(const std::string& msg);
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// Tile shape of the score kernel: strip width (output columns), band height
+// (output rows) and channels per wavefront.
+struct ScoreTile {
+    int Ws = 64;
+    int Hb = 64;
+    int S = 1;
+};
+
+// Device-resident tables of a model that the score kernel reads.  For the
+// cumulative reference cR of channel c (total m = T*T):
+//   psig[c][t] = (Psi_c(t), sigma_c(t)), t in [0, m], where
+//     Psi_c(t)   = sum_{k<B-1} max(0, t - cR_c[k])   (integral of the reference
+//                  bin index over the first t units of reference mass) and
+//     sigma_c(t) = #{k < B-1 : cR_c[k] <= t}        (its slope on [t, t+1]);
+//   cRm1[c][i] = cR_c[i-1] (0 for i = 0), Dm1[c][i] = Psi_c(cRm1[c][i]),
+//   cRl[c][i] = cR_c[i] for i < B-1 and 0 otherwise (window W1 by-product);
+//   rcp[P] = 1/P as float32 (rcp[0] = 0).
+struct ScoreTables {
+    int2* psig = nullptr;
+    int32_t* cRm1 = nullptr;
+    int32_t* Dm1 = nullptr;
+    int32_t* cRl = nullptr;
+    float* rcp = nullptr;
+    double* delta = nullptr;  // [C]
+    int Bp = 0;               // lanes per channel (power of two, >= 8)
+};
+
+struct ScoreLaunch {
+    const uint8_t* bins;  // [C][H][W]
+    int C, H, W, T, B;
+    ScoreTables tab;
+    float* achan;   // [C][H][W] out
+    float* w1chan;  // [C][H][W] out or nullptr
+    ScoreTile tile;
+};
+
+size_t score_lds_bytes(int T, int Bp, int S, int Ws);
+hipError_t launch_score(const ScoreLaunch& L, hipStream_t st);
+hipError_t launch_chanmean(const float* achan, const float* w1chan, int C, int N, float* amap,
+                           float* w1, hipStream_t st);
+hipError_t launch_blur(const float* in, int H, int W, float sigma, float* out, hipStream_t st);
+
+// Reference fit: count table [C][B][m+1] (uint32, zeroed by the launcher) of
+// full-window cumulative counts, then the selection of cR.
+hipError_t launch_refcount(const uint8_t* bins, int C, int H, int W, int T, int B,
+                           uint32_t* counts, hipStream_t st);
+hipError_t launch_refselect(const uint32_t* counts, int C, int B, int m, long long h,
+                            int32_t* cR, hipStream_t st);
+
+// Projection + quantisation.
+struct ProjLaunch {
+    const float* X;  // [C][N]
+    int C, N, k, B;
+    int preproc, prec;
+    const float* mu;        // [C]
+    const float* V;         // [C][k] float32
+    const uint16_t* Vbf;    // [C][k] bf16 bits
+    const float* edges;     // [C][B-1]
+    const float* lo;        // [C]
+    const float* inv_delta; // [C] (0 for a degenerate channel)
+    uint8_t* bins;          // [C][N] or nullptr
+    float* resid;           // [C][N] or nullptr
+};
+hipError_t launch_proj(const ProjLaunch& L, hipStream_t st);
+
+// Fit statistics.
+hipError_t launch_mean(const float* X, int C, long N, double* mu, hipStream_t st);
+hipError_t launch_cov(const float* X, int C, long N, const double* mu, double* cov,
+                      hipStream_t st);
+// Exact order statistics: for every channel c and every j < nr, out[c*nr+j] =
+// the ranks[j]-th smallest (0-based) value of vals[c][0..N).
+hipError_t launch_select(const float* vals, int C, long N, const long long* ranks_dev, int nr,
+                         float* out, hipStream_t st);
+
+// Host FP64 symmetric eigensolver: A [n][n] row-major (destroyed); evals
+// descending; vecs [n][n] row-major with column j the j-th eigenvector.
+int sym_eig(double* A, int n, double* evals, double* vecs);
+
+}  // namespace qfca

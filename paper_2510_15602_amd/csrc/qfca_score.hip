@@ -1,0 +1,367 @@
+// Patch statistics comparison (Sec. 3.1, Alg. 1), error-to-pixel association
+// with sigma_p = infinity (Sec. 3.1, Sec. 4.5.4), channel mean (Eq. 1) and the
+// final sigma_s blur (Sec. 4.5.4) for gfx950.
+//
+// Work decomposition of k_score: one wavefront per (column strip, row band,
+// group of S channels).  Lane (s, j) owns bin j of channel s; lanes walk the
+// strip left to right, one row of patch centres at a time, streaming down the
+// band:
+//   * vc[x][lane]: the number of pixels of column x inside the current T-row
+//     window whose bin is <= j (updated by one add and one remove per row),
+//   * cP: running horizontal sum of vc, i.e. the window's cumulative count at
+//     bin j,
+//   * Algorithm 1's per-bin transport numerator I_j is evaluated in closed
+//     form from cP_{j-1}, cP_j (the previous lane) and the reference tables:
+//     with a_i = cP_i m, c_k = cR_k n (equal-mass scaling, m = T^2 reference
+//     mass, n in-image window mass) and Phi(t) = sum_{k<B-1} (t - c_k)^+,
+//     the bin's mass occupies quantiles (a_{j-1}, a_j] and is sent to the
+//     reference bin J(u) = #{k : c_k < u}, so
+//       I_j = int_{a_{j-1}}^{a_j} |j - J(u)| du
+//           = Phi(a_{j-1}) + Phi(a_j) - 2 Phi(s) + j (2 s - a_{j-1} - a_j),
+//     s = clamp(c_{j-1}, a_{j-1}, a_j).  This is exactly what the two-pointer
+//     loop of Alg. 1 accumulates; e_j = I_j / (P_j m) in bin units.
+//   * e is summed over the T patch columns around each output column in
+//     double precision (running sum), and the result for the pixel's own bin
+//     is gathered across lanes and added to the pixel's accumulator for each
+//     of the T patch rows that cover it.
+// All counts are exact integers; per-channel results are written to a
+// [C][H][W] buffer and reduced over channels in a fixed order.
+#include "qfca_internal.h"
+
+namespace qfca {
+namespace {
+
+__device__ __forceinline__ int lane_prev(int v) {
+    // Value held by lane-1 (DPP wave_shr:1); lane 0 receives 0.
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+}
+
+__host__ __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+struct KArgs {
+    const uint8_t* bins;
+    int C, H, W, T, B, Bp, S, r, m, Ws, Hb;
+    const int2* psig;
+    const int32_t* cRm1;
+    const int32_t* Dm1;
+    const int32_t* cRl;
+    const float* rcp;
+    const double* delta;
+    float* achan;
+    float* w1chan;
+};
+
+struct Lds {
+    size_t vc, ring, acc, psig, rcp, ering, total;
+};
+
+__host__ __device__ inline Lds lds_layout(int T, int Bp, int S, int Ws) {
+    (void)Bp;
+    const int r = T / 2, m = T * T;
+    const size_t WbMax = (size_t)Ws + 4 * r;
+    Lds L;
+    size_t off = 0;
+    L.vc = off;    off += align16(WbMax * 64);
+    L.ring = off;  off += align16((size_t)(T + 1) * S * WbMax);
+    L.acc = off;   off += align16((size_t)T * S * Ws * 4);
+    L.psig = off;  off += align16((size_t)S * (m + 1) * 8);
+    L.rcp = off;   off += align16((size_t)(m + 1) * 4);
+    L.ering = off; off += align16((size_t)T * 64 * 4);
+    L.total = off;
+    return L;
+}
+
+__global__ __launch_bounds__(64) void k_score(KArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x;
+    const int Bp = a.Bp, S = a.S, T = a.T, r = a.r, m = a.m, H = a.H, W = a.W;
+    const int T1 = T + 1;
+    const int s = lane / Bp;
+    const int sa = s < S ? s : S - 1;
+    const int j = lane - s * Bp;
+    const int x0 = blockIdx.x * a.Ws;
+    const int xe = min(W, x0 + a.Ws);
+    const int ws = xe - x0;
+    const int y0 = blockIdx.y * a.Hb;
+    const int ye = min(H, y0 + a.Hb);
+    const int cbase = blockIdx.z * S;
+    const int c = cbase + s;
+    const bool cval = (s < S) && (c < a.C);
+    const int WbMax = a.Ws + 4 * r;
+    const int Wb = ws + 4 * r;
+    const int xb0 = x0 - 2 * r;
+
+    const Lds L = lds_layout(T, Bp, S, a.Ws);
+    uint8_t* vc = smem + L.vc;
+    uint8_t* ring = smem + L.ring;
+    float* acc = (float*)(smem + L.acc);
+    int2* psig = (int2*)(smem + L.psig);
+    float* rcp = (float*)(smem + L.rcp);
+    float* ering = (float*)(smem + L.ering);
+
+    for (int t = lane; t < S * (m + 1); t += 64) {
+        const int ss = t / (m + 1), tt = t - ss * (m + 1);
+        const int cc = cbase + ss;
+        psig[t] = (cc < a.C) ? a.psig[(size_t)cc * (m + 1) + tt] : make_int2(0, 0);
+    }
+    for (int t = lane; t <= m; t += 64) rcp[t] = a.rcp[t];
+    for (int t = lane; t < WbMax * 16; t += 64) ((uint32_t*)vc)[t] = 0u;
+    for (int t = lane; t < T * S * a.Ws; t += 64) acc[t] = 0.f;
+    const int ci = cval ? c : 0;
+    const int crm1 = a.cRm1[ci * Bp + j];
+    const int dm1 = a.Dm1[ci * Bp + j];
+    const int crl = a.cRl[ci * Bp + j];
+    const bool binok = cval && (j < a.B);
+    const bool w1ok = cval && (j < a.B - 1);
+    const bool want_w1 = a.w1chan != nullptr;
+    const float inv_m = 1.0f / (float)m;
+    __syncthreads();
+
+    auto load_row = [&](int yy) {
+        uint8_t* dst = ring + (size_t)(yy % T1) * S * WbMax;
+        for (int t = lane; t < S * Wb; t += 64) {
+            const int ss = t / Wb, q = t - ss * Wb;
+            const int cc = cbase + ss, xx = xb0 + q;
+            uint8_t v = 0xFF;  // out of the image: never counted
+            if (cc < a.C && xx >= 0 && xx < W) v = a.bins[((size_t)cc * H + yy) * W + xx];
+            dst[ss * WbMax + q] = v;
+        }
+    };
+
+    const int ys = max(0, y0 - r);
+    const int yend = min(H, ye + r);
+    const int lo_add = max(0, ys - r);
+    const int hi_add = min(H, ys + r);
+    // Bring the vertical window of the first processed row up to date.
+    for (int yy = lo_add; yy < hi_add; ++yy) {
+        load_row(yy);
+        __syncthreads();
+        const uint8_t* row = ring + (size_t)(yy % T1) * S * WbMax + sa * WbMax;
+        for (int q = 0; q < Wb; ++q) {
+            const int xl = xb0 + q;
+            if (xl >= 0 && xl < W) vc[q * 64 + lane] += (row[q] <= j) ? 1 : 0;
+        }
+        __syncthreads();
+    }
+
+    for (int y = ys; y < yend; ++y) {
+        const bool add = (y + r) < H;
+        const bool rem = (y - r - 1) >= lo_add;
+        if (add) load_row(y + r);
+        __syncthreads();
+        const uint8_t* rowA = ring + (size_t)((y + r) % T1) * S * WbMax + sa * WbMax;
+        const uint8_t* rowR = ring + (size_t)((y - r - 1 + T1) % T1) * S * WbMax + sa * WbMax;
+        const int ny = min(H - 1, y + r) - max(0, y - r) + 1;
+        const bool own_row = (y >= y0) && (y < ye);
+        int cP = 0;
+        double hs = 0.0;
+        int slot = 0;
+        for (int q = 0; q < Wb; ++q) {
+            const int xl = xb0 + q;
+            int v = 0;
+            if (xl >= 0 && xl < W) {
+                v = vc[q * 64 + lane];
+                if (add) v += (rowA[q] <= j) ? 1 : 0;
+                if (rem) v -= (rowR[q] <= j) ? 1 : 0;
+                vc[q * 64 + lane] = (uint8_t)v;
+            }
+            const int vold = (q >= T) ? (int)vc[(q - T) * 64 + lane] : 0;
+            cP += v - vold;
+            const int p = xl - r;  // patch-centre column
+            float e = 0.f;
+            if (q >= 2 * r && p >= 0 && p < W) {
+                const int nx = min(W - 1, p + r) - max(0, p - r) + 1;
+                const int n = ny * nx;
+                int cPm1 = lane_prev(cP);
+                if (j == 0) cPm1 = 0;
+                const int P = cP - cPm1;
+                if (n == m) {
+                    // Interior window: equal masses, Phi(c P) = m Psi(cP).
+                    const int psv = psig[sa * (m + 1) + cP].x;
+                    int psu = lane_prev(psv);
+                    if (j == 0) psu = 0;
+                    const int u = cPm1, vv = cP;
+                    const int sc = min(max(crm1, u), vv);
+                    const int pss = (crm1 <= u) ? psu : ((crm1 >= vv) ? psv : dm1);
+                    const int I = (psv - pss) + (psu - pss) + j * (2 * sc - u - vv);
+                    e = (binok && P > 0) ? (float)I * rcp[P] : 0.f;
+                } else {
+                    // Clipped window: a = cP m, c = cR n, Phi(a) = n Psi(t) with
+                    // t = a / n, evaluated by linear interpolation of Psi.
+                    const int av = cP * m;
+                    int q0 = (int)((float)av * rcp[n]);
+                    if ((q0 + 1) * n <= av) q0++;
+                    if (q0 * n > av) q0--;
+                    const int2 ps = psig[sa * (m + 1) + q0];
+                    const int phia = n * ps.x + (av - q0 * n) * ps.y;
+                    int phiu = lane_prev(phia);
+                    if (j == 0) phiu = 0;
+                    const int au = cPm1 * m;
+                    const int cm = crm1 * n;
+                    const int sc = min(max(cm, au), av);
+                    const int phis = (cm <= au) ? phiu : ((cm >= av) ? phia : n * dm1);
+                    const int I = (phia - phis) + (phiu - phis) + j * (2 * sc - au - av);
+                    e = (binok && P > 0) ? (float)I * rcp[P] * inv_m : 0.f;
+                }
+                if (want_w1 && own_row && p >= x0 && p < xe) {
+                    int d = w1ok ? abs(cP * m - crl * n) : 0;
+                    for (int o = Bp >> 1; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+                    if (cval && j == 0)
+                        a.w1chan[((size_t)c * H + y) * W + p] =
+                            (float)(a.delta[c] * (double)d / ((double)n * (double)m));
+                }
+            }
+            // Horizontal window sum of e over the T patch columns around
+            // output column p - r.
+            const float eold = (q >= T) ? ering[slot * 64 + lane] : 0.f;
+            ering[slot * 64 + lane] = e;
+            slot = (slot + 1 == T) ? 0 : slot + 1;
+            hs += (double)e - (double)eold;
+            const int xo = q - 4 * r;  // local output column
+            if (xo >= 0) {
+                const float hf = (float)hs;
+                for (int tc = 0; tc < T; tc += Bp) {
+                    const int t = tc + j;
+                    const int yo = y - r + t;
+                    const bool ok = cval && (t < T) && (yo >= y0) && (yo < ye);
+                    int b = 0;
+                    if (ok) b = ring[(size_t)(yo % T1) * S * WbMax + sa * WbMax + xo + 2 * r];
+                    const float hv = __shfl(hf, sa * Bp + b, 64);
+                    if (ok) acc[((yo % T) * S + sa) * a.Ws + xo] += hv;
+                }
+            }
+        }
+        // Output rows whose last covering patch row is y.
+        int yo_lo = y - r, yo_hi = (y < H - 1) ? y - r : H - 1;
+        yo_lo = max(yo_lo, y0);
+        yo_hi = min(yo_hi, ye - 1);
+        __syncthreads();
+        for (int yo = yo_lo; yo <= yo_hi; ++yo) {
+            const int nyo = min(H - 1, yo + r) - max(0, yo - r) + 1;
+            for (int t = lane; t < S * ws; t += 64) {
+                const int ss = t / ws, xo = t - ss * ws;
+                const int cc = cbase + ss;
+                float* ap = acc + ((yo % T) * S + ss) * a.Ws + xo;
+                if (cc < a.C) {
+                    const int xg = x0 + xo;
+                    const int nxo = min(W - 1, xg + r) - max(0, xg - r) + 1;
+                    a.achan[((size_t)cc * H + yo) * W + xg] =
+                        (float)((double)(*ap) * a.delta[cc] / (double)(nyo * nxo));
+                }
+                *ap = 0.f;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// A(x) = (1/C) sum_c achan[c][x] in double precision, fixed channel order.
+__global__ void k_chanmean(const float* __restrict__ achan, const float* __restrict__ w1chan,
+                           int C, int N, float* __restrict__ amap, float* __restrict__ w1) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = 0.0, t = 0.0;
+    for (int c = 0; c < C; ++c) {
+        s += (double)achan[(size_t)c * N + i];
+        if (w1chan) t += (double)w1chan[(size_t)c * N + i];
+    }
+    amap[i] = (float)(s / (double)C);
+    if (w1chan) w1[i] = (float)(t / (double)C);
+}
+
+// Separable Gaussian, radius R, renormalised over in-image taps (the 2-D
+// renormalisation factorises because the in-image tap set is a rectangle).
+constexpr int BT = 16;
+constexpr int RMAX = 16;
+
+struct BlurW {
+    double w[RMAX + 1];
+};
+
+__global__ __launch_bounds__(256) void k_blur(const float* __restrict__ in, int H, int W, int R,
+                                              BlurW wts, float* __restrict__ out) {
+    __shared__ double tile[BT + 2 * RMAX][BT + 2 * RMAX];
+    __shared__ double hpass[BT + 2 * RMAX][BT];
+    __shared__ double w[RMAX + 1];
+    const int tx = threadIdx.x % BT, ty = threadIdx.x / BT;
+    const int bx = blockIdx.x * BT, by = blockIdx.y * BT;
+    const int TS = BT + 2 * R;
+    if (threadIdx.x <= R) w[threadIdx.x] = wts.w[threadIdx.x];
+    for (int t = threadIdx.x; t < TS * TS; t += 256) {
+        const int ly = t / TS, lx = t - ly * TS;
+        const int gy = by + ly - R, gx = bx + lx - R;
+        tile[ly][lx] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? (double)in[(size_t)gy * W + gx] : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < TS * BT; t += 256) {
+        const int ly = t / BT, lx = t - ly * BT;
+        const int gx = bx + lx;
+        double s = 0.0, ws = 0.0;
+        for (int d = -R; d <= R; ++d) {
+            const int xx = gx + d;
+            if (xx < 0 || xx >= W) continue;
+            const double wd = w[d < 0 ? -d : d];
+            s += wd * tile[ly][lx + R + d];
+            ws += wd;
+        }
+        hpass[ly][lx] = s / ws;
+    }
+    __syncthreads();
+    const int gy = by + ty, gx = bx + tx;
+    if (gy >= H || gx >= W) return;
+    double s = 0.0, ws = 0.0;
+    for (int d = -R; d <= R; ++d) {
+        const int yy = gy + d;
+        if (yy < 0 || yy >= H) continue;
+        const double wd = w[d < 0 ? -d : d];
+        s += wd * hpass[ty + R + d][tx];
+        ws += wd;
+    }
+    out[(size_t)gy * W + gx] = (float)(s / ws);
+}
+
+}  // namespace
+
+size_t score_lds_bytes(int T, int Bp, int S, int Ws) { return lds_layout(T, Bp, S, Ws).total; }
+
+hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
+    KArgs a;
+    a.bins = L.bins;
+    a.C = L.C; a.H = L.H; a.W = L.W; a.T = L.T; a.B = L.B;
+    a.Bp = L.tab.Bp;
+    a.S = L.tile.S;
+    a.r = L.T / 2;
+    a.m = L.T * L.T;
+    a.Ws = L.tile.Ws;
+    a.Hb = L.tile.Hb;
+    a.psig = L.tab.psig; a.cRm1 = L.tab.cRm1; a.Dm1 = L.tab.Dm1; a.cRl = L.tab.cRl;
+    a.rcp = L.tab.rcp; a.delta = L.tab.delta;
+    a.achan = L.achan; a.w1chan = L.w1chan;
+    if (a.S < 1 || a.S * a.Bp > 64) return hipErrorInvalidValue;
+    const size_t lds = score_lds_bytes(a.T, a.Bp, a.S, a.Ws);
+    if (lds > 65536) return hipErrorInvalidValue;
+    dim3 grid((L.W + a.Ws - 1) / a.Ws, (L.H + a.Hb - 1) / a.Hb, (L.C + a.S - 1) / a.S);
+    hipLaunchKernelGGL(k_score, grid, dim3(64), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_chanmean(const float* achan, const float* w1chan, int C, int N, float* amap,
+                           float* w1, hipStream_t st) {
+    hipLaunchKernelGGL(k_chanmean, dim3((N + 255) / 256), dim3(256), 0, st, achan, w1chan, C, N,
+                       amap, w1);
+    return hipGetLastError();
+}
+
+hipError_t launch_blur(const float* in, int H, int W, float sigma, float* out, hipStream_t st) {
+    if (!(sigma > 0.f)) return hipMemcpyAsync(out, in, (size_t)H * W * 4, hipMemcpyDeviceToDevice, st);
+    const int R = (int)ceil(3.0 * (double)sigma);
+    if (R > RMAX) return hipErrorInvalidValue;
+    BlurW wts;
+    for (int d = 0; d <= RMAX; ++d)
+        wts.w[d] = d <= R ? exp(-(double)(d * d) / (2.0 * (double)sigma * (double)sigma)) : 0.0;
+    dim3 grid((W + BT - 1) / BT, (H + BT - 1) / BT);
+    hipLaunchKernelGGL(k_blur, grid, dim3(256), 0, st, in, H, W, R, wts, out);
+    return hipGetLastError();
+}
+
+}  // namespace qfca

@@ -1,0 +1,62 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/qfca.h declares, and the host eigensolver agrees with LAPACK."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2510_15602_amd as q
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "qfca.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qfca_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_symbols() == sorted(q.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = q.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+    assert L.qfca_version() >= 100
+    assert L.qfca_status_str(2) == b"invalid shape"
+
+
+def test_params_struct_layout():
+    import ctypes
+    assert ctypes.sizeof(q.Params) == 36
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 33, 128])
+def test_host_eigensolver_matches_eigh(n):
+    g = np.random.Generator(np.random.PCG64(n))
+    M = g.standard_normal((n, 2 * n + 3))
+    A = M @ M.T / M.shape[1]
+    ev, V = q.host_sym_eig(A)
+    w, U = np.linalg.eigh(A)
+    np.testing.assert_allclose(ev, w[::-1], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(V.T @ V, np.eye(n), atol=1e-12)
+    np.testing.assert_allclose(A @ V, V * ev, atol=1e-11)
+    assert np.all(np.diff(ev) <= 0)
+
+
+def test_host_eigensolver_degenerate_spectrum():
+    A = np.diag([3.0, 3.0, 1.0, 1.0, 1.0]) + 0.0
+    ev, V = q.host_sym_eig(A)
+    np.testing.assert_allclose(ev, [3, 3, 1, 1, 1], atol=1e-14)
+    np.testing.assert_allclose(V.T @ V, np.eye(5), atol=1e-14)
+
+
+def test_oracle_library_builds_and_is_separate():
+    import oracle
+    assert os.path.exists(oracle.build(force=False))
+    # the product package never imports the oracle
+    src = open(os.path.join(ROOT, "paper_2510_15602_amd", "__init__.py")).read()
+    assert "import oracle" not in src

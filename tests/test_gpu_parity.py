@@ -1,0 +1,211 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances:
+  * bins, window counts, the reference and every integer stage: bit-exact
+    given the same inputs;
+  * score-side maps (per channel, channel mean, W1, blurred score), given the
+    oracle's bins and model: |gpu - oracle| <= 1e-5 |oracle| + 1e-7 max|oracle|
+    per pixel (the per-bin errors are formed in float32 from exact integer
+    numerators and accumulated in float64/float32; ~1e-6 is expected);
+  * quantisation from float features: bins equal the oracle's wherever the
+    oracle's FP64 residual is farther than the float32 error band from every
+    edge; inside the band a bin may differ by one.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import paper_2510_15602_amd as q  # noqa: E402
+import qfca_synth  # noqa: E402
+
+RTOL, ATOL_REL = 1e-5, 1e-7
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return q.Context(0)
+
+
+def close(g, o, what):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    tol = RTOL * np.abs(o) + ATOL_REL * max(np.abs(o).max(), 1e-30)
+    bad = np.abs(g - o) > tol
+    if bad.any():
+        i = np.unravel_index(np.argmax(np.abs(g - o) - tol), g.shape)
+        raise AssertionError(f"{what}: {bad.sum()} of {bad.size} outside tolerance; worst at {i}: "
+                             f"gpu {g[i]!r} oracle {o[i]!r}")
+    return float((np.abs(g - o) / (np.abs(o) + 1e-30)).max())
+
+
+def rand_problem(seed, C, H, W, T, B):
+    g = np.random.Generator(np.random.PCG64(seed))
+    R = g.standard_normal((C, H, W))
+    _, _, delta, e = oracle.edges(R, B)
+    bins = oracle.quantize(R, B, e)
+    if H >= T and W >= T:
+        cR = oracle.reference_cdf(bins, T, B)
+    else:  # any valid cumulative reference of mass T*T
+        cR = np.cumsum(np.bincount(g.integers(0, B, T * T), minlength=B))[None].repeat(C, 0)
+    return bins, delta, e, cR.astype(np.int32)
+
+
+def gpu_score(ctx, bins, delta, e, cR, T, B, sigma=1.0, w1=True):
+    C = bins.shape[0]
+    prm = q.Params.make(C=C, k=0, B=B, T=T, sigma_s=sigma, preproc=q.QFCA_PRE_NONE)
+    m = q.qfca_model_create(ctx, prm, None, None, e, delta, cR)
+    out = q.qfca_score_map(ctx, m, torch.from_numpy(bins).cuda(), amap=True, w1=w1, achan=True)
+    torch.cuda.synchronize()
+    return out, m
+
+
+CASES = [
+    # C, H, W, T, B
+    (3, 20, 17, 5, 6),
+    (4, 64, 64, 7, 16),
+    (2, 70, 131, 7, 16),     # several strips, ragged tail
+    (5, 33, 40, 9, 10),      # B not a power of two
+    (2, 130, 65, 15, 32),    # several bands and strips
+    (1, 40, 40, 31, 64),     # large window, 64 bins
+    (3, 12, 9, 15, 8),       # image smaller than the window
+    (2, 25, 30, 1, 12),      # T = 1
+    (2, 25, 30, 5, 1),       # one bin
+    (9, 21, 23, 3, 4),       # many channels per wavefront, ragged channel group
+    (1, 1, 1, 3, 4),         # single pixel
+    (2, 3, 200, 5, 8),       # very flat image
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "C%d_H%d_W%d_T%d_B%d" % c)
+def test_score_map_matches_oracle(ctx, case):
+    C, H, W, T, B = case
+    say(f"[score parity] C={C} H={H} W={W} T={T} B={B}")
+    bins, delta, e, cR = rand_problem(sum(case), C, H, W, T, B)
+    out, _ = gpu_score(ctx, bins, delta, e, cR, T, B)
+    ref = oracle.score(bins, T, B, cR, delta, 1.0, want_w1=True, want_chan=True)
+    close(out.achan.cpu().numpy(), ref.Achan, "per-channel map")
+    close(out.amap.cpu().numpy(), ref.A, "channel mean")
+    close(out.score.cpu().numpy(), ref.score, "score")
+    close(out.w1.cpu().numpy(), ref.W1, "window W1")
+
+
+def test_score_deterministic(ctx):
+    say("[determinism] C=4 H=64 W=80 T=7 B=16")
+    bins, delta, e, cR = rand_problem(5, 4, 64, 80, 7, 16)
+    a, _ = gpu_score(ctx, bins, delta, e, cR, 7, 16)
+    b, _ = gpu_score(ctx, bins, delta, e, cR, 7, 16)
+    assert torch.equal(a.score, b.score) and torch.equal(a.achan, b.achan)
+
+
+@pytest.mark.parametrize("case", [(3, 20, 17, 5, 6), (2, 64, 70, 7, 16), (2, 130, 100, 15, 32),
+                                  (1, 40, 45, 31, 64), (3, 9, 9, 9, 5), (2, 30, 30, 1, 7)],
+                         ids=lambda c: "C%d_H%d_W%d_T%d_B%d" % c)
+def test_reference_exact(ctx, case):
+    C, H, W, T, B = case
+    say(f"[reference] C={C} H={H} W={W} T={T} B={B}")
+    bins, delta, e, cR = rand_problem(100 + sum(case), C, H, W, T, B)
+    prm = q.Params.make(C=C, k=0, B=B, T=T, preproc=q.QFCA_PRE_NONE)
+    m = q.qfca_model_create(ctx, prm, None, None, e, delta, None)
+    q.qfca_fit_reference(ctx, m, torch.from_numpy(bins).cuda())
+    np.testing.assert_array_equal(m.read("cR"), cR)
+
+
+def edge_band(R, e, k_terms, scale):
+    """True where an FP64 residual lies within the float32 error band of an edge."""
+    C = R.shape[0]
+    gam = (k_terms + 4) * 2.0 ** -23
+    band = np.zeros(R.shape, bool)
+    for c in range(C):
+        ec = e[c].astype(np.float64)
+        if ec.size == 0:
+            continue
+        idx = np.clip(np.searchsorted(ec, R[c]), 0, ec.size - 1)
+        d = np.minimum(np.abs(R[c] - ec[idx]), np.abs(R[c] - ec[np.maximum(idx - 1, 0)]))
+        band[c] = d <= gam * scale[c] + 2.0 ** -23 * np.abs(ec).max()
+    return band
+
+
+@pytest.mark.parametrize("preproc", [0, 1])
+def test_quantize_against_oracle(ctx, preproc):
+    ts, p = qfca_synth.workload_small()
+    X = ts[0].X
+    say(f"[quantize] 64x64 C=64 preproc={preproc}")
+    om, R, obins = oracle.fit(X, p["k"], p["B"], p["T"], preproc=preproc)
+    prm = q.Params.make(C=p["C"], k=p["k"], B=p["B"], T=p["T"], preproc=preproc)
+    m = q.qfca_model_create(ctx, prm, om.mu, om.V, om.edges, om.delta, om.cR)
+    bins, resid = q.qfca_quantize(ctx, m, torch.from_numpy(X).cuda(), resid=True)
+    g = bins.cpu().numpy()
+    r = resid.cpu().numpy().astype(np.float64)
+    # the float32 residual stays within the float32 error bound of the FP64 one
+    scale = np.abs(X.astype(np.float64)).sum(0).max() * np.ones(p["C"]) * (1 + p["k"])
+    assert np.abs(r - R).max() <= 1e-5 * scale.max()
+    band = edge_band(R, om.edges, p["C"] + p["k"], scale)
+    diff = g != obins
+    assert not (diff & ~band).any(), f"{(diff & ~band).sum()} bins differ outside the edge band"
+    assert np.abs(g.astype(int) - obins.astype(int)).max() <= 1
+    # bins are exactly #{m : r_gpu >= e_m} for the GPU's own float32 residual
+    for c in range(p["C"]):
+        np.testing.assert_array_equal(
+            g[c], np.searchsorted(om.edges[c].astype(np.float32), resid.cpu().numpy()[c], side="right"))
+    say(f"  bins differing from the FP64 oracle: {int(diff.sum())} of {diff.size}")
+
+
+def test_fit_against_oracle(ctx):
+    ts, p = qfca_synth.workload_small()
+    X = ts[0].X
+    say("[fit] 64x64 C=64 k=16 B=16 T=7")
+    om, R, obins = oracle.fit(X, p["k"], p["B"], p["T"])
+    prm = q.Params.make(C=p["C"], k=p["k"], B=p["B"], T=p["T"])
+    m = q.qfca_fit_pca(ctx, prm, torch.from_numpy(X).cuda())
+    mu = m.read("mu").astype(np.float64)
+    np.testing.assert_allclose(mu, om.mu, rtol=0, atol=1e-6 * np.abs(om.mu).max() + 1e-7)
+    ev = m.read("evals")
+    np.testing.assert_allclose(ev, om.evals, rtol=1e-9, atol=1e-12 * ev[0])
+    V = m.read("V").astype(np.float64)
+    gap = om.evals[p["k"] - 1] - om.evals[p["k"]]
+    assert gap > 1e-6 * om.evals[0]
+    assert np.abs(V @ V.T - om.V @ om.V.T).max() <= 1e-5
+    lo, hi = m.read("lo"), m.read("hi")
+    span = om.hi - om.lo
+    assert np.abs(lo - om.lo).max() <= 1e-5 * span.max()
+    assert np.abs(hi - om.hi).max() <= 1e-5 * span.max()
+    edges = m.read("edges").astype(np.float64)
+    assert np.abs(edges - om.edges).max() <= 1e-5 * span.max()
+    # reference from the GPU's own bins equals the oracle's reference of those bins
+    gb, _ = q.qfca_quantize(ctx, m, torch.from_numpy(X).cuda())
+    np.testing.assert_array_equal(m.read("cR"), oracle.reference_cdf(gb.cpu().numpy(), p["T"], p["B"]))
+    flips = int((gb.cpu().numpy() != obins).sum())
+    say(f"  zero-shot bins differing from the FP64 oracle: {flips} of {obins.size}")
+    assert flips <= 1e-3 * obins.size
+
+
+def test_full_path_256(ctx):
+    """The 256x256, C=256, k=32, B=32, T=15 workload: the oracle's bins and model
+    through the GPU score path, every pixel compared."""
+    ts, p = qfca_synth.workload_256()
+    X = ts[0].X
+    say("[full 256] oracle fit")
+    om, R, obins = oracle.fit(X, p["k"], p["B"], p["T"])
+    say("[full 256] oracle score")
+    ref = oracle.score(obins, p["T"], p["B"], om.cR, om.delta, 1.0, want_w1=True)
+    say("[full 256] gpu score")
+    out, _ = gpu_score(ctx, obins, om.delta, om.edges, om.cR, p["T"], p["B"])
+    close(out.amap.cpu().numpy(), ref.A, "channel mean 256")
+    close(out.score.cpu().numpy(), ref.score, "score 256")
+    close(out.w1.cpu().numpy(), ref.W1, "W1 256")
+    # and the GPU reference of the oracle's bins is exact
+    prm = q.Params.make(C=p["C"], k=0, B=p["B"], T=p["T"], preproc=q.QFCA_PRE_NONE)
+    m = q.qfca_model_create(ctx, prm, None, None, om.edges, om.delta, None)
+    q.qfca_fit_reference(ctx, m, torch.from_numpy(obins).cuda())
+    np.testing.assert_array_equal(m.read("cR"), om.cR)
