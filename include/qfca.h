@@ -87,6 +87,18 @@ qfca_status qfca_ctx_create(int32_t device, void* hip_stream, qfca_ctx* out);
 qfca_status qfca_ctx_set_stream(qfca_ctx ctx, void* hip_stream);
 qfca_status qfca_ctx_destroy(qfca_ctx ctx);
 
+/* Per-kernel timing for benchmarking: when enabled, the library records a
+ * pair of HIP events on the context's stream around every launch of the
+ * kernels below (a few microseconds of overhead per launch).
+ * qfca_ctx_profile_read synchronises on the recorded events and returns the
+ * summed duration (ms) and the number of launches of one kernel since the
+ * previous read, then resets that kernel's record.  Kernel ids:
+ *   0 score (window histograms, Alg. 1, association), 1 projection +
+ *   quantisation, 2 channel mean, 3 blur. */
+qfca_status qfca_ctx_profile(qfca_ctx ctx, int32_t enable);
+qfca_status qfca_ctx_profile_read(qfca_ctx ctx, int32_t kernel, double* total_ms,
+                                  int64_t* launches);
+
 /* Zero-shot fit on one image (Sec. 3.2, Sec. 3.3).  Synchronous.
  * X: device [C][H][W] float32 with H, W >= T.  Computes, in order:
  *   mean mu and covariance (FP64 on the GPU); the top-k eigenvectors V of the

@@ -29,7 +29,10 @@ STATUS = {0: "QFCA_OK", 1: "QFCA_E_ARG", 2: "QFCA_E_SHAPE", 3: "QFCA_E_NOMEM", 4
 EXPORTS = ("qfca_status_str", "qfca_last_error", "qfca_version", "qfca_ctx_create",
            "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca", "qfca_model_create",
            "qfca_fit_reference", "qfca_quantize", "qfca_score_map", "qfca_model_params",
-           "qfca_model_read", "qfca_model_destroy", "qfca_host_sym_eig")
+           "qfca_model_read", "qfca_model_destroy", "qfca_host_sym_eig", "qfca_ctx_profile",
+           "qfca_ctx_profile_read")
+
+KERNELS = {"score": 0, "proj": 1, "chanmean": 2, "blur": 3}
 
 
 class QfcaError(RuntimeError):
@@ -82,9 +85,13 @@ def lib():
         L.qfca_model_destroy.argtypes = [P]
         L.qfca_host_sym_eig.argtypes = [P, i32, P, P]
         L.qfca_host_sym_eig.restype = i32
+        L.qfca_ctx_profile.argtypes = [P, i32]
+        L.qfca_ctx_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int64)]
         for name in ("qfca_ctx_create", "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca",
                      "qfca_model_create", "qfca_fit_reference", "qfca_quantize", "qfca_score_map",
-                     "qfca_model_params", "qfca_model_read", "qfca_model_destroy"):
+                     "qfca_model_params", "qfca_model_read", "qfca_model_destroy",
+                     "qfca_ctx_profile", "qfca_ctx_profile_read"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -129,6 +136,15 @@ class Context:
     def set_stream(self, stream):
         self.stream = stream
         _check(lib().qfca_ctx_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def profile(self, enable: bool = True):
+        _check(lib().qfca_ctx_profile(self.handle, int(bool(enable))))
+
+    def profile_read(self, kernel: str):
+        """(total_ms, launches) of one kernel since the previous read."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().qfca_ctx_profile_read(self.handle, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def close(self):
         if getattr(self, "handle", None):

@@ -25,11 +25,16 @@ enum Slot {
     SL_COV, SL_MU, SL_RANKS, SL_CR, SL_COUNT
 };
 
+enum { K_SCORE = 0, K_PROJ, K_CHANMEAN, K_BLUR, K_COUNT };
+
 struct qfca_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
     DevBuf scratch[SL_COUNT];
     std::map<long long, ScoreTile> tiles;  // tile-configuration cache
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[K_COUNT];
+    std::vector<hipEvent_t> event_pool;
 };
 
 struct qfca_model_s {
@@ -232,6 +237,40 @@ qfca_model new_model(qfca_ctx ctx, const qfca_params* p) {
     return m;
 }
 
+hipEvent_t take_event(qfca_ctx ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records events around one kernel launch when profiling is on.
+struct KernelTimer {
+    qfca_ctx ctx;
+    int kernel;
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelTimer(qfca_ctx c, int k) : ctx(c), kernel(k) {
+        if (ctx->profiling) {
+            a = take_event(ctx);
+            b = take_event(ctx);
+            if (a) (void)hipEventRecord(a, ctx->stream);
+        }
+    }
+    ~KernelTimer() {
+        if (a && b) {
+            (void)hipEventRecord(b, ctx->stream);
+            ctx->timed[kernel].push_back({a, b});
+        } else {
+            if (a) ctx->event_pool.push_back(a);
+            if (b) ctx->event_pool.push_back(b);
+        }
+    }
+};
+
 ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
     const long long key = (((long long)T * 128 + B) * 4096 + std::min(W, 4095)) * 4096 + std::min(H, 4095);
     auto it = ctx->tiles.find(key);
@@ -292,10 +331,40 @@ qfca_status qfca_ctx_set_stream(qfca_ctx ctx, void* hip_stream) {
     return QFCA_OK;
 }
 
+qfca_status qfca_ctx_profile(qfca_ctx ctx, int32_t enable) {
+    if (!ctx) return fail(QFCA_E_ARG, "ctx is NULL");
+    ctx->profiling = enable != 0;
+    return QFCA_OK;
+}
+
+qfca_status qfca_ctx_profile_read(qfca_ctx ctx, int32_t kernel, double* total_ms, int64_t* launches) {
+    if (!ctx || !total_ms || !launches) return fail(QFCA_E_ARG, "NULL argument");
+    if (kernel < 0 || kernel >= K_COUNT) return fail(QFCA_E_ARG, "unknown kernel id");
+    HIP_TRY(hipSetDevice(ctx->device));
+    double tot = 0.0;
+    int64_t n = 0;
+    for (auto& pr : ctx->timed[kernel]) {
+        HIP_TRY(hipEventSynchronize(pr.second));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        tot += ms;
+        ++n;
+        ctx->event_pool.push_back(pr.first);
+        ctx->event_pool.push_back(pr.second);
+    }
+    ctx->timed[kernel].clear();
+    *total_ms = tot;
+    *launches = n;
+    return QFCA_OK;
+}
+
 qfca_status qfca_ctx_destroy(qfca_ctx ctx) {
     if (!ctx) return QFCA_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (auto& v : ctx->timed)
+        for (auto& pr : v) ctx->event_pool.push_back(pr.first), ctx->event_pool.push_back(pr.second);
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     for (auto& b : ctx->scratch)
         if (b.p) (void)hipFree(b.p);
     delete ctx;
@@ -411,6 +480,7 @@ qfca_status qfca_quantize(qfca_ctx ctx, qfca_model m, const float* X, int32_t H,
     L.preproc = m->p.preproc; L.prec = m->p.proj_prec;
     L.mu = m->d_mu; L.V = m->d_V; L.Vbf = m->d_Vbf; L.edges = m->d_edges; L.lo = m->d_lo;
     L.inv_delta = m->d_invd; L.bins = bins; L.resid = resid;
+    KernelTimer kt(ctx, K_PROJ);
     HIP_TRY(launch_proj(L, ctx->stream));
     return QFCA_OK;
 }
@@ -564,9 +634,18 @@ qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int3
     L.tab = m->tab;
     L.achan = ach; L.w1chan = w1ch;
     L.tile = choose_tile(ctx, C, H, W, m->p.T, m->p.B, m->Bp);
-    HIP_TRY(launch_score(L, s));
-    HIP_TRY(launch_chanmean(ach, w1ch, C, (int)N, am, w1o, s));
-    HIP_TRY(launch_blur(am, H, W, m->p.sigma_s, score, s));
+    {
+        KernelTimer kt(ctx, K_SCORE);
+        HIP_TRY(launch_score(L, s));
+    }
+    {
+        KernelTimer kt(ctx, K_CHANMEAN);
+        HIP_TRY(launch_chanmean(ach, w1ch, C, (int)N, am, w1o, s));
+    }
+    {
+        KernelTimer kt(ctx, K_BLUR);
+        HIP_TRY(launch_blur(am, H, W, m->p.sigma_s, score, s));
+    }
     return QFCA_OK;
 }
 
