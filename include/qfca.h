@@ -99,6 +99,15 @@ qfca_status qfca_ctx_profile(qfca_ctx ctx, int32_t enable);
 qfca_status qfca_ctx_profile_read(qfca_ctx ctx, int32_t kernel, double* total_ms,
                                   int64_t* launches);
 
+/* Tile configuration of the score kernel for later qfca_score_map calls on
+ * this context: Ws output columns per strip, Hb output rows per band, S
+ * channels per wavefront (S * lanes-per-channel <= 64, where lanes per
+ * channel is the next power of two >= max(B, 8)) and the kernel variant
+ * (0: column walk for any T; 1: block walk, T in 3..31).  Ws == 0 restores
+ * the automatic choice.  A tile that does not fit in 64 KiB of LDS makes the
+ * later score call fail with QFCA_E_UNSUPPORTED. */
+qfca_status qfca_ctx_set_tile(qfca_ctx ctx, int32_t Ws, int32_t Hb, int32_t S, int32_t variant);
+
 /* Zero-shot fit on one image (Sec. 3.2, Sec. 3.3).  Synchronous.
  * X: device [C][H][W] float32 with H, W >= T.  Computes, in order:
  *   mean mu and covariance (FP64 on the GPU); the top-k eigenvectors V of the

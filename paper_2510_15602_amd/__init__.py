@@ -30,7 +30,7 @@ EXPORTS = ("qfca_status_str", "qfca_last_error", "qfca_version", "qfca_ctx_creat
            "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca", "qfca_model_create",
            "qfca_fit_reference", "qfca_quantize", "qfca_score_map", "qfca_model_params",
            "qfca_model_read", "qfca_model_destroy", "qfca_host_sym_eig", "qfca_ctx_profile",
-           "qfca_ctx_profile_read")
+           "qfca_ctx_profile_read", "qfca_ctx_set_tile")
 
 KERNELS = {"score": 0, "proj": 1, "chanmean": 2, "blur": 3}
 
@@ -86,12 +86,13 @@ def lib():
         L.qfca_host_sym_eig.argtypes = [P, i32, P, P]
         L.qfca_host_sym_eig.restype = i32
         L.qfca_ctx_profile.argtypes = [P, i32]
+        L.qfca_ctx_set_tile.argtypes = [P, i32, i32, i32, i32]
         L.qfca_ctx_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64)]
         for name in ("qfca_ctx_create", "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca",
                      "qfca_model_create", "qfca_fit_reference", "qfca_quantize", "qfca_score_map",
                      "qfca_model_params", "qfca_model_read", "qfca_model_destroy",
-                     "qfca_ctx_profile", "qfca_ctx_profile_read"):
+                     "qfca_ctx_profile", "qfca_ctx_profile_read", "qfca_ctx_set_tile"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -136,6 +137,10 @@ class Context:
     def set_stream(self, stream):
         self.stream = stream
         _check(lib().qfca_ctx_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def set_tile(self, Ws=0, Hb=0, S=0, variant=1):
+        """Pin the score kernel's tile (Ws=0 restores the automatic choice)."""
+        _check(lib().qfca_ctx_set_tile(self.handle, int(Ws), int(Hb), int(S), int(variant)))
 
     def profile(self, enable: bool = True):
         _check(lib().qfca_ctx_profile(self.handle, int(bool(enable))))

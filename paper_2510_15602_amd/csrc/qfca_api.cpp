@@ -32,6 +32,7 @@ struct qfca_ctx_s {
     hipStream_t stream = nullptr;
     DevBuf scratch[SL_COUNT];
     std::map<long long, ScoreTile> tiles;  // tile-configuration cache
+    ScoreTile tile_override{0, 0, 0, 0};   // Ws == 0: automatic
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[K_COUNT];
     std::vector<hipEvent_t> event_pool;
@@ -279,8 +280,9 @@ ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
     t.S = 64 / Bp;
     t.Ws = 64;
     t.Hb = 64;
-    while (score_lds_bytes(T, Bp, t.S, t.Ws) > 65536 && t.S > 1) t.S >>= 1;
-    while (score_lds_bytes(T, Bp, t.S, t.Ws) > 65536 && t.Ws > 8) t.Ws >>= 1;
+    t.variant = score_has_block_kernel(T) ? 1 : 0;
+    while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.S > 1) t.S >>= 1;
+    while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.Ws > 8) t.Ws >>= 1;
     (void)C;
     ctx->tiles[key] = t;
     return t;
@@ -328,6 +330,22 @@ qfca_status qfca_ctx_create(int32_t device, void* hip_stream, qfca_ctx* out) {
 qfca_status qfca_ctx_set_stream(qfca_ctx ctx, void* hip_stream) {
     if (!ctx) return fail(QFCA_E_ARG, "ctx is NULL");
     ctx->stream = (hipStream_t)hip_stream;
+    return QFCA_OK;
+}
+
+qfca_status qfca_ctx_set_tile(qfca_ctx ctx, int32_t Ws, int32_t Hb, int32_t S, int32_t variant) {
+    if (!ctx) return fail(QFCA_E_ARG, "ctx is NULL");
+    if (Ws == 0) {
+        ctx->tile_override = ScoreTile();
+        ctx->tile_override.Ws = 0;
+        return QFCA_OK;
+    }
+    if (Ws < 1 || Ws > 1024 || Hb < 1 || S < 1 || S > 64 || (variant != 0 && variant != 1))
+        return fail(QFCA_E_ARG, "bad tile");
+    ctx->tile_override.Ws = Ws;
+    ctx->tile_override.Hb = Hb;
+    ctx->tile_override.S = S;
+    ctx->tile_override.variant = variant;
     return QFCA_OK;
 }
 
@@ -633,7 +651,15 @@ qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int3
     L.bins = bins; L.C = C; L.H = H; L.W = W; L.T = m->p.T; L.B = m->p.B;
     L.tab = m->tab;
     L.achan = ach; L.w1chan = w1ch;
-    L.tile = choose_tile(ctx, C, H, W, m->p.T, m->p.B, m->Bp);
+    if (ctx->tile_override.Ws > 0) {
+        L.tile = ctx->tile_override;
+        if (L.tile.S * m->Bp > 64) return fail(QFCA_E_UNSUPPORTED, "S * lanes per channel exceeds 64");
+        if (L.tile.variant == 1 && !score_has_block_kernel(m->p.T)) L.tile.variant = 0;
+        if (score_lds_bytes(m->p.T, m->Bp, L.tile.S, L.tile.Ws, L.tile.variant) > 65536)
+            return fail(QFCA_E_UNSUPPORTED, "tile does not fit in LDS");
+    } else {
+        L.tile = choose_tile(ctx, C, H, W, m->p.T, m->p.B, m->Bp);
+    }
     {
         KernelTimer kt(ctx, K_SCORE);
         HIP_TRY(launch_score(L, s));

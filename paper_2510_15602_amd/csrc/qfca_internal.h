@@ -25,6 +25,7 @@ struct ScoreTile {
     int Ws = 64;
     int Hb = 64;
     int S = 1;
+    int variant = 1;  // 0: runtime-T column walk, 1: compile-time-T block walk (T = 3..31)
 };
 
 // Device-resident tables of a model that the score kernel reads.  For the
@@ -55,7 +56,8 @@ struct ScoreLaunch {
     ScoreTile tile;
 };
 
-size_t score_lds_bytes(int T, int Bp, int S, int Ws);
+size_t score_lds_bytes(int T, int Bp, int S, int Ws, int variant);
+bool score_has_block_kernel(int T);
 hipError_t launch_score(const ScoreLaunch& L, hipStream_t st);
 hipError_t launch_chanmean(const float* achan, const float* w1chan, int C, int N, float* amap,
                            float* w1, hipStream_t st);

@@ -40,7 +40,7 @@ __host__ __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) &
 
 struct KArgs {
     const uint8_t* bins;
-    int C, H, W, T, B, Bp, S, r, m, Ws, Hb;
+    int C, H, W, T, B, Bp, S, r, m, Ws, Hb, WbA;
     const int2* psig;
     const int32_t* cRm1;
     const int32_t* Dm1;
@@ -55,10 +55,12 @@ struct Lds {
     size_t vc, ring, acc, psig, rcp, ering, total;
 };
 
-__host__ __device__ inline Lds lds_layout(int T, int Bp, int S, int Ws) {
+// WbA: allocated bin columns per row (>= Ws + 4r; the block-walk kernel
+// rounds it up to a multiple of T).
+__host__ __device__ inline Lds lds_layout(int T, int Bp, int S, int Ws, int WbA) {
     (void)Bp;
-    const int r = T / 2, m = T * T;
-    const size_t WbMax = (size_t)Ws + 4 * r;
+    const int m = T * T;
+    const size_t WbMax = (size_t)WbA;
     Lds L;
     size_t off = 0;
     L.vc = off;    off += align16(WbMax * 64);
@@ -87,11 +89,11 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
     const int cbase = blockIdx.z * S;
     const int c = cbase + s;
     const bool cval = (s < S) && (c < a.C);
-    const int WbMax = a.Ws + 4 * r;
+    const int WbMax = a.WbA;
     const int Wb = ws + 4 * r;
     const int xb0 = x0 - 2 * r;
 
-    const Lds L = lds_layout(T, Bp, S, a.Ws);
+    const Lds L = lds_layout(T, Bp, S, a.Ws, a.WbA);
     uint8_t* vc = smem + L.vc;
     uint8_t* ring = smem + L.ring;
     float* acc = (float*)(smem + L.acc);
@@ -255,6 +257,232 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
     }
 }
 
+// Same computation as k_score with the window side T fixed at compile time.
+// Each row is walked in blocks of T columns: the T steps of a block are
+// straight-line code (no uniform branches inside a block), and the values
+// that leave the running sums T columns later (vertical counts, per-bin
+// errors) stay in register rings, so the LDS accesses of the T steps are
+// independent of each other and overlap.  Blocks whose windows are all full
+// take the equal-mass fast path; blocks touching the image border take the
+// clipped-window path.
+template <int T>
+__global__ __launch_bounds__(64) void k_score_t(KArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int r = T / 2, m = T * T, T1 = T + 1;
+    const int lane = threadIdx.x;
+    const int Bp = a.Bp, S = a.S, H = a.H, W = a.W;
+    const int s = lane / Bp;
+    const int sa = s < S ? s : S - 1;
+    const int j = lane - s * Bp;
+    const int x0 = blockIdx.x * a.Ws;
+    const int xe = min(W, x0 + a.Ws);
+    const int ws = xe - x0;
+    const int y0 = blockIdx.y * a.Hb;
+    const int ye = min(H, y0 + a.Hb);
+    const int cbase = blockIdx.z * S;
+    const int c = cbase + s;
+    const bool cval = (s < S) && (c < a.C);
+    const int WbMax = a.WbA;                        // allocated bin columns (multiple of T)
+    const int Wb = ws + 4 * r;                      // used bin columns [x0-2r, xe+2r)
+    const int nblk = (Wb + T - 1) / T;
+    const int xb0 = x0 - 2 * r;
+
+    const Lds L = lds_layout(T, Bp, S, a.Ws, a.WbA);
+    uint8_t* vc = smem + L.vc;
+    uint8_t* ring = smem + L.ring;
+    float* acc = (float*)(smem + L.acc);
+    int2* psig = (int2*)(smem + L.psig);
+    float* rcp = (float*)(smem + L.rcp);
+
+    for (int t = lane; t < S * (m + 1); t += 64) {
+        const int ss = t / (m + 1), tt = t - ss * (m + 1);
+        const int cc = cbase + ss;
+        psig[t] = (cc < a.C) ? a.psig[(size_t)cc * (m + 1) + tt] : make_int2(0, 0);
+    }
+    for (int t = lane; t <= m; t += 64) rcp[t] = a.rcp[t];
+    for (int t = lane; t < WbMax * 16; t += 64) ((uint32_t*)vc)[t] = 0u;
+    for (int t = lane; t < T * S * a.Ws; t += 64) acc[t] = 0.f;
+    const int ci = cval ? c : 0;
+    const int crm1 = a.cRm1[ci * Bp + j];
+    const int dm1 = a.Dm1[ci * Bp + j];
+    const int crl = a.cRl[ci * Bp + j];
+    const bool binok = cval && (j < a.B);
+    const bool w1ok = cval && (j < a.B - 1);
+    const bool want_w1 = a.w1chan != nullptr;
+    constexpr float inv_m = 1.0f / (float)m;
+    __syncthreads();
+
+    auto load_row = [&](int yy) {
+        uint8_t* dst = ring + (size_t)(yy % T1) * S * WbMax;
+        for (int ss = 0; ss < S; ++ss) {
+            const int cc = cbase + ss;
+            const uint8_t* src = a.bins + ((size_t)(cc < a.C ? cc : 0) * H + yy) * W;
+            for (int q = lane; q < WbMax; q += 64) {
+                const int xx = xb0 + q;
+                dst[ss * WbMax + q] = (cc < a.C && q < Wb && xx >= 0 && xx < W) ? src[xx] : (uint8_t)0xFF;
+            }
+        }
+    };
+
+    const int ys = max(0, y0 - r);
+    const int yend = min(H, ye + r);
+    const int lo_add = max(0, ys - r);
+    const int hi_add = min(H, ys + r);
+    for (int yy = lo_add; yy < hi_add; ++yy) {
+        load_row(yy);
+        __syncthreads();
+        const uint8_t* row = ring + (size_t)(yy % T1) * S * WbMax + sa * WbMax;
+        for (int q = 0; q < WbMax; ++q) vc[q * 64 + lane] += (row[q] <= j) ? 1 : 0;
+        __syncthreads();
+    }
+
+    for (int y = ys; y < yend; ++y) {
+        const int add = (y + r) < H ? 1 : 0;
+        const int rem = (y - r - 1) >= lo_add ? 1 : 0;
+        if (add) load_row(y + r);
+        __syncthreads();
+        const uint8_t* rowA = ring + (size_t)((y + r) % T1) * S * WbMax + sa * WbMax;
+        const uint8_t* rowR = ring + (size_t)((y - r - 1 + T1) % T1) * S * WbMax + sa * WbMax;
+        const int ny = min(H - 1, y + r) - max(0, y - r) + 1;
+        const bool row_full = (ny == T);
+        const bool own_row = (y >= y0) && (y < ye);
+        const bool w1_row = want_w1 && own_row;
+        int cP = 0;
+        double hs = 0.0;
+        int vring[T];
+        double ering[T];
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            vring[k] = 0;
+            ering[k] = 0.0;
+        }
+        for (int blk = 0; blk < nblk; ++blk) {
+            const int q0 = blk * T;
+            // patch columns of this block: p = xb0 + q - r, q in [q0, q0 + T)
+            const int p0 = xb0 + q0 - r;
+            const bool full = row_full && (q0 >= 2 * r) && (q0 + T <= Wb) && (p0 >= r) &&
+                              (p0 + T - 1 <= W - 1 - r);
+            float ev[T];
+            int cpv[T];
+            if (full) {
+#pragma unroll
+                for (int k = 0; k < T; ++k) {
+                    const int q = q0 + k;
+                    int v = vc[q * 64 + lane];
+                    v += ((rowA[q] <= j) ? add : 0) - ((rowR[q] <= j) ? rem : 0);
+                    vc[q * 64 + lane] = (uint8_t)v;
+                    cP += v - vring[k];
+                    vring[k] = v;
+                    cpv[k] = cP;
+                    int cPm1 = lane_prev(cP);
+                    if (j == 0) cPm1 = 0;
+                    const int psv = psig[sa * (m + 1) + cP].x;
+                    int psu = lane_prev(psv);
+                    if (j == 0) psu = 0;
+                    const int u = cPm1, vv = cP;
+                    const int sc = min(max(crm1, u), vv);
+                    const int pss = (crm1 <= u) ? psu : ((crm1 >= vv) ? psv : dm1);
+                    const int I = (psv - pss) + (psu - pss) + j * (2 * sc - u - vv);
+                    const int P = vv - u;
+                    ev[k] = binok ? (float)I * rcp[P] : 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < T; ++k) {
+                    const int q = q0 + k;
+                    const int xl = xb0 + q;
+                    const bool inimg = (q < Wb) && (xl >= 0) && (xl < W);
+                    int v = vc[q * 64 + lane];
+                    v += ((rowA[q] <= j) ? add : 0) - ((rowR[q] <= j) ? rem : 0);
+                    v = inimg ? v : 0;
+                    vc[q * 64 + lane] = (uint8_t)v;
+                    cP += v - vring[k];
+                    vring[k] = v;
+                    cpv[k] = cP;
+                    const int p = xl - r;
+                    const bool pval = (q >= 2 * r) && (q < Wb) && (p >= 0) && (p < W);
+                    const int nx = max(1, min(W - 1, p + r) - max(0, p - r) + 1);
+                    const int n = ny * nx;
+                    int cPm1 = lane_prev(cP);
+                    if (j == 0) cPm1 = 0;
+                    const int av = cP * m;
+                    int q0d = (int)((float)av * rcp[min(n, m)]);
+                    q0d = max(0, min(q0d, m));
+                    if (q0d < m && (q0d + 1) * n <= av) q0d++;
+                    if (q0d > 0 && q0d * n > av) q0d--;
+                    const int2 ps = psig[sa * (m + 1) + q0d];
+                    const int phia = n * ps.x + (av - q0d * n) * ps.y;
+                    int phiu = lane_prev(phia);
+                    if (j == 0) phiu = 0;
+                    const int au = cPm1 * m;
+                    const int cm = crm1 * n;
+                    const int sc = min(max(cm, au), av);
+                    const int phis = (cm <= au) ? phiu : ((cm >= av) ? phia : n * dm1);
+                    const int I = (phia - phis) + (phiu - phis) + j * (2 * sc - au - av);
+                    const int P = min(max(cP - cPm1, 0), m);
+                    ev[k] = (binok && pval) ? (float)I * rcp[P] * inv_m : 0.f;
+                }
+            }
+            // window W1 by-product for the owned patch columns of this block
+            if (w1_row) {
+#pragma unroll
+                for (int k = 0; k < T; ++k) {
+                    const int p = xb0 + q0 + k - r;
+                    if (p >= x0 && p < xe) {
+                        const int nx = min(W - 1, p + r) - max(0, p - r) + 1;
+                        const int n = ny * nx;
+                        int d = w1ok ? abs(cpv[k] * m - crl * n) : 0;
+                        for (int o = Bp >> 1; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+                        if (cval && j == 0)
+                            a.w1chan[((size_t)c * H + y) * W + p] =
+                                (float)(a.delta[c] * (double)d / ((double)n * (double)m));
+                    }
+                }
+            }
+            // horizontal window sums and the gather into the pending rows
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const double ed = (double)ev[k];
+                hs += ed - ering[k];
+                ering[k] = ed;
+                const int xo = q0 + k - 4 * r;  // local output column of this step
+                const bool xok = (xo >= 0) && (xo < ws);
+                const float hf = (float)hs;
+                const int xoc = xok ? xo : 0;
+                for (int tc = 0; tc < T; tc += Bp) {
+                    const int t = tc + j;
+                    const int yo = y - r + t;
+                    const bool ok = xok && cval && (t < T) && (yo >= y0) && (yo < ye);
+                    const int yoc = ok ? yo : y0;
+                    const int b = ring[(size_t)(yoc % T1) * S * WbMax + sa * WbMax + xoc + 2 * r];
+                    const float hv = __shfl(hf, sa * Bp + (b & (Bp - 1)), 64);
+                    if (ok) acc[((yoc % T) * S + sa) * a.Ws + xoc] += hv;
+                }
+            }
+        }
+        int yo_lo = y - r, yo_hi = (y < H - 1) ? y - r : H - 1;
+        yo_lo = max(yo_lo, y0);
+        yo_hi = min(yo_hi, ye - 1);
+        __syncthreads();
+        for (int yo = yo_lo; yo <= yo_hi; ++yo) {
+            const int nyo = min(H - 1, yo + r) - max(0, yo - r) + 1;
+            for (int t = lane; t < S * ws; t += 64) {
+                const int ss = t / ws, xo = t - ss * ws;
+                const int cc = cbase + ss;
+                float* ap = acc + ((yo % T) * S + ss) * a.Ws + xo;
+                if (cc < a.C) {
+                    const int xg = x0 + xo;
+                    const int nxo = min(W - 1, xg + r) - max(0, xg - r) + 1;
+                    a.achan[((size_t)cc * H + yo) * W + xg] =
+                        (float)((double)(*ap) * a.delta[cc] / (double)(nyo * nxo));
+                }
+                *ap = 0.f;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // A(x) = (1/C) sum_c achan[c][x] in double precision, fixed channel order.
 __global__ void k_chanmean(const float* __restrict__ achan, const float* __restrict__ w1chan,
                            int C, int N, float* __restrict__ amap, float* __restrict__ w1) {
@@ -322,7 +550,16 @@ __global__ __launch_bounds__(256) void k_blur(const float* __restrict__ in, int 
 
 }  // namespace
 
-size_t score_lds_bytes(int T, int Bp, int S, int Ws) { return lds_layout(T, Bp, S, Ws).total; }
+bool score_has_block_kernel(int T) { return T >= 3 && T <= 31 && (T & 1); }
+
+static int alloc_cols(int T, int Ws, int variant) {
+    const int w = Ws + 4 * (T / 2);
+    return (variant == 1 && score_has_block_kernel(T)) ? (w + T - 1) / T * T : w;
+}
+
+size_t score_lds_bytes(int T, int Bp, int S, int Ws, int variant) {
+    return lds_layout(T, Bp, S, Ws, alloc_cols(T, Ws, variant)).total;
+}
 
 hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     KArgs a;
@@ -334,14 +571,28 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     a.m = L.T * L.T;
     a.Ws = L.tile.Ws;
     a.Hb = L.tile.Hb;
+    const int variant = (L.tile.variant == 1 && score_has_block_kernel(L.T)) ? 1 : 0;
+    a.WbA = alloc_cols(L.T, a.Ws, variant);
     a.psig = L.tab.psig; a.cRm1 = L.tab.cRm1; a.Dm1 = L.tab.Dm1; a.cRl = L.tab.cRl;
     a.rcp = L.tab.rcp; a.delta = L.tab.delta;
     a.achan = L.achan; a.w1chan = L.w1chan;
     if (a.S < 1 || a.S * a.Bp > 64) return hipErrorInvalidValue;
-    const size_t lds = score_lds_bytes(a.T, a.Bp, a.S, a.Ws);
+    const size_t lds = score_lds_bytes(a.T, a.Bp, a.S, a.Ws, variant);
     if (lds > 65536) return hipErrorInvalidValue;
     dim3 grid((L.W + a.Ws - 1) / a.Ws, (L.H + a.Hb - 1) / a.Hb, (L.C + a.S - 1) / a.S);
-    hipLaunchKernelGGL(k_score, grid, dim3(64), lds, st, a);
+    if (variant == 0) {
+        hipLaunchKernelGGL(k_score, grid, dim3(64), lds, st, a);
+        return hipGetLastError();
+    }
+    switch (a.T) {
+#define QFCA_T_CASE(TT) \
+        case TT: hipLaunchKernelGGL(k_score_t<TT>, grid, dim3(64), lds, st, a); break;
+        QFCA_T_CASE(3) QFCA_T_CASE(5) QFCA_T_CASE(7) QFCA_T_CASE(9) QFCA_T_CASE(11)
+        QFCA_T_CASE(13) QFCA_T_CASE(15) QFCA_T_CASE(17) QFCA_T_CASE(19) QFCA_T_CASE(21)
+        QFCA_T_CASE(23) QFCA_T_CASE(25) QFCA_T_CASE(27) QFCA_T_CASE(29) QFCA_T_CASE(31)
+#undef QFCA_T_CASE
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -87,25 +87,51 @@ CASES = [
 ]
 
 
+def lanes(B):
+    b = 8
+    while b < B:
+        b *= 2
+    return b
+
+
+# (Ws, Hb, S, variant); Ws = 0 is the automatic choice
+TILES = [(0, 0, 0, 1), (64, 64, 0, 0), (16, 8, 1, 1), (24, 5, 0, 1), (40, 13, 1, 0)]
+
+
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "C%d_H%d_W%d_T%d_B%d" % c)
 def test_score_map_matches_oracle(ctx, case):
     C, H, W, T, B = case
-    say(f"[score parity] C={C} H={H} W={W} T={T} B={B}")
     bins, delta, e, cR = rand_problem(sum(case), C, H, W, T, B)
-    out, _ = gpu_score(ctx, bins, delta, e, cR, T, B)
     ref = oracle.score(bins, T, B, cR, delta, 1.0, want_w1=True, want_chan=True)
-    close(out.achan.cpu().numpy(), ref.Achan, "per-channel map")
-    close(out.amap.cpu().numpy(), ref.A, "channel mean")
-    close(out.score.cpu().numpy(), ref.score, "score")
-    close(out.w1.cpu().numpy(), ref.W1, "window W1")
+    try:
+        for (Ws, Hb, S, var) in TILES:
+            S = S or 64 // lanes(B)
+            say(f"[score parity] C={C} H={H} W={W} T={T} B={B} tile Ws={Ws} Hb={Hb} S={S} variant={var}")
+            ctx.set_tile(Ws, Hb, S, var)
+            out, _ = gpu_score(ctx, bins, delta, e, cR, T, B)
+            what = f"tile {(Ws, Hb, S, var)}"
+            close(out.achan.cpu().numpy(), ref.Achan, "per-channel map " + what)
+            close(out.amap.cpu().numpy(), ref.A, "channel mean " + what)
+            close(out.score.cpu().numpy(), ref.score, "score " + what)
+            close(out.w1.cpu().numpy(), ref.W1, "window W1 " + what)
+    finally:
+        ctx.set_tile(0)
 
 
-def test_score_deterministic(ctx):
+def test_score_deterministic_and_tile_independent(ctx):
     say("[determinism] C=4 H=64 W=80 T=7 B=16")
     bins, delta, e, cR = rand_problem(5, 4, 64, 80, 7, 16)
     a, _ = gpu_score(ctx, bins, delta, e, cR, 7, 16)
     b, _ = gpu_score(ctx, bins, delta, e, cR, 7, 16)
     assert torch.equal(a.score, b.score) and torch.equal(a.achan, b.achan)
+    # the per-bin errors and their sums do not depend on the tiling: the
+    # per-channel maps agree to rounding of the final float32 scaling
+    try:
+        ctx.set_tile(16, 8, 1, 1)
+        c, _ = gpu_score(ctx, bins, delta, e, cR, 7, 16)
+    finally:
+        ctx.set_tile(0)
+    close(c.achan.cpu().numpy(), a.achan.cpu().numpy(), "tile independence")
 
 
 @pytest.mark.parametrize("case", [(3, 20, 17, 5, 6), (2, 64, 70, 7, 16), (2, 130, 100, 15, 32),
