@@ -108,7 +108,12 @@ def test_score_map_matches_oracle(ctx, case):
             S = S or 64 // lanes(B)
             say(f"[score parity] C={C} H={H} W={W} T={T} B={B} tile Ws={Ws} Hb={Hb} S={S} variant={var}")
             ctx.set_tile(Ws, Hb, S, var)
-            out, _ = gpu_score(ctx, bins, delta, e, cR, T, B)
+            try:
+                out, _ = gpu_score(ctx, bins, delta, e, cR, T, B)
+            except q.QfcaError as err:  # tile larger than the LDS budget: refused before launch
+                assert err.status == 7, err
+                say("   (tile does not fit in LDS; refused)")
+                continue
             what = f"tile {(Ws, Hb, S, var)}"
             close(out.achan.cpu().numpy(), ref.Achan, "per-channel map " + what)
             close(out.amap.cpu().numpy(), ref.A, "channel mean " + what)
