@@ -50,6 +50,8 @@ struct qfca_model_s {
     bool has_ref = false, has_evals = false, has_lohi = false;
     float* d_mu = nullptr;
     float* d_V = nullptr;
+    void* d_V1 = nullptr;  // MFMA operand tables of the projection (nullptr: VALU path)
+    void* d_V2 = nullptr;
     uint16_t* d_Vbf = nullptr;
     float* d_edges = nullptr;
     float* d_lo = nullptr;
@@ -168,6 +170,31 @@ qfca_status upload_projection(qfca_model m) {
     HIP_TRY(upload(m, &m->d_mu, muf.data(), muf.size()));
     HIP_TRY(upload(m, &m->d_V, Vf.data(), Vf.size()));
     HIP_TRY(upload(m, &m->d_Vbf, Vb.data(), Vb.size()));
+    m->d_V1 = m->d_V2 = nullptr;
+    if (pre && k > 0 && mfma_cmax(C, m->p.proj_prec) && mfma_kt(k, m->p.proj_prec)) {
+        std::vector<float> Vk((size_t)C * k);
+        for (size_t i = 0; i < Vk.size(); ++i) Vk[i] = (float)m->V[i];
+        if (m->p.proj_prec == QFCA_PREC_BF16) {
+            std::vector<uint16_t> Vkb(Vk.size()), T1, T2;
+            for (size_t i = 0; i < Vk.size(); ++i) Vkb[i] = f32_to_bf16(Vk[i]);
+            mfma_tables_bf16(Vkb.data(), C, k, T1, T2);
+            uint16_t *p1 = nullptr, *p2 = nullptr;
+            HIP_TRY(upload(m, &p1, T1.data(), T1.size()));
+            HIP_TRY(upload(m, &p2, T2.data(), T2.size()));
+            m->d_V1 = p1;
+            m->d_V2 = p2;
+        } else {
+            std::vector<float> T1, T2;
+            mfma_tables_f32(Vk.data(), C, k, T1, T2);
+            float *p1 = nullptr, *p2 = nullptr;
+            HIP_TRY(upload(m, &p1, T1.data(), T1.size()));
+            HIP_TRY(upload(m, &p2, T2.data(), T2.size()));
+            m->d_V1 = p1;
+            m->d_V2 = p2;
+        }
+    } else if (pre && k > 0 && m->p.proj_prec == QFCA_PREC_BF16) {
+        return fail(QFCA_E_UNSUPPORTED, "the BF16 projection needs C <= 512");
+    }
     return QFCA_OK;
 }
 
@@ -498,6 +525,7 @@ qfca_status qfca_quantize(qfca_ctx ctx, qfca_model m, const float* X, int32_t H,
     L.preproc = m->p.preproc; L.prec = m->p.proj_prec;
     L.mu = m->d_mu; L.V = m->d_V; L.Vbf = m->d_Vbf; L.edges = m->d_edges; L.lo = m->d_lo;
     L.inv_delta = m->d_invd; L.bins = bins; L.resid = resid;
+    L.V1 = m->d_V1; L.V2 = m->d_V2;
     KernelTimer kt(ctx, K_PROJ);
     HIP_TRY(launch_proj(L, ctx->stream));
     return QFCA_OK;
@@ -576,6 +604,7 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
         L.X = X; L.C = C; L.N = (int)N; L.k = k; L.B = B; L.preproc = p->preproc;
         L.prec = p->proj_prec; L.mu = m->d_mu; L.V = m->d_V; L.Vbf = m->d_Vbf;
         L.edges = nullptr; L.lo = nullptr; L.inv_delta = nullptr; L.bins = nullptr; L.resid = resid;
+        L.V1 = m->d_V1; L.V2 = m->d_V2;
         HIP_TRY(launch_proj(L, s));
     }
     const double hq[2] = {(double)(N - 1) * (double)p->q_lo, (double)(N - 1) * (double)p->q_hi};

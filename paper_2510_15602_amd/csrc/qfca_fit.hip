@@ -359,6 +359,8 @@ hipError_t launch_refselect(const uint32_t* counts, int C, int B, int m, long lo
 }
 
 hipError_t launch_proj(const ProjLaunch& L, hipStream_t st) {
+    if (L.preproc && L.k > 0 && L.V1 && L.V2) return launch_proj_mfma(L, L.V1, L.V2, st);
+    if (L.prec == QFCA_PREC_BF16 && L.preproc && L.k > 0) return hipErrorInvalidValue;
     PArgs a;
     a.X = L.X; a.C = L.C; a.N = L.N; a.k = L.k; a.B = L.B; a.preproc = L.preproc;
     a.mu = L.mu; a.V = L.V; a.edges = L.edges; a.lo = L.lo; a.inv_delta = L.inv_delta;

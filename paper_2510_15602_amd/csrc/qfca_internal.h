@@ -83,8 +83,20 @@ struct ProjLaunch {
     const float* inv_delta; // [C] (0 for a degenerate channel)
     uint8_t* bins;          // [C][N] or nullptr
     float* resid;           // [C][N] or nullptr
+    const void* V1 = nullptr;  // MFMA operand tables (precision of prec), or nullptr
+    const void* V2 = nullptr;
 };
 hipError_t launch_proj(const ProjLaunch& L, hipStream_t st);
+
+// MFMA projection: padded channel count (0 if C > 512), number of 16-wide
+// component tiles (0 if k is 0 or > 64), host builders of the operand
+// tables, and the launcher.
+int mfma_cmax(int C, int prec);
+int mfma_kt(int k, int prec);
+void mfma_tables_f32(const float* V, int C, int k, std::vector<float>& V1, std::vector<float>& V2);
+void mfma_tables_bf16(const uint16_t* Vb, int C, int k, std::vector<uint16_t>& V1,
+                      std::vector<uint16_t>& V2);
+hipError_t launch_proj_mfma(const ProjLaunch& L, const void* V1, const void* V2, hipStream_t st);
 
 // Fit statistics.
 hipError_t launch_mean(const float* X, int C, long N, double* mu, hipStream_t st);

@@ -1,0 +1,347 @@
+// Projection + quantisation on MFMA for gfx950 (Sec. 3.3 residual, Sec. 3.1
+// bins): r = (x - mu) - V (V^T (x - mu)), then bin = #{m : r >= edge_m}.
+//
+// One wavefront owns 16 pixels.  Their centred features d stay in registers
+// for the whole pixel tile, laid out as the B operand of the first product
+// (Z = V^T D, K = channels).  Because the summation order over K is free, the
+// channel order of that product and the row order of the second product
+// (V Z, M = channels) are chosen so that every output of the second product
+// lands in the lane and register that already hold the same channel's d:
+// the residual is formed with no data movement.  Likewise the component order
+// of the second product's K dimension is the one in which Z comes out of the
+// first.  V is stored twice on the device in exactly these operand orders
+// (built on the host with the model), so every operand load is contiguous.
+//
+// FP32 path: v_mfma_f32_16x16x4f32.  Lane l = n + 16 g feeds A[n][g] and
+//   B[g][n] and receives D[4 g + v][n] in register v.
+//   GEMM1 step s: lane group g supplies channel 4 s + g.
+//   GEMM2 tile t: output row 4 g + v is channel 16 t + 4 v + g (held in d[4 t + v]);
+//   K step u supplies component 16 (u / 4) + 4 g + (u % 4) (held in z[u / 4][u % 4]).
+// BF16 path: v_mfma_f32_16x16x32_bf16, 8 K values per lane, FP32 accumulation;
+//   GEMM1 step s: lane group g supplies channels 32 s + 8 g + t (t < 8);
+//   GEMM2 tile 2 s + h: output row 4 g + v is channel 32 s + 8 g + 4 h + v;
+//   K step u supplies components 16 (2 u + t / 4) + 4 g + (t % 4).
+// The subtraction, the comparisons with the edges and all counting stay FP32.
+#include <algorithm>
+
+#include "qfca_internal.h"
+
+namespace qfca {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct MArgs {
+    const float* X;
+    int C, N, k, B;
+    const float* mu;
+    const void* V1;  // GEMM1 A operands
+    const void* V2;  // GEMM2 A operands
+    const float* edges;
+    const float* lo;
+    const float* inv_delta;
+    uint8_t* bins;
+    float* resid;
+    int ntiles;
+};
+
+__device__ __forceinline__ int bin_of_m(float rr, const float* __restrict__ e, float lo, float idl, int B) {
+    if (idl == 0.f) return 0;
+    int b = (int)floorf((rr - lo) * idl);
+    b = b < 0 ? 0 : (b > B - 1 ? B - 1 : b);
+    while (b > 0 && rr < e[b - 1]) --b;
+    while (b < B - 1 && rr >= e[b]) ++b;
+    return b;
+}
+
+__device__ __forceinline__ void emit(const MArgs& a, int c, int px, float r, const float* slo,
+                                     const float* sid) {
+    if (a.resid) a.resid[(size_t)c * a.N + px] = r;
+    if (a.bins)
+        a.bins[(size_t)c * a.N + px] =
+            (uint8_t)bin_of_m(r, a.edges + (size_t)c * (a.B - 1), slo[c], sid[c], a.B);
+}
+
+// ------------------------------------------------------------------------
+// The four wavefronts of a block share one 16-pixel tile: wave w owns the
+// channel quarter [w CMAX/4, (w+1) CMAX/4) in both products.  Partial Z of the
+// four quarters are added through LDS in a fixed order.
+template <int CMAX, int KT, bool VLDS>
+__global__ __launch_bounds__(256) void k_proj_f32_mfma(MArgs a) {
+    constexpr int NSW = CMAX / 16;   // GEMM1 K steps per wave (4 channels each)
+    constexpr int NTW = CMAX / 64;   // GEMM2 channel tiles per wave (16 channels each)
+    constexpr int NU = 4 * KT;       // GEMM2 K steps
+    constexpr int VSZ = CMAX * KT * 16;
+    extern __shared__ __align__(16) float lds[];
+    float* smu = lds;
+    float* slo = smu + CMAX;
+    float* sid = slo + CMAX;
+    float* zp = sid + CMAX;              // [4 waves][KT][4][64]
+    float* sv1 = zp + 4 * KT * 4 * 64;
+    float* sv2 = sv1 + (VLDS ? VSZ : 0);
+    for (int i = threadIdx.x; i < CMAX; i += 256) {
+        const bool ok = i < a.C;
+        smu[i] = ok ? a.mu[i] : 0.f;
+        slo[i] = ok && a.lo ? a.lo[i] : 0.f;
+        sid[i] = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
+    }
+    const float* V1 = (const float*)a.V1;
+    const float* V2 = (const float*)a.V2;
+    if (VLDS) {
+        for (int i = threadIdx.x; i < VSZ; i += 256) {
+            sv1[i] = V1[i];
+            sv2[i] = V2[i];
+        }
+        V1 = sv1;
+        V2 = sv2;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int px = tile * 16 + n;
+        const bool pxok = px < a.N;
+        float d[NSW];
+        floatx4 z[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) z[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < NSW; ++i) {
+            const int s = w * NSW + i;
+            const int c = 4 * s + g;
+            const float x = (pxok && c < a.C) ? a.X[(size_t)c * a.N + px] : 0.f;
+            d[i] = (c < a.C) ? x - smu[c] : 0.f;
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+                z[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(V1[((s * KT + kt) * 4 + g) * 16 + n], d[i],
+                                                             z[kt], 0, 0, 0);
+            if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zp[((w * KT + kt) * 4 + v) * 64 + lane] = z[kt][v];
+        __syncthreads();
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float acc = zp[((0 * KT + kt) * 4 + v) * 64 + lane];
+                acc += zp[((1 * KT + kt) * 4 + v) * 64 + lane];
+                acc += zp[((2 * KT + kt) * 4 + v) * 64 + lane];
+                acc += zp[((3 * KT + kt) * 4 + v) * 64 + lane];
+                z[kt][v] = acc;
+            }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NTW; ++i) {
+            const int t = w * NTW + i;
+            floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(V2[((t * NU + u) * 4 + g) * 16 + n],
+                                                           z[u >> 2][u & 3], acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = 16 * t + 4 * v + g;
+                const float r = d[4 * i + v] - acc[v];
+                if (pxok && c < a.C) emit(a, c, px, r, slo, sid);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+template <int CMAX, int KT, bool VLDS>
+__global__ __launch_bounds__(256) void k_proj_bf16_mfma(MArgs a) {
+    constexpr int NSW = CMAX / 128;  // GEMM1 K steps per wave (32 channels each)
+    constexpr int NU = KT / 2;       // GEMM2 K steps (32 components each)
+    constexpr int VSZ = CMAX * KT * 16;  // bf16 elements per table
+    extern __shared__ __align__(16) float lds[];
+    float* smu = lds;
+    float* slo = smu + CMAX;
+    float* sid = slo + CMAX;
+    float* zp = sid + CMAX;              // [4 waves][KT][4][64]
+    bf16x8* sv1 = (bf16x8*)(zp + 4 * KT * 4 * 64);
+    bf16x8* sv2 = sv1 + (VLDS ? VSZ / 8 : 0);
+    for (int i = threadIdx.x; i < CMAX; i += 256) {
+        const bool ok = i < a.C;
+        smu[i] = ok ? a.mu[i] : 0.f;
+        slo[i] = ok && a.lo ? a.lo[i] : 0.f;
+        sid[i] = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
+    }
+    const bf16x8* V1 = (const bf16x8*)a.V1;
+    const bf16x8* V2 = (const bf16x8*)a.V2;
+    if (VLDS) {
+        for (int i = threadIdx.x; i < VSZ / 8; i += 256) {
+            sv1[i] = V1[i];
+            sv2[i] = V2[i];
+        }
+        V1 = sv1;
+        V2 = sv2;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int px = tile * 16 + n;
+        const bool pxok = px < a.N;
+        float d[NSW][8];
+        floatx4 z[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) z[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < NSW; ++i) {
+            const int s = w * NSW + i;
+            bf16x8 bv;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int c = 32 * s + 8 * g + t;
+                const float x = (pxok && c < a.C) ? a.X[(size_t)c * a.N + px] : 0.f;
+                d[i][t] = (c < a.C) ? x - smu[c] : 0.f;
+                bv[t] = (__bf16)d[i][t];
+            }
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+                z[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V1[((s * KT + kt) * 4 + g) * 16 + n], bv,
+                                                                z[kt], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zp[((w * KT + kt) * 4 + v) * 64 + lane] = z[kt][v];
+        __syncthreads();
+        bf16x8 zb[NU];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float acc = zp[((0 * KT + kt) * 4 + v) * 64 + lane];
+                acc += zp[((1 * KT + kt) * 4 + v) * 64 + lane];
+                acc += zp[((2 * KT + kt) * 4 + v) * 64 + lane];
+                acc += zp[((3 * KT + kt) * 4 + v) * 64 + lane];
+                zb[kt >> 1][4 * (kt & 1) + v] = (__bf16)acc;
+            }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NSW; ++i) {
+            const int s = w * NSW + i;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t2 = 2 * s + h;
+                floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int u = 0; u < NU; ++u)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V2[((t2 * NU + u) * 4 + g) * 16 + n],
+                                                                  zb[u], acc, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = 32 * s + 8 * g + 4 * h + v;
+                    const float r = d[i][4 * h + v] - acc[v];
+                    if (pxok && c < a.C) emit(a, c, px, r, slo, sid);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+}
+
+template <class K>
+hipError_t go(K kern, const MArgs& a, size_t lds, hipStream_t st) {
+    const int blocks = std::max(1, std::min(a.ntiles, 4096));
+    if (lds > 65536) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int mfma_cmax(int C, int prec) {
+    int cm = prec == QFCA_PREC_BF16 ? 128 : 64;
+    while (cm < C) cm <<= 1;
+    return cm <= 512 ? cm : 0;
+}
+
+int mfma_kt(int k, int prec) {
+    if (k <= 0 || k > 64) return 0;
+    int kt = (k + 15) / 16;
+    if (prec == QFCA_PREC_BF16) kt = (kt + 1) / 2 * 2;
+    return kt == 3 ? 4 : kt;
+}
+
+// Operand tables: see the file comment.  V: host [C][k] (float).
+void mfma_tables_f32(const float* V, int C, int k, std::vector<float>& V1, std::vector<float>& V2) {
+    const int CM = mfma_cmax(C, QFCA_PREC_FP32), KT = mfma_kt(k, QFCA_PREC_FP32), NU = 4 * KT;
+    V1.assign((size_t)CM * KT * 16, 0.f);
+    V2.assign((size_t)CM * KT * 16, 0.f);
+    auto at = [&](int c, int j) { return (c < C && j < k) ? V[(size_t)c * k + j] : 0.f; };
+    for (int s = 0; s < CM / 4; ++s)
+        for (int kt = 0; kt < KT; ++kt)
+            for (int g = 0; g < 4; ++g)
+                for (int n = 0; n < 16; ++n) V1[((s * KT + kt) * 4 + g) * 16 + n] = at(4 * s + g, 16 * kt + n);
+    for (int t = 0; t < CM / 16; ++t)
+        for (int u = 0; u < NU; ++u)
+            for (int g = 0; g < 4; ++g)
+                for (int n = 0; n < 16; ++n)
+                    V2[((t * NU + u) * 4 + g) * 16 + n] =
+                        at(16 * t + 4 * (n % 4) + n / 4, 16 * (u / 4) + 4 * g + (u % 4));
+}
+
+void mfma_tables_bf16(const uint16_t* Vb, int C, int k, std::vector<uint16_t>& V1, std::vector<uint16_t>& V2) {
+    const int CM = mfma_cmax(C, QFCA_PREC_BF16), KT = mfma_kt(k, QFCA_PREC_BF16), NU = KT / 2;
+    V1.assign((size_t)CM * KT * 16, 0);
+    V2.assign((size_t)CM * KT * 16, 0);
+    auto at = [&](int c, int j) -> uint16_t { return (c < C && j < k) ? Vb[(size_t)c * k + j] : (uint16_t)0; };
+    for (int s = 0; s < CM / 32; ++s)
+        for (int kt = 0; kt < KT; ++kt)
+            for (int g = 0; g < 4; ++g)
+                for (int n = 0; n < 16; ++n)
+                    for (int t = 0; t < 8; ++t)
+                        V1[(((s * KT + kt) * 4 + g) * 16 + n) * 8 + t] = at(32 * s + 8 * g + t, 16 * kt + n);
+    for (int s = 0; s < CM / 32; ++s)
+        for (int h = 0; h < 2; ++h)
+            for (int u = 0; u < NU; ++u)
+                for (int g = 0; g < 4; ++g)
+                    for (int n = 0; n < 16; ++n)
+                        for (int t = 0; t < 8; ++t)
+                            V2[((((2 * s + h) * NU + u) * 4 + g) * 16 + n) * 8 + t] =
+                                at(32 * s + 8 * (n / 4) + 4 * h + (n % 4), 16 * (2 * u + t / 4) + 4 * g + (t % 4));
+}
+
+hipError_t launch_proj_mfma(const ProjLaunch& L, const void* V1, const void* V2, hipStream_t st) {
+    MArgs a;
+    a.X = L.X; a.C = L.C; a.N = L.N; a.k = L.k; a.B = L.B;
+    a.mu = L.mu; a.V1 = V1; a.V2 = V2;
+    a.edges = L.edges; a.lo = L.lo; a.inv_delta = L.inv_delta;
+    a.bins = L.bins; a.resid = L.resid;
+    a.ntiles = (L.N + 15) / 16;
+    const int CM = mfma_cmax(L.C, L.prec), KT = mfma_kt(L.k, L.prec);
+    if (!CM || !KT) return hipErrorInvalidValue;
+    const size_t base = (size_t)3 * CM * 4 + (size_t)4 * KT * 4 * 64 * 4;
+    const bool bf = L.prec == QFCA_PREC_BF16;
+    const size_t tab = (size_t)2 * CM * KT * 16 * (bf ? 2 : 4);
+    const bool vl = base + tab <= 65536;
+    const size_t lds = base + (vl ? tab : 0);
+#define QFCA_F32_CASE(CMV, KTV)                                                       \
+    if (!bf && CM == CMV && KT == KTV)                                                 \
+        return vl ? go(k_proj_f32_mfma<CMV, KTV, true>, a, lds, st)                    \
+                  : go(k_proj_f32_mfma<CMV, KTV, false>, a, lds, st);
+#define QFCA_BF_CASE(CMV, KTV)                                                        \
+    if (bf && CM == CMV && KT == KTV)                                                  \
+        return vl ? go(k_proj_bf16_mfma<CMV, KTV, true>, a, lds, st)                   \
+                  : go(k_proj_bf16_mfma<CMV, KTV, false>, a, lds, st);
+#define QFCA_F32_CM(CMV) QFCA_F32_CASE(CMV, 1) QFCA_F32_CASE(CMV, 2) QFCA_F32_CASE(CMV, 4)
+#define QFCA_BF_CM(CMV) QFCA_BF_CASE(CMV, 2) QFCA_BF_CASE(CMV, 4)
+    QFCA_F32_CM(64) QFCA_F32_CM(128) QFCA_F32_CM(256) QFCA_F32_CM(512)
+    QFCA_BF_CM(128) QFCA_BF_CM(256) QFCA_BF_CM(512)
+#undef QFCA_BF_CM
+#undef QFCA_F32_CM
+#undef QFCA_BF_CASE
+#undef QFCA_F32_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace qfca

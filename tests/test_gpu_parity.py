@@ -240,3 +240,54 @@ def test_full_path_256(ctx):
     m = q.qfca_model_create(ctx, prm, None, None, om.edges, om.delta, None)
     q.qfca_fit_reference(ctx, m, torch.from_numpy(obins).cuda())
     np.testing.assert_array_equal(m.read("cR"), om.cR)
+
+
+@pytest.fixture(scope="module")
+def oracle_256():
+    ts, p = qfca_synth.workload_256()
+    X = ts[0].X
+    say("[oracle 256] fit")
+    om, R, obins = oracle.fit(X, p["k"], p["B"], p["T"])
+    return X, p, om, R, obins
+
+
+def test_quantize_mfma_fp32_256(ctx, oracle_256):
+    """FP32 MFMA projection at C=256, k=32: bins equal the oracle's outside the
+    float32 edge band, and equal #{m : r >= e_m} of the GPU's own residual."""
+    X, p, om, R, obins = oracle_256
+    say("[quantize fp32 mfma] 256x256 C=256 k=32")
+    prm = q.Params.make(C=p["C"], k=p["k"], B=p["B"], T=p["T"])
+    m = q.qfca_model_create(ctx, prm, om.mu, om.V, om.edges, om.delta, om.cR)
+    bins, resid = q.qfca_quantize(ctx, m, torch.from_numpy(X).cuda(), resid=True)
+    g = bins.cpu().numpy()
+    r = resid.cpu().numpy()
+    scale = np.abs(X.astype(np.float64)).sum(0).max() * np.ones(p["C"]) * (1 + p["k"])
+    assert np.abs(r.astype(np.float64) - R).max() <= 1e-5 * scale.max()
+    band = edge_band(R, om.edges, p["C"] + p["k"], scale)
+    diff = g != obins
+    assert not (diff & ~band).any(), f"{(diff & ~band).sum()} bins differ outside the edge band"
+    for c in range(0, p["C"], 37):
+        np.testing.assert_array_equal(g[c], np.searchsorted(om.edges[c], r[c], side="right"))
+    say(f"  fp32 bins differing from the FP64 oracle: {int(diff.sum())} of {diff.size}")
+
+
+def test_quantize_bf16_flip_rate_256(ctx, oracle_256):
+    """BF16 MFMA projection (FP32 accumulation, FP32 subtraction and edges):
+    the fraction of bins that differ from the FP64 oracle, and the score error
+    that follows, are measured and bounded (no exactness claim)."""
+    X, p, om, R, obins = oracle_256
+    say("[quantize bf16 mfma] 256x256 C=256 k=32")
+    prm = q.Params.make(C=p["C"], k=p["k"], B=p["B"], T=p["T"], proj_prec=q.QFCA_PREC_BF16)
+    m = q.qfca_model_create(ctx, prm, om.mu, om.V, om.edges, om.delta, om.cR)
+    bins, resid = q.qfca_quantize(ctx, m, torch.from_numpy(X).cuda(), resid=True)
+    g = bins.cpu().numpy()
+    flips = (g != obins).mean()
+    assert np.abs(g.astype(int) - obins.astype(int)).max() <= 2
+    r = resid.cpu().numpy()
+    for c in range(0, p["C"], 41):  # bins are still exact for the BF16 residual itself
+        np.testing.assert_array_equal(g[c], np.searchsorted(om.edges[c], r[c], side="right"))
+    out = q.qfca_score_map(ctx, m, bins)
+    ref = oracle.score(obins, p["T"], p["B"], om.cR, om.delta, 1.0)
+    err = np.abs(out.score.cpu().numpy() - ref.score).max() / np.abs(ref.score).max()
+    say(f"  bf16 flip rate {flips:.4%}, max score error {err:.3e} of max score")
+    assert flips < 0.05 and err < 0.05
