@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-steps", type=int, default=50)
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-sized float32 buffer twice (device to device) so that "
+                         "hardware byte counters of the run can be scaled by a copy of known size")
     return ap.parse_args()
 
 
@@ -171,6 +174,13 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+    if args.calib_copy:
+        n = args.calib_copy * 1024 * 1024 // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

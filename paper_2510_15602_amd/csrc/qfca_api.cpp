@@ -305,9 +305,11 @@ ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
     if (it != ctx->tiles.end()) return it->second;
     ScoreTile t;
     t.S = 64 / Bp;
-    t.Ws = 64;
-    t.Hb = 64;
     t.variant = score_has_block_kernel(T) ? 1 : 0;
+    if (t.variant) t.S = std::min(t.S, score_block_max_S(T));
+    // block walk: strips of n T - 2r columns fill whole blocks of T patch columns
+    t.Ws = t.variant ? std::max(8, 4 * T - (T - 1)) : 64;
+    t.Hb = 128;
     while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.S > 1) t.S >>= 1;
     while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.Ws > 8) t.Ws >>= 1;
     (void)C;
@@ -683,7 +685,8 @@ qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int3
     if (ctx->tile_override.Ws > 0) {
         L.tile = ctx->tile_override;
         if (L.tile.S * m->Bp > 64) return fail(QFCA_E_UNSUPPORTED, "S * lanes per channel exceeds 64");
-        if (L.tile.variant == 1 && !score_has_block_kernel(m->p.T)) L.tile.variant = 0;
+        if (L.tile.variant == 1 && (!score_has_block_kernel(m->p.T) || L.tile.S > score_block_max_S(m->p.T)))
+            L.tile.variant = 0;
         if (score_lds_bytes(m->p.T, m->Bp, L.tile.S, L.tile.Ws, L.tile.variant) > 65536)
             return fail(QFCA_E_UNSUPPORTED, "tile does not fit in LDS");
     } else {

@@ -58,6 +58,7 @@ struct ScoreLaunch {
 
 size_t score_lds_bytes(int T, int Bp, int S, int Ws, int variant);
 bool score_has_block_kernel(int T);
+int score_block_max_S(int T);  // channels per wavefront the block walk supports
 hipError_t launch_score(const ScoreLaunch& L, hipStream_t st);
 hipError_t launch_chanmean(const float* achan, const float* w1chan, int C, int N, float* amap,
                            float* w1, hipStream_t st);
