@@ -165,6 +165,42 @@ qfca_status qfca_quantize(qfca_ctx ctx, qfca_model model, const float* X, int32_
 qfca_status qfca_score_map(qfca_ctx ctx, qfca_model model, const uint8_t* bins, int32_t H,
                            int32_t W, float* score, float* amap, float* w1, float* achan);
 
+/* One image of a batch. */
+typedef struct {
+    qfca_model model;  /* fitted model; all jobs of a batch share C, k, B, T, sigma_s,
+                          preproc and proj_prec (the values of mu, V, edges and cR may differ) */
+    const float* X;    /* device [C][H][W] float32 features */
+    int32_t H, W;      /* any size >= 1 */
+    float* score;      /* device [H][W] float32 out */
+    uint8_t* bins;     /* device [C][H][W] uint8 out, or NULL for library scratch */
+    float* amap;       /* device [H][W] float32 out (map before the blur), or NULL */
+} qfca_job;
+
+/* Quantise and score n (1..256) images of different sizes: one persistent
+ * kernel drains a device work queue holding the projection tiles of every
+ * image followed by their score tiles (a score tile waits for its image's
+ * projection tiles), then batched channel-mean and blur kernels run; the
+ * launch sequence is a HIP graph captured once per context and shape class
+ * and replayed.  Stream-ordered like qfca_score_map; the per-channel
+ * arithmetic is that of qfca_quantize + qfca_score_map, so results agree
+ * with them to float rounding, and each image's result does not depend on
+ * the other images of the batch.  Requires preproc = QFCA_PRE_RESIDUAL,
+ * T in {5, 7, 9, 11, 15, 31} and (C, k) within (64, 16), (256, 32) or
+ * (512, 64) (FP32; BF16 needs C > 128); QFCA_E_UNSUPPORTED otherwise. */
+qfca_status qfca_score_batch(qfca_ctx ctx, const qfca_job* jobs, int32_t n);
+
+/* Synchronises the context's stream and reports whether a batch on it gave
+ * up waiting for its projection tiles (*failed = 1; never expected). */
+qfca_status qfca_batch_error(qfca_ctx ctx, int32_t* failed);
+
+/* Tile autotuner: runs the batch `jobs` with candidate score tiles (strip
+ * widths n T - (T - 1), band heights 64..256) timed with HIP events, keeps the
+ * fastest as this context's tile for later score calls (single image and
+ * batch) with the same (T, B), and returns it.  Synchronous; overwrites the
+ * jobs' outputs. */
+qfca_status qfca_autotune(qfca_ctx ctx, const qfca_job* jobs, int32_t n, int32_t* best_Ws,
+                          int32_t* best_Hb, double* best_ms);
+
 /* Model queries.  qfca_model_read copies one field to host memory:
  *   field 0 mu [C] float32, 1 V [C][k] float32, 2 edges [C][B-1] float32,
  *   3 delta [C] float64, 4 cR [C][B] int32, 5 eigenvalues [C] float64

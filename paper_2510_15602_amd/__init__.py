@@ -30,7 +30,8 @@ EXPORTS = ("qfca_status_str", "qfca_last_error", "qfca_version", "qfca_ctx_creat
            "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca", "qfca_model_create",
            "qfca_fit_reference", "qfca_quantize", "qfca_score_map", "qfca_model_params",
            "qfca_model_read", "qfca_model_destroy", "qfca_host_sym_eig", "qfca_ctx_profile",
-           "qfca_ctx_profile_read", "qfca_ctx_set_tile")
+           "qfca_ctx_profile_read", "qfca_ctx_set_tile", "qfca_score_batch", "qfca_batch_error",
+           "qfca_autotune")
 
 KERNELS = {"score": 0, "proj": 1, "chanmean": 2, "blur": 3}
 
@@ -55,6 +56,12 @@ class Params(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_void_p), ("X", ctypes.c_void_p), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32), ("score", ctypes.c_void_p), ("bins", ctypes.c_void_p),
+                ("amap", ctypes.c_void_p)]
 
 
 _lib = None
@@ -87,12 +94,17 @@ def lib():
         L.qfca_host_sym_eig.restype = i32
         L.qfca_ctx_profile.argtypes = [P, i32]
         L.qfca_ctx_set_tile.argtypes = [P, i32, i32, i32, i32]
+        L.qfca_score_batch.argtypes = [P, ctypes.POINTER(Job), i32]
+        L.qfca_batch_error.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+        L.qfca_autotune.argtypes = [P, ctypes.POINTER(Job), i32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
         L.qfca_ctx_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64)]
         for name in ("qfca_ctx_create", "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca",
                      "qfca_model_create", "qfca_fit_reference", "qfca_quantize", "qfca_score_map",
                      "qfca_model_params", "qfca_model_read", "qfca_model_destroy",
-                     "qfca_ctx_profile", "qfca_ctx_profile_read", "qfca_ctx_set_tile"):
+                     "qfca_ctx_profile", "qfca_ctx_profile_read", "qfca_ctx_set_tile",
+                     "qfca_score_batch", "qfca_batch_error", "qfca_autotune"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -291,6 +303,50 @@ def qfca_score_map(ctx: Context, model: Model, bins, amap=False, w1=False, achan
     return out
 
 
+def _jobs(items):
+    """items: sequence of (model, X, score[, bins[, amap]])."""
+    arr = (Job * len(items))()
+    for i, it in enumerate(items):
+        model, X, score = it[0], it[1], it[2]
+        bins = it[3] if len(it) > 3 else None
+        amap = it[4] if len(it) > 4 else None
+        import torch
+        _dev_tensor(X, torch.float32, "X", 3)
+        _dev_tensor(score, torch.float32, "score", 2)
+        C, H, W = X.shape
+        if C != model.params.C or tuple(score.shape) != (H, W):
+            raise ValueError("job shapes do not match")
+        if bins is not None:
+            _dev_tensor(bins, torch.uint8, "bins", 3)
+        if amap is not None:
+            _dev_tensor(amap, torch.float32, "amap", 2)
+        arr[i] = Job(model.handle.value if hasattr(model.handle, "value") else model.handle,
+                     X.data_ptr(), H, W, score.data_ptr(), bins.data_ptr() if bins is not None else None,
+                     amap.data_ptr() if amap is not None else None)
+    return arr
+
+
+def qfca_score_batch(ctx: Context, items):
+    """Quantise and score a batch.  items: sequence of (model, X [C,H,W],
+    score [H,W] out[, bins [C,H,W] out[, amap [H,W] out]])."""
+    arr = _jobs(items)
+    _check(lib().qfca_score_batch(ctx.handle, arr, len(items)))
+
+
+def qfca_batch_error(ctx: Context) -> int:
+    v = ctypes.c_int32()
+    _check(lib().qfca_batch_error(ctx.handle, ctypes.byref(v)))
+    return v.value
+
+
+def qfca_autotune(ctx: Context, items):
+    """Returns (Ws, Hb, ms) of the fastest score tile for this batch and keeps it."""
+    arr = _jobs(items)
+    ws, hb, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(lib().qfca_autotune(ctx.handle, arr, len(items), ctypes.byref(ws), ctypes.byref(hb), ctypes.byref(ms)))
+    return ws.value, hb.value, ms.value
+
+
 def host_sym_eig(A: np.ndarray):
     """The library's host eigensolver (no GPU needed): (evals desc, vecs)."""
     A = np.array(A, dtype=np.float64, order="C", copy=True)
@@ -310,3 +366,4 @@ model_create = qfca_model_create
 fit_reference = qfca_fit_reference
 quantize = qfca_quantize
 score_map = qfca_score_map
+score_batch = qfca_score_batch

@@ -22,7 +22,12 @@ using namespace qfca;
 
 enum Slot {
     SL_ACHAN = 0, SL_W1CHAN, SL_AMAP, SL_W1TMP, SL_RESID, SL_BINS, SL_COUNTS, SL_SEL,
-    SL_COV, SL_MU, SL_RANKS, SL_CR, SL_COUNT
+    SL_COV, SL_MU, SL_RANKS, SL_CR, SL_BBINS, SL_BACHAN, SL_BAMAP, SL_COUNT
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 enum { K_SCORE = 0, K_PROJ, K_CHANMEAN, K_BLUR, K_COUNT };
@@ -36,6 +41,15 @@ struct qfca_ctx_s {
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[K_COUNT];
     std::vector<hipEvent_t> event_pool;
+    // batched path
+    BatchHeader* d_hdr = nullptr;
+    BatchJob* d_jobs = nullptr;
+    BatchHeader* h_hdr = nullptr;  // pinned staging
+    BatchJob* h_jobs = nullptr;
+    hipEvent_t staged = nullptr;   // the last upload from the staging buffers
+    hipStream_t capture = nullptr; // private stream used only to capture graphs
+    std::map<long long, GraphEntry> graphs;
+    std::map<long long, ScoreTile> tuned;  // autotuned tiles keyed by (T, B)
 };
 
 struct qfca_model_s {
@@ -145,6 +159,8 @@ uint16_t f32_to_bf16(float f) {
     u += 0x7FFFu + lsb;  // round to nearest even
     return (uint16_t)(u >> 16);
 }
+
+size_t align16c(size_t x) { return (x + 15) & ~size_t(15); }
 
 int pow2_at_least(int v, int lo) {
     int p = lo;
@@ -300,6 +316,8 @@ struct KernelTimer {
 };
 
 ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
+    auto tn = ctx->tuned.find((long long)T * 128 + B);
+    if (tn != ctx->tuned.end()) return tn->second;
     const long long key = (((long long)T * 128 + B) * 4096 + std::min(W, 4095)) * 4096 + std::min(H, 4095);
     auto it = ctx->tiles.find(key);
     if (it != ctx->tiles.end()) return it->second;
@@ -409,6 +427,16 @@ qfca_status qfca_ctx_destroy(qfca_ctx ctx) {
     if (!ctx) return QFCA_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (auto& g : ctx->graphs) {
+        if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+        if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
+    }
+    if (ctx->d_hdr) (void)hipFree(ctx->d_hdr);
+    if (ctx->d_jobs) (void)hipFree(ctx->d_jobs);
+    if (ctx->h_hdr) (void)hipHostFree(ctx->h_hdr);
+    if (ctx->h_jobs) (void)hipHostFree(ctx->h_jobs);
+    if (ctx->staged) (void)hipEventDestroy(ctx->staged);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     for (auto& v : ctx->timed)
         for (auto& pr : v) ctx->event_pool.push_back(pr.first), ctx->event_pool.push_back(pr.second);
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
@@ -704,6 +732,225 @@ qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int3
         KernelTimer kt(ctx, K_BLUR);
         HIP_TRY(launch_blur(am, H, W, m->p.sigma_s, score, s));
     }
+    return QFCA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int batch_lanes(int B) { return pow2_at_least(B, 8); }
+
+ScoreTile batch_tile(qfca_ctx ctx, const qfca_params& p) {
+    const int Bp = batch_lanes(p.B);
+    ScoreTile t = choose_tile(ctx, p.C, 256, 256, p.T, p.B, Bp);
+    if (ctx->tile_override.Ws > 0) t = ctx->tile_override;
+    t.variant = 1;
+    t.S = std::min(std::min(t.S, 64 / Bp), score_block_max_S(p.T));
+    if (t.S < 1) t.S = 1;
+    return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+qfca_status qfca_score_batch(qfca_ctx ctx, const qfca_job* jobs, int32_t n) {
+    if (!ctx || !jobs) return fail(QFCA_E_ARG, "NULL argument");
+    if (n < 1 || n > BATCH_MAXJ) return fail(QFCA_E_ARG, "n must be in [1, 256]");
+    const qfca_model m0 = jobs[0].model;
+    if (!m0) return fail(QFCA_E_ARG, "job 0 has no model");
+    const qfca_params p = m0->p;
+    for (int i = 0; i < n; ++i) {
+        const qfca_job& J = jobs[i];
+        if (!J.model || !J.X || !J.score) return fail(QFCA_E_ARG, "job with a NULL model, X or score");
+        const qfca_params& q = J.model->p;
+        if (q.C != p.C || q.k != p.k || q.B != p.B || q.T != p.T || q.preproc != p.preproc ||
+            q.proj_prec != p.proj_prec || q.sigma_s != p.sigma_s)
+            return fail(QFCA_E_ARG, "all jobs of a batch must share C, k, B, T, sigma_s, preproc, proj_prec");
+        if (!J.model->has_ref) return fail(QFCA_E_STATE, "model without reference");
+        if (J.model->device != ctx->device) return fail(QFCA_E_ARG, "model on another device");
+        qfca_status st = check_shape(J.H, J.W, p.C);
+        if (st != QFCA_OK) return st;
+    }
+    const int CM = mfma_cmax(p.C, p.proj_prec), KT = mfma_kt(p.k, p.proj_prec);
+    if (p.preproc != QFCA_PRE_RESIDUAL || !CM || !KT || !batch_supported(p.T, CM, KT, p.proj_prec) ||
+        !m0->d_V1)
+        return fail(QFCA_E_UNSUPPORTED, "batched path: unsupported (T, C, k, precision) combination");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const ScoreTile tile = batch_tile(ctx, p);
+    const int Bp = batch_lanes(p.B);
+    const size_t wave_lds = align16c(batch_wave_lds(p.T, tile.S, tile.Ws));
+    const size_t lds = std::max((size_t)4 * wave_lds, batch_proj_lds(CM, KT));
+    if (lds > 160 * 1024) return fail(QFCA_E_UNSUPPORTED, "batch tile does not fit in LDS");
+
+    // device + pinned staging buffers
+    if (!ctx->d_hdr) {
+        HIP_TRY(hipMalloc((void**)&ctx->d_hdr, sizeof(BatchHeader)));
+        HIP_TRY(hipMalloc((void**)&ctx->d_jobs, sizeof(BatchJob) * BATCH_MAXJ));
+        HIP_TRY(hipHostMalloc((void**)&ctx->h_hdr, sizeof(BatchHeader), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&ctx->h_jobs, sizeof(BatchJob) * BATCH_MAXJ, hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming));
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    } else {
+        HIP_TRY(hipEventSynchronize(ctx->staged));  // previous upload has left the staging buffers
+    }
+    // scratch for bins, per-channel maps and channel means
+    size_t nb = 0, na = 0, nm = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t N = (size_t)jobs[i].H * jobs[i].W;
+        if (!jobs[i].bins) nb += (size_t)p.C * N;
+        na += (size_t)p.C * N;
+        if (!jobs[i].amap) nm += N;
+    }
+    uint8_t* sb = nullptr;
+    float* sa = nullptr;
+    float* sm = nullptr;
+    HIP_TRY(scratch(ctx, SL_BBINS, std::max<size_t>(nb, 1), &sb));
+    HIP_TRY(scratch(ctx, SL_BACHAN, std::max<size_t>(na, 1) * 4, &sa));
+    HIP_TRY(scratch(ctx, SL_BAMAP, std::max<size_t>(nm, 1) * 4, &sm));
+    BatchHeader& h = *ctx->h_hdr;
+    memset(&h, 0, sizeof(h));
+    h.n = n;
+    const int S = tile.S;
+    const int cgroups = (p.C + S - 1) / S;
+    int np = 0, ns = 0;
+    size_t ob = 0, oa = 0, om = 0;
+    for (int i = 0; i < n; ++i) {
+        const qfca_job& J = jobs[i];
+        const qfca_model m = J.model;
+        BatchJob& b = ctx->h_jobs[i];
+        memset(&b, 0, sizeof(b));
+        const int N = J.H * J.W;
+        uint8_t* bins = J.bins ? J.bins : sb + ob;
+        if (!J.bins) ob += (size_t)p.C * N;
+        float* achan = sa + oa;
+        oa += (size_t)p.C * N;
+        float* amap = J.amap ? J.amap : sm + om;
+        if (!J.amap) om += N;
+        b.pa.X = J.X; b.pa.C = p.C; b.pa.N = N; b.pa.k = p.k; b.pa.B = p.B;
+        b.pa.mu = m->d_mu; b.pa.V1 = m->d_V1; b.pa.V2 = m->d_V2; b.pa.edges = m->d_edges;
+        b.pa.lo = m->d_lo; b.pa.inv_delta = m->d_invd; b.pa.bins = bins; b.pa.resid = nullptr;
+        b.pa.ntiles = (N + 15) / 16;
+        b.sa.bins = bins; b.sa.C = p.C; b.sa.H = J.H; b.sa.W = J.W; b.sa.T = p.T; b.sa.B = p.B;
+        b.sa.Bp = Bp; b.sa.S = S; b.sa.r = p.T / 2; b.sa.m = p.T * p.T; b.sa.Ws = tile.Ws;
+        b.sa.Hb = tile.Hb; b.sa.WbA = tile.Ws + 4 * (p.T / 2);
+        b.sa.psig = m->tab.psig; b.sa.cRm1 = m->tab.cRm1; b.sa.Dm1 = m->tab.Dm1; b.sa.cRl = m->tab.cRl;
+        b.sa.rcp = m->tab.rcp; b.sa.delta = m->d_delta; b.sa.achan = achan; b.sa.w1chan = nullptr;
+        b.ntiles_proj = b.pa.ntiles;
+        b.nstrips = (J.W + tile.Ws - 1) / tile.Ws;
+        b.nbands = (J.H + tile.Hb - 1) / tile.Hb;
+        b.amap = amap;
+        b.score = J.score;
+        h.proj_prefix[i] = np;
+        h.score_prefix[i] = ns;
+        np += b.ntiles_proj;
+        ns += b.nstrips * b.nbands * ((cgroups + 3) / 4);
+    }
+    h.proj_prefix[n] = np;
+    h.score_prefix[n] = ns;
+    h.nproj = np;
+    h.nitems = np + ns;
+    const float sig = p.sigma_s;
+    h.blur_R = sig > 0.f ? (int)ceil(3.0 * (double)sig) : 0;
+    for (int d = 0; d <= 16; ++d)
+        h.blur_w[d] = (d <= h.blur_R) ? (sig > 0.f ? exp(-(double)(d * d) / (2.0 * (double)sig * sig)) : 1.0) : 0.0;
+    HIP_TRY(hipMemcpyAsync(ctx->d_jobs, ctx->h_jobs, sizeof(BatchJob) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->d_hdr, ctx->h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->staged, ctx->stream));
+
+    // grid: as many resident blocks as fit
+    int per_cu = 1, ncu = 1;
+    {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, ctx->device));
+        ncu = prop.multiProcessorCount;
+        per_cu = std::max(1, (int)(prop.maxSharedMemoryPerMultiProcessor / std::max<size_t>(lds, 1)));
+        per_cu = std::min(per_cu, 2);
+    }
+    const int grid = ncu * per_cu;
+    int maxn = 1;
+    while (maxn < n) maxn <<= 1;
+    const long long key = ((((long long)p.T * 1024 + CM) * 8 + KT) * 2 + p.proj_prec) * 1000003LL +
+                          ((long long)lds * 64 + maxn) * 4096 + grid;
+    GraphEntry& ge = ctx->graphs[key];
+    if (!ge.exec) {
+        HIP_TRY(prepare_batch(p.T, CM, KT, p.proj_prec, lds));
+        HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+        hipError_t le = launch_batch(p.T, CM, KT, p.proj_prec, ctx->d_hdr, ctx->d_jobs, (int)wave_lds, lds,
+                                     grid, maxn, ctx->capture);
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(ctx->capture, &g);
+        if (le != hipSuccess) return hip_fail(le, "launch_batch (capture)");
+        if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+        ge.graph = g;
+        HIP_TRY(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0));
+    }
+    KernelTimer kt(ctx, K_SCORE);
+    HIP_TRY(hipGraphLaunch(ge.exec, ctx->stream));
+    return QFCA_OK;
+}
+
+qfca_status qfca_batch_error(qfca_ctx ctx, int32_t* failed) {
+    if (!ctx || !failed) return fail(QFCA_E_ARG, "NULL argument");
+    *failed = 0;
+    if (!ctx->d_hdr) return QFCA_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    int v = 0;
+    HIP_TRY(hipMemcpyAsync(&v, &ctx->d_hdr->error, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    *failed = v;
+    return QFCA_OK;
+}
+
+qfca_status qfca_autotune(qfca_ctx ctx, const qfca_job* jobs, int32_t n, int32_t* best_Ws,
+                          int32_t* best_Hb, double* best_ms) {
+    if (!ctx || !jobs || n < 1 || !best_Ws || !best_Hb) return fail(QFCA_E_ARG, "NULL argument");
+    const qfca_params p = jobs[0].model->p;
+    const int T = p.T, Bp = batch_lanes(p.B);
+    const ScoreTile saved = ctx->tile_override;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best = 1e30;
+    ScoreTile bt;
+    bool found = false;
+    for (int kmul = 2; kmul <= 8; ++kmul) {
+        const int Ws = kmul * T - (T - 1);
+        if (Ws < 8 || Ws > 256) continue;
+        for (int Hb : {64, 128, 256}) {
+            ScoreTile t;
+            t.Ws = Ws;
+            t.Hb = Hb;
+            t.variant = 1;
+            t.S = std::min(64 / Bp, score_block_max_S(T));
+            if (4 * align16c(batch_wave_lds(T, t.S, t.Ws)) > 160 * 1024) continue;
+            ctx->tile_override = t;
+            qfca_status st = qfca_score_batch(ctx, jobs, n);  // warm-up (and graph capture)
+            if (st != QFCA_OK) continue;
+            HIP_TRY(hipEventRecord(e0, ctx->stream));
+            for (int rep = 0; rep < 2; ++rep)
+                if ((st = qfca_score_batch(ctx, jobs, n)) != QFCA_OK) break;
+            HIP_TRY(hipEventRecord(e1, ctx->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (st == QFCA_OK && ms / 2 < best) {
+                best = ms / 2;
+                bt = t;
+                found = true;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->tile_override = saved;
+    if (!found) return fail(QFCA_E_UNSUPPORTED, "no candidate tile ran");
+    ctx->tuned[(long long)T * 128 + p.B] = bt;
+    ctx->tiles.clear();
+    *best_Ws = bt.Ws;
+    *best_Hb = bt.Hb;
+    if (best_ms) *best_ms = best;
     return QFCA_OK;
 }
 

@@ -1,0 +1,238 @@
+// Batched QFCA for images of different sizes (gfx950): one persistent kernel
+// drains a device work queue of projection tiles (16 pixels of one image:
+// residual + bins) and score tiles (a strip x band of one image for 4 channel
+// groups: window histograms, Alg. 1, association), followed by batched
+// channel-mean and blur kernels.  The launch sequence is captured once in a
+// hipGraph whose kernels read every per-batch quantity from device-resident
+// descriptors, so one graph replays any batch within its capacity.
+//
+// Ordering: every projection item precedes every score item in the queue.
+// A block that takes a score item of image i waits (bounded spin) until all
+// projection items of image i are done; those items were taken earlier by
+// blocks that are already running, so the wait always ends.  Projection
+// blocks publish with a device-scope release (fence + atomic add), score
+// blocks acquire with an atomic load and a fence before reading the bins.
+#include <algorithm>
+
+#include "qfca_internal.h"
+#include "qfca_tiles.h"
+
+namespace qfca {
+
+namespace {
+using namespace tiles;
+
+constexpr int SPIN_LIMIT = 1 << 22;
+
+__global__ void k_batch_reset(BatchHeader* h, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        h->head = 0;
+        h->error = 0;
+    }
+    if (i < n) h->done[i] = 0;
+}
+
+__device__ int find_job(const int* prefix, int n, int item) {
+    // largest j with prefix[j] <= item (prefix[0] = 0, nondecreasing)
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int T, int CMAX, int KT, bool BF>
+__global__ __launch_bounds__(256) void k_batch(BatchHeader* hdr, const BatchJob* jobs, int wave_lds) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item, s_job, s_ok;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = hdr->n, nproj = hdr->nproj, nitems = hdr->nitems;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int it = atomicAdd(&hdr->head, 1);
+            s_item = it;
+            s_job = it < nproj ? find_job(hdr->proj_prefix, n, it)
+                               : (it < nitems ? find_job(hdr->score_prefix, n, it - nproj) : 0);
+        }
+        __syncthreads();
+        const int item = s_item, jb = s_job;
+        if (item >= nitems) break;
+        const BatchJob& J = jobs[jb];
+        if (item < nproj) {
+            const int tile = item - hdr->proj_prefix[jb];
+            float* smu = (float*)smem;
+            float* slo = smu + CMAX;
+            float* sid = slo + CMAX;
+            float* zp = sid + CMAX;
+            for (int i = threadIdx.x; i < CMAX; i += 256) {
+                const bool ok = i < J.pa.C;
+                smu[i] = ok ? J.pa.mu[i] : 0.f;
+                slo[i] = ok ? J.pa.lo[i] : 0.f;
+                sid[i] = ok ? J.pa.inv_delta[i] : 0.f;
+            }
+            __syncthreads();
+            if constexpr (BF)
+                proj_tile_bf16<CMAX, KT>(J.pa, tile, w, lane, (const bf16x8*)J.pa.V1, (const bf16x8*)J.pa.V2,
+                                         smu, slo, sid, zp);
+            else
+                proj_tile_f32<CMAX, KT>(J.pa, tile, w, lane, (const float*)J.pa.V1, (const float*)J.pa.V2,
+                                        smu, slo, sid, zp);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __threadfence();
+                atomicAdd(&hdr->done[jb], 1);
+            }
+        } else {
+            const int local = item - nproj - hdr->score_prefix[jb];
+            if (threadIdx.x == 0) {
+                const int need = J.ntiles_proj;
+                int ok = 0;
+                for (int sp = 0; sp < SPIN_LIMIT; ++sp) {
+                    if (__hip_atomic_load(&hdr->done[jb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= need) {
+                        ok = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+                if (!ok) atomicOr(&hdr->error, 1);
+                s_ok = ok;
+            }
+            __syncthreads();
+            __threadfence();
+            if (s_ok) {
+                // local = ((gz * nbands) + by) * nstrips + bx
+                const int bx = local % J.nstrips;
+                const int rest = local / J.nstrips;
+                const int by = rest % J.nbands;
+                const int gz = rest / J.nbands;
+                score_tile<T>(J.sa, bx, by, 4 * gz + w, lane, smem + (size_t)w * wave_lds);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// A(x) = (1/C) sum_c achan[c][x] for every image (grid: x chunks, images).
+__global__ void k_batch_chanmean(const BatchHeader* hdr, const BatchJob* jobs) {
+    const int jb = blockIdx.y;
+    if (jb >= hdr->n) return;
+    const BatchJob& J = jobs[jb];
+    const int N = J.sa.H * J.sa.W;
+    const int C = J.sa.C;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < C; ++c) s += (double)J.sa.achan[(size_t)c * N + i];
+        J.amap[i] = (float)(s / (double)C);
+    }
+}
+
+// Separable Gaussian (radius R <= 16) for every image (grid: tiles, images).
+__global__ __launch_bounds__(256) void k_batch_blur(const BatchHeader* hdr, const BatchJob* jobs) {
+    constexpr int BT = 16, RM = 16;
+    __shared__ double tile[BT + 2 * RM][BT + 2 * RM];
+    __shared__ double hp[BT + 2 * RM][BT];
+    const int jb = blockIdx.z;
+    if (jb >= hdr->n) return;
+    const BatchJob& J = jobs[jb];
+    const int H = J.sa.H, W = J.sa.W, R = hdr->blur_R;
+    const int ntx = (W + BT - 1) / BT, nty = (H + BT - 1) / BT;
+    const int tx = threadIdx.x % BT, ty = threadIdx.x / BT, TS = BT + 2 * R;
+    for (int tb = blockIdx.x; tb < ntx * nty; tb += gridDim.x) {
+        const int bx = (tb % ntx) * BT, by = (tb / ntx) * BT;
+        __syncthreads();
+        for (int t = threadIdx.x; t < TS * TS; t += 256) {
+            const int ly = t / TS, lx = t - ly * TS;
+            const int gy = by + ly - R, gx = bx + lx - R;
+            tile[ly][lx] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? (double)J.amap[(size_t)gy * W + gx] : 0.0;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < TS * BT; t += 256) {
+            const int ly = t / BT, lx = t - ly * BT;
+            const int gx = bx + lx;
+            double s = 0.0, ws = 0.0;
+            for (int d = -R; d <= R; ++d) {
+                const int xx = gx + d;
+                if (xx < 0 || xx >= W) continue;
+                const double wd = hdr->blur_w[d < 0 ? -d : d];
+                s += wd * tile[ly][lx + R + d];
+                ws += wd;
+            }
+            hp[ly][lx] = ws > 0.0 ? s / ws : 0.0;
+        }
+        __syncthreads();
+        const int gy = by + ty, gx = bx + tx;
+        if (gy < H && gx < W) {
+            double s = 0.0, ws = 0.0;
+            for (int d = -R; d <= R; ++d) {
+                const int yy = gy + d;
+                if (yy < 0 || yy >= H) continue;
+                const double wd = hdr->blur_w[d < 0 ? -d : d];
+                s += wd * hp[ty + R + d][tx];
+                ws += wd;
+            }
+            J.score[(size_t)gy * W + gx] = (float)(s / ws);
+        }
+    }
+}
+
+template <int T, int CMAX, int KT, bool BF>
+hipError_t run_batch(BatchHeader* hdr, const BatchJob* jobs, int wave_lds, size_t lds, int grid,
+                     int maxn, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_reset, dim3((maxn + 255) / 256), dim3(256), 0, st, hdr, maxn);
+    hipLaunchKernelGGL((k_batch<T, CMAX, KT, BF>), dim3(grid), dim3(256), lds, st, hdr, jobs, wave_lds);
+    hipLaunchKernelGGL(k_batch_chanmean, dim3(512, maxn), dim3(256), 0, st, (const BatchHeader*)hdr, jobs);
+    hipLaunchKernelGGL(k_batch_blur, dim3(256, 1, maxn), dim3(256), 0, st, (const BatchHeader*)hdr, jobs);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t batch_wave_lds(int T, int S, int Ws) {
+    switch (T) {
+#define QFCA_BL(TT) case TT: return BLayout<TT>(S, Ws).total;
+        QFCA_BL(5) QFCA_BL(7) QFCA_BL(9) QFCA_BL(11) QFCA_BL(15) QFCA_BL(31)
+#undef QFCA_BL
+        default: return 0;
+    }
+}
+
+bool batch_supported(int T, int CMAX, int KT, int prec) {
+    const bool t_ok = T == 5 || T == 7 || T == 9 || T == 11 || T == 15 || T == 31;
+    if (!t_ok) return false;
+    if (prec == QFCA_PREC_BF16) return (CMAX == 256 && KT == 2) || (CMAX == 512 && KT == 4);
+    return (CMAX == 64 && KT == 1) || (CMAX == 256 && KT == 2) || (CMAX == 512 && KT == 4);
+}
+
+size_t batch_proj_lds(int CMAX, int KT) { return (size_t)3 * CMAX * 4 + (size_t)4 * KT * 4 * 64 * 4; }
+
+hipError_t prepare_batch(int T, int CMAX, int KT, int prec, size_t lds) {
+    const bool bf = prec == QFCA_PREC_BF16;
+#define QFCA_PREP_CASE(TT, CM, KK, BFV)                                                    \
+    if (T == TT && CMAX == CM && KT == KK && bf == BFV)                                    \
+        return hipFuncSetAttribute((const void*)k_batch<TT, CM, KK, BFV>,                  \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+#define QFCA_PREP_T(TT) QFCA_PREP_CASE(TT, 64, 1, false) QFCA_PREP_CASE(TT, 256, 2, false) \
+    QFCA_PREP_CASE(TT, 512, 4, false) QFCA_PREP_CASE(TT, 256, 2, true) QFCA_PREP_CASE(TT, 512, 4, true)
+    QFCA_PREP_T(5) QFCA_PREP_T(7) QFCA_PREP_T(9) QFCA_PREP_T(11) QFCA_PREP_T(15) QFCA_PREP_T(31)
+#undef QFCA_PREP_T
+#undef QFCA_PREP_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch(int T, int CMAX, int KT, int prec, BatchHeader* hdr, const BatchJob* jobs,
+                        int wave_lds, size_t lds, int grid, int maxn, hipStream_t st) {
+    const bool bf = prec == QFCA_PREC_BF16;
+#define QFCA_BATCH_CASE(TT, CM, KK, BFV)                                                   \
+    if (T == TT && CMAX == CM && KT == KK && bf == BFV)                                    \
+        return run_batch<TT, CM, KK, BFV>(hdr, jobs, wave_lds, lds, grid, maxn, st);
+#define QFCA_BATCH_T(TT) QFCA_BATCH_CASE(TT, 64, 1, false) QFCA_BATCH_CASE(TT, 256, 2, false) \
+    QFCA_BATCH_CASE(TT, 512, 4, false) QFCA_BATCH_CASE(TT, 256, 2, true) QFCA_BATCH_CASE(TT, 512, 4, true)
+    QFCA_BATCH_T(5) QFCA_BATCH_T(7) QFCA_BATCH_T(9) QFCA_BATCH_T(11) QFCA_BATCH_T(15) QFCA_BATCH_T(31)
+#undef QFCA_BATCH_T
+#undef QFCA_BATCH_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace qfca

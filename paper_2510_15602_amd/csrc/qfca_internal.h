@@ -11,6 +11,62 @@
 
 namespace qfca {
 
+// Arguments of one score tile (see qfca_tiles.h).
+struct KArgs {
+    const uint8_t* bins;
+    int C, H, W, T, B, Bp, S, r, m, Ws, Hb, WbA;
+    const int2* psig;
+    const int32_t* cRm1;
+    const int32_t* Dm1;
+    const int32_t* cRl;
+    const float* rcp;
+    const double* delta;
+    float* achan;
+    float* w1chan;
+};
+
+// Arguments of the MFMA projection (see qfca_tiles.h).
+struct MArgs {
+    const float* X;
+    int C, N, k, B;
+    const float* mu;
+    const void* V1;  // GEMM1 A operands
+    const void* V2;  // GEMM2 A operands
+    const float* edges;
+    const float* lo;
+    const float* inv_delta;
+    uint8_t* bins;
+    float* resid;
+    int ntiles;
+};
+
+// Batched path: one descriptor per image and one header per batch, both in
+// device memory.
+constexpr int BATCH_MAXJ = 256;
+struct BatchJob {
+    MArgs pa;             // projection of this image
+    KArgs sa;             // score tiles of this image
+    int ntiles_proj;      // projection items of this image
+    int nstrips, nbands;  // score item grid (x strips, y bands; z = channel groups / 4)
+    float* amap;          // [H][W] channel mean
+    float* score;         // [H][W] blurred score
+};
+struct BatchHeader {
+    int head;             // next queue item
+    int error;            // set if a wait gave up (never expected)
+    int n, nproj, nitems, blur_R;
+    double blur_w[17];
+    int done[BATCH_MAXJ];
+    int proj_prefix[BATCH_MAXJ + 1];
+    int score_prefix[BATCH_MAXJ + 1];
+};
+size_t batch_wave_lds(int T, int S, int Ws);
+size_t batch_proj_lds(int CMAX, int KT);
+bool batch_supported(int T, int CMAX, int KT, int prec);
+hipError_t prepare_batch(int T, int CMAX, int KT, int prec, size_t lds);
+hipError_t launch_batch(int T, int CMAX, int KT, int prec, BatchHeader* hdr, const BatchJob* jobs,
+                        int wave_lds, size_t lds, int grid, int maxn, hipStream_t st);
+
 // Per-thread last error message, set by the API layer.
 void set_error(const std::string& msg);
 

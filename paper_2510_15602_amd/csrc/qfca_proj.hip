@@ -25,43 +25,11 @@
 #include <algorithm>
 
 #include "qfca_internal.h"
+#include "qfca_tiles.h"
 
 namespace qfca {
 namespace {
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-struct MArgs {
-    const float* X;
-    int C, N, k, B;
-    const float* mu;
-    const void* V1;  // GEMM1 A operands
-    const void* V2;  // GEMM2 A operands
-    const float* edges;
-    const float* lo;
-    const float* inv_delta;
-    uint8_t* bins;
-    float* resid;
-    int ntiles;
-};
-
-__device__ __forceinline__ int bin_of_m(float rr, const float* __restrict__ e, float lo, float idl, int B) {
-    if (idl == 0.f) return 0;
-    int b = (int)floorf((rr - lo) * idl);
-    b = b < 0 ? 0 : (b > B - 1 ? B - 1 : b);
-    while (b > 0 && rr < e[b - 1]) --b;
-    while (b < B - 1 && rr >= e[b]) ++b;
-    return b;
-}
-
-__device__ __forceinline__ void emit(const MArgs& a, int c, int px, float r, const float* slo,
-                                     const float* sid) {
-    if (a.resid) a.resid[(size_t)c * a.N + px] = r;
-    if (a.bins)
-        a.bins[(size_t)c * a.N + px] =
-            (uint8_t)bin_of_m(r, a.edges + (size_t)c * (a.B - 1), slo[c], sid[c], a.B);
-}
+using namespace tiles;
 
 // ------------------------------------------------------------------------
 // The four wavefronts of a block share one 16-pixel tile: wave w owns the
@@ -98,62 +66,10 @@ __global__ __launch_bounds__(256) void k_proj_f32_mfma(MArgs a) {
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int g = lane >> 4, n = lane & 15;
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int px = tile * 16 + n;
-        const bool pxok = px < a.N;
-        float d[NSW];
-        floatx4 z[KT];
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) z[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int i = 0; i < NSW; ++i) {
-            const int s = w * NSW + i;
-            const int c = 4 * s + g;
-            const float x = (pxok && c < a.C) ? a.X[(size_t)c * a.N + px] : 0.f;
-            d[i] = (c < a.C) ? x - smu[c] : 0.f;
-#pragma unroll
-            for (int kt = 0; kt < KT; ++kt)
-                z[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(V1[((s * KT + kt) * 4 + g) * 16 + n], d[i],
-                                                             z[kt], 0, 0, 0);
-            if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-        }
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) zp[((w * KT + kt) * 4 + v) * 64 + lane] = z[kt][v];
-        __syncthreads();
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float acc = zp[((0 * KT + kt) * 4 + v) * 64 + lane];
-                acc += zp[((1 * KT + kt) * 4 + v) * 64 + lane];
-                acc += zp[((2 * KT + kt) * 4 + v) * 64 + lane];
-                acc += zp[((3 * KT + kt) * 4 + v) * 64 + lane];
-                z[kt][v] = acc;
-            }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NTW; ++i) {
-            const int t = w * NTW + i;
-            floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int u = 0; u < NU; ++u)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(V2[((t * NU + u) * 4 + g) * 16 + n],
-                                                           z[u >> 2][u & 3], acc, 0, 0, 0);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int c = 16 * t + 4 * v + g;
-                const float r = d[4 * i + v] - acc[v];
-                if (pxok && c < a.C) emit(a, c, px, r, slo, sid);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
+        proj_tile_f32<CMAX, KT>(a, tile, w, lane, V1, V2, smu, slo, sid, zp);
 }
 
-// ------------------------------------------------------------------------
 template <int CMAX, int KT, bool VLDS>
 __global__ __launch_bounds__(256) void k_proj_bf16_mfma(MArgs a) {
     constexpr int NSW = CMAX / 128;  // GEMM1 K steps per wave (32 channels each)
@@ -184,70 +100,10 @@ __global__ __launch_bounds__(256) void k_proj_bf16_mfma(MArgs a) {
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int g = lane >> 4, n = lane & 15;
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int px = tile * 16 + n;
-        const bool pxok = px < a.N;
-        float d[NSW][8];
-        floatx4 z[KT];
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) z[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int i = 0; i < NSW; ++i) {
-            const int s = w * NSW + i;
-            bf16x8 bv;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int c = 32 * s + 8 * g + t;
-                const float x = (pxok && c < a.C) ? a.X[(size_t)c * a.N + px] : 0.f;
-                d[i][t] = (c < a.C) ? x - smu[c] : 0.f;
-                bv[t] = (__bf16)d[i][t];
-            }
-#pragma unroll
-            for (int kt = 0; kt < KT; ++kt)
-                z[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V1[((s * KT + kt) * 4 + g) * 16 + n], bv,
-                                                                z[kt], 0, 0, 0);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) zp[((w * KT + kt) * 4 + v) * 64 + lane] = z[kt][v];
-        __syncthreads();
-        bf16x8 zb[NU];
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float acc = zp[((0 * KT + kt) * 4 + v) * 64 + lane];
-                acc += zp[((1 * KT + kt) * 4 + v) * 64 + lane];
-                acc += zp[((2 * KT + kt) * 4 + v) * 64 + lane];
-                acc += zp[((3 * KT + kt) * 4 + v) * 64 + lane];
-                zb[kt >> 1][4 * (kt & 1) + v] = (__bf16)acc;
-            }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NSW; ++i) {
-            const int s = w * NSW + i;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int t2 = 2 * s + h;
-                floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int u = 0; u < NU; ++u)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V2[((t2 * NU + u) * 4 + g) * 16 + n],
-                                                                  zb[u], acc, 0, 0, 0);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int c = 32 * s + 8 * g + 4 * h + v;
-                    const float r = d[i][4 * h + v] - acc[v];
-                    if (pxok && c < a.C) emit(a, c, px, r, slo, sid);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-    }
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
+        proj_tile_bf16<CMAX, KT>(a, tile, w, lane, V1, V2, smu, slo, sid, zp);
 }
+
 
 template <class K>
 hipError_t go(K kern, const MArgs& a, size_t lds, hipStream_t st) {

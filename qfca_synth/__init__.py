@@ -182,3 +182,67 @@ def poisson_arrivals(rate: float, duration: float, seed: int = 4, sides=(128, 25
             break
         out.append((t, int(rng.choice(sides)), int(rng.integers(0, n_classes))))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Device-side generator for large batches: the same recipe (blur, standardise,
+# mix, anomalous squares) drawn with torch's generator on the GPU.  It does
+# not reproduce the numpy streams above; it is used where generating on the
+# host would take minutes (64 images up to 512x512x256).
+
+def make_texture_torch(C: int, H: int, W: int, seed: int, device="cuda", *, anomalies=(),
+                       subset: int | None = None, class_seed: int | None = None):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    cg = g if class_seed is None else torch.Generator(device=device)
+    if class_seed is not None:
+        cg.manual_seed(int(class_seed))
+    su = float(torch.empty(1, device=device).uniform_(1.5, 6.0, generator=cg))
+    sv = float(torch.empty(1, device=device).uniform_(0.5, 1.5, generator=cg))
+    th = float(torch.empty(1, device=device).uniform_(0.0, float(np.pi), generator=cg))
+    M = torch.randn((C, C), generator=cg, device=device, dtype=torch.float32) / np.sqrt(C)
+    Z = torch.randn((C, H, W), generator=g, device=device, dtype=torch.float32)
+    fy = torch.fft.fftfreq(H, device=device)[:, None]
+    fx = torch.fft.rfftfreq(W, device=device)[None, :]
+    ct, st = np.cos(th), np.sin(th)
+    fu = ct * fx + st * fy
+    fv = -st * fx + ct * fy
+    filt = torch.exp(-2.0 * np.pi ** 2 * ((su * fu) ** 2 + (sv * fv) ** 2))
+    Z = torch.fft.irfft2(torch.fft.rfft2(Z) * filt, s=(H, W))
+    Z = (Z - Z.mean(dim=(1, 2), keepdim=True)) / Z.std(dim=(1, 2), keepdim=True)
+    X = (M @ Z.reshape(C, -1)).reshape(C, H, W)
+    mask = torch.zeros((H, W), dtype=torch.uint8, device=device)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes, kinds = [], []
+    for a in anomalies:
+        s = int(a[1]) if len(a) == 2 else int(rng.integers(a[1], a[2] + 1))
+        kinds.append(a[0])
+        sizes.append(min(s, H, W))
+    info = []
+    if sizes:
+        placed = _place_squares(rng, H, W, sizes)
+        ns = min(subset if subset is not None else max(1, C // 4), C)
+        mu = X.mean(dim=(1, 2))
+        sd = X.std(dim=(1, 2))
+        for kind, (y, x, s) in zip(kinds, placed):
+            S = torch.from_numpy(rng.choice(C, size=ns, replace=False)).to(device)
+            if kind == "shift":
+                X[S, y:y + s, x:x + s] += 1.5 * sd[S, None, None]
+            elif kind == "scale":
+                X[S, y:y + s, x:x + s] = mu[S, None, None] + np.sqrt(3.0) * (X[S, y:y + s, x:x + s] - mu[S, None, None])
+            else:
+                perm = S[torch.from_numpy(rng.permutation(ns)).to(device)]
+                X[S, y:y + s, x:x + s] = X[perm, y:y + s, x:x + s].clone()
+            mask[y:y + s, x:x + s] = 1
+            info.append((kind, y, x, s))
+    return X.contiguous(), mask, info
+
+
+def workload_batch_torch(n: int = 64, C: int = 256, first_seed: int = 300, sides=None, device="cuda"):
+    """The 64-image uneven batch generated on the device."""
+    sides = sides if sides is not None else batch_sides(n)
+    out = [make_texture_torch(C, s, s, first_seed + i, device,
+                              anomalies=[("shift", 8, 32), ("scale", 8, 32), ("permute", 8, 32)])
+           for i, s in enumerate(sides)]
+    return out, dict(C=C, k=32, B=32, T=15, q_lo=0.01, q_hi=0.99, sigma_s=1.0)
