@@ -35,7 +35,7 @@ def make_jobs(ctx, shapes, C, k, B, T, prec, seed0):
     prm = q.Params.make(C=C, k=k, B=B, T=T, proj_prec=prec)
     jobs = []
     for i, (H, W) in enumerate(shapes):
-        t = qfca_synth.make_texture(C, H, W, seed0 + i, anomalies=[("shift", 4, min(H, W) // 3)])
+        t = qfca_synth.make_texture(C, H, W, seed0 + i, anomalies=[("shift", 2, max(3, min(H, W) // 3))])
         X = torch.from_numpy(t.X).cuda()
         m = q.qfca_fit_pca(ctx, prm, X)
         jobs.append((m, X, torch.empty((H, W), device="cuda"), torch.empty((C, H, W), dtype=torch.uint8, device="cuda"),
