@@ -210,6 +210,77 @@ qfca_status qfca_model_params(qfca_model model, qfca_params* out);
 qfca_status qfca_model_read(qfca_model model, int32_t field, void* host_dst, size_t bytes);
 qfca_status qfca_model_destroy(qfca_model model);
 
+/* ------------------------------------------------------------------------
+ * Serving.  A server scores single images submitted one at a time, each
+ * against a resident model (for instance one per texture class), with
+ * continuous batching: a dispatcher thread owned by the server admits
+ * pending requests into a batch (qfca_score_batch arithmetic: each result is
+ * the one that image gets alone) whenever one of its launch slots is free
+ * and their device working memory fits in the server's budget, and launches
+ * it on that slot's own stream, so batches launched while others run
+ * overlap on the device.  Admission is first-come first-served among
+ * requests that can share a launch (same C, k, B, T, sigma_s, precision);
+ * a request whose memory does not fit waits, and later requests of its kind
+ * wait behind it.  Working memory per request is
+ * 256-byte-aligned C*H*W (bins) + 4*C*H*W (channel maps) + 4*H*W bytes. */
+typedef struct qfca_server_s* qfca_server;
+
+typedef struct {
+    uint64_t hbm_budget;   /* bytes of device memory for in-flight requests (one allocation) */
+    int32_t max_inflight;  /* launch slots (streams), 1..8 */
+    int32_t max_batch;     /* requests per launch, 1..256 */
+    int32_t Ws, Hb;        /* score tile for every slot (0, 0: automatic) */
+} qfca_server_config;
+
+typedef struct {
+    uint64_t ticket;      /* as returned by qfca_server_submit */
+    int32_t status;       /* QFCA_OK, or the failure of the launch that held it */
+    int32_t batch_size;   /* requests in the launch that held it */
+    double t_submit;      /* qfca_clock() at submission */
+    double t_launch;      /* qfca_clock() when its launch was issued */
+    double t_done;        /* qfca_clock() when the dispatcher saw the launch complete */
+} qfca_completion;
+
+typedef struct {
+    uint64_t submitted, completed, failed, launches;
+    uint64_t deferred_memory;     /* launches cut short because memory did not fit */
+    int32_t max_inflight_seen;    /* most launches in flight at once */
+    int32_t max_batch_seen;       /* largest launch */
+    uint64_t arena_bytes, arena_peak;
+    double device_busy_s;         /* union of the launches' device intervals (HIP events) */
+    double device_span_s;         /* first launch start to last launch end */
+    uint64_t overlapped;          /* launches whose device interval met another launch's */
+} qfca_server_counters;
+
+/* Seconds of the host's monotonic clock (CLOCK_MONOTONIC), the clock of
+ * qfca_completion's times. */
+double qfca_clock(void);
+
+/* Creates a server on `device`: allocates the budget, one stream and
+ * context per slot, and starts the dispatcher thread.  QFCA_E_NOMEM if the
+ * budget cannot be allocated. */
+qfca_status qfca_server_create(int32_t device, const qfca_server_config* cfg, qfca_server* out);
+
+/* Queues one request and returns at once with its ticket.  X: device
+ * [C][H][W] float32 and score: device [H][W] float32 out, both owned by the
+ * caller and left untouched by it until the ticket completes.  model must
+ * have a reference and satisfy qfca_score_batch's conditions.
+ * QFCA_E_NOMEM if the request alone exceeds the budget. */
+qfca_status qfca_server_submit(qfca_server server, qfca_model model, const float* X, int32_t H,
+                               int32_t W, float* score, uint64_t* ticket);
+
+/* Moves up to cap completions (in completion order) to out; *n receives how
+ * many.  Non-blocking. */
+qfca_status qfca_server_poll(qfca_server server, qfca_completion* out, int32_t cap, int32_t* n);
+
+/* Blocks until every submitted request has completed. */
+qfca_status qfca_server_drain(qfca_server server);
+
+qfca_status qfca_server_stats(qfca_server server, qfca_server_counters* out);
+
+/* Drains, stops the dispatcher and frees the server. */
+qfca_status qfca_server_destroy(qfca_server server);
+
 /* The host FP64 symmetric eigensolver used by qfca_fit_pca (Householder
  * tridiagonalisation, then implicit QL), exposed for testing.  A: host
  * [n][n] row-major symmetric (destroyed); evals: host [n] out, descending;

@@ -31,7 +31,8 @@ EXPORTS = ("qfca_status_str", "qfca_last_error", "qfca_version", "qfca_ctx_creat
            "qfca_fit_reference", "qfca_quantize", "qfca_score_map", "qfca_model_params",
            "qfca_model_read", "qfca_model_destroy", "qfca_host_sym_eig", "qfca_ctx_profile",
            "qfca_ctx_profile_read", "qfca_ctx_set_tile", "qfca_score_batch", "qfca_batch_error",
-           "qfca_autotune")
+           "qfca_autotune", "qfca_clock", "qfca_server_create", "qfca_server_submit",
+           "qfca_server_poll", "qfca_server_drain", "qfca_server_stats", "qfca_server_destroy")
 
 KERNELS = {"score": 0, "proj": 1, "chanmean": 2, "blur": 3}
 
@@ -62,6 +63,28 @@ class Job(ctypes.Structure):
     _fields_ = [("model", ctypes.c_void_p), ("X", ctypes.c_void_p), ("H", ctypes.c_int32),
                 ("W", ctypes.c_int32), ("score", ctypes.c_void_p), ("bins", ctypes.c_void_p),
                 ("amap", ctypes.c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("Ws", ctypes.c_int32), ("Hb", ctypes.c_int32)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("deferred_memory", ctypes.c_uint64),
+                ("max_inflight_seen", ctypes.c_int32), ("max_batch_seen", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64),
+                ("device_busy_s", ctypes.c_double), ("device_span_s", ctypes.c_double),
+                ("overlapped", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _lib = None
@@ -100,6 +123,17 @@ def lib():
                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
         L.qfca_ctx_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64)]
+        L.qfca_clock.restype = ctypes.c_double
+        L.qfca_clock.argtypes = []
+        L.qfca_server_create.argtypes = [i32, ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
+        L.qfca_server_submit.argtypes = [P, P, P, i32, i32, P, ctypes.POINTER(ctypes.c_uint64)]
+        L.qfca_server_poll.argtypes = [P, ctypes.POINTER(Completion), i32, ctypes.POINTER(ctypes.c_int32)]
+        L.qfca_server_drain.argtypes = [P]
+        L.qfca_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+        L.qfca_server_destroy.argtypes = [P]
+        for name in ("qfca_server_create", "qfca_server_submit", "qfca_server_poll", "qfca_server_drain",
+                     "qfca_server_stats", "qfca_server_destroy"):
+            getattr(L, name).restype = i32
         for name in ("qfca_ctx_create", "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca",
                      "qfca_model_create", "qfca_fit_reference", "qfca_quantize", "qfca_score_map",
                      "qfca_model_params", "qfca_model_read", "qfca_model_destroy",
@@ -345,6 +379,68 @@ def qfca_autotune(ctx: Context, items):
     ws, hb, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     _check(lib().qfca_autotune(ctx.handle, arr, len(items), ctypes.byref(ws), ctypes.byref(hb), ctypes.byref(ms)))
     return ws.value, hb.value, ms.value
+
+
+def qfca_clock() -> float:
+    """Seconds of the host monotonic clock that completion times use."""
+    return lib().qfca_clock()
+
+
+class Server:
+    """Continuous-batching server (qfca_server_*): requests are submitted one
+    image at a time against resident models and complete asynchronously."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_inflight: int = 2,
+                 max_batch: int = 64, Ws: int = 0, Hb: int = 0):
+        cfg = ServerConfig(int(hbm_budget), int(max_inflight), int(max_batch), int(Ws), int(Hb))
+        h = ctypes.c_void_p()
+        _check(lib().qfca_server_create(int(device), ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._buf = (Completion * 1024)()
+
+    def submit(self, model: "Model", X, score) -> int:
+        """X: [C, H, W] float32 and score: [H, W] float32 on the device; both
+        must stay alive and untouched until the returned ticket completes."""
+        import torch
+        _dev_tensor(X, torch.float32, "X", 3)
+        _dev_tensor(score, torch.float32, "score", 2)
+        C, H, W = X.shape
+        if C != model.params.C or tuple(score.shape) != (H, W):
+            raise ValueError("request shapes do not match")
+        t = ctypes.c_uint64()
+        _check(lib().qfca_server_submit(self.handle, model.handle, _ptr(X), H, W, _ptr(score), ctypes.byref(t)))
+        return t.value
+
+    def poll(self):
+        """Completions since the last poll, as dicts."""
+        out = []
+        n = ctypes.c_int32()
+        while True:
+            _check(lib().qfca_server_poll(self.handle, self._buf, len(self._buf), ctypes.byref(n)))
+            for i in range(n.value):
+                c = self._buf[i]
+                out.append({f: getattr(c, f) for f, _ in Completion._fields_})
+            if n.value < len(self._buf):
+                return out
+
+    def drain(self):
+        _check(lib().qfca_server_drain(self.handle))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().qfca_server_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().qfca_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def host_sym_eig(A: np.ndarray):

@@ -15,7 +15,7 @@ OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("QFCA_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-pthread",
     # packed FP32 instructions stay off (hipcc's host pass warns about the
     # feature name; that is expected)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -48,7 +48,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(hipcc, s, verbose), srcs))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -50,6 +50,8 @@ struct qfca_ctx_s {
     hipStream_t capture = nullptr; // private stream used only to capture graphs
     std::map<long long, GraphEntry> graphs;
     std::map<long long, ScoreTile> tuned;  // autotuned tiles keyed by (T, B)
+    int ncu = 0;            // compute units of the device (0: not read yet)
+    size_t lds_per_cu = 0;  // bytes of LDS per compute unit
 };
 
 struct qfca_model_s {
@@ -756,27 +758,41 @@ ScoreTile batch_tile(qfca_ctx ctx, const qfca_params& p) {
 extern "C" {
 
 qfca_status qfca_score_batch(qfca_ctx ctx, const qfca_job* jobs, int32_t n) {
+    return score_batch_ext(ctx, jobs, n, nullptr, nullptr);
+}
+
+}  // extern "C"
+
+qfca_status qfca::batch_job_check(qfca_ctx ctx, const qfca_job& J, const qfca_params& p) {
+    if (!J.model || !J.X || !J.score) return fail(QFCA_E_ARG, "job with a NULL model, X or score");
+    const qfca_params& q = J.model->p;
+    if (q.C != p.C || q.k != p.k || q.B != p.B || q.T != p.T || q.preproc != p.preproc ||
+        q.proj_prec != p.proj_prec || q.sigma_s != p.sigma_s)
+        return fail(QFCA_E_ARG, "all jobs of a batch must share C, k, B, T, sigma_s, preproc, proj_prec");
+    if (!J.model->has_ref) return fail(QFCA_E_STATE, "model without reference");
+    if (J.model->device != ctx->device) return fail(QFCA_E_ARG, "model on another device");
+    qfca_status st = check_shape(J.H, J.W, p.C);
+    if (st != QFCA_OK) return st;
+    const int CM = mfma_cmax(p.C, p.proj_prec), KT = mfma_kt(p.k, p.proj_prec);
+    if (p.preproc != QFCA_PRE_RESIDUAL || !CM || !KT || !batch_supported(p.T, CM, KT, p.proj_prec) ||
+        !J.model->d_V1)
+        return fail(QFCA_E_UNSUPPORTED, "batched path: unsupported (T, C, k, precision) combination");
+    return QFCA_OK;
+}
+
+qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n, float* const* achan_ext,
+                                  int32_t* err_host) {
     if (!ctx || !jobs) return fail(QFCA_E_ARG, "NULL argument");
     if (n < 1 || n > BATCH_MAXJ) return fail(QFCA_E_ARG, "n must be in [1, 256]");
     const qfca_model m0 = jobs[0].model;
     if (!m0) return fail(QFCA_E_ARG, "job 0 has no model");
     const qfca_params p = m0->p;
     for (int i = 0; i < n; ++i) {
-        const qfca_job& J = jobs[i];
-        if (!J.model || !J.X || !J.score) return fail(QFCA_E_ARG, "job with a NULL model, X or score");
-        const qfca_params& q = J.model->p;
-        if (q.C != p.C || q.k != p.k || q.B != p.B || q.T != p.T || q.preproc != p.preproc ||
-            q.proj_prec != p.proj_prec || q.sigma_s != p.sigma_s)
-            return fail(QFCA_E_ARG, "all jobs of a batch must share C, k, B, T, sigma_s, preproc, proj_prec");
-        if (!J.model->has_ref) return fail(QFCA_E_STATE, "model without reference");
-        if (J.model->device != ctx->device) return fail(QFCA_E_ARG, "model on another device");
-        qfca_status st = check_shape(J.H, J.W, p.C);
+        qfca_status st = batch_job_check(ctx, jobs[i], p);
         if (st != QFCA_OK) return st;
+        if (achan_ext && !achan_ext[i]) return fail(QFCA_E_ARG, "NULL channel-map buffer");
     }
     const int CM = mfma_cmax(p.C, p.proj_prec), KT = mfma_kt(p.k, p.proj_prec);
-    if (p.preproc != QFCA_PRE_RESIDUAL || !CM || !KT || !batch_supported(p.T, CM, KT, p.proj_prec) ||
-        !m0->d_V1)
-        return fail(QFCA_E_UNSUPPORTED, "batched path: unsupported (T, C, k, precision) combination");
     HIP_TRY(hipSetDevice(ctx->device));
     const ScoreTile tile = batch_tile(ctx, p);
     const int Bp = batch_lanes(p.B);
@@ -800,7 +816,7 @@ qfca_status qfca_score_batch(qfca_ctx ctx, const qfca_job* jobs, int32_t n) {
     for (int i = 0; i < n; ++i) {
         const size_t N = (size_t)jobs[i].H * jobs[i].W;
         if (!jobs[i].bins) nb += (size_t)p.C * N;
-        na += (size_t)p.C * N;
+        if (!achan_ext) na += (size_t)p.C * N;
         if (!jobs[i].amap) nm += N;
     }
     uint8_t* sb = nullptr;
@@ -824,8 +840,8 @@ qfca_status qfca_score_batch(qfca_ctx ctx, const qfca_job* jobs, int32_t n) {
         const int N = J.H * J.W;
         uint8_t* bins = J.bins ? J.bins : sb + ob;
         if (!J.bins) ob += (size_t)p.C * N;
-        float* achan = sa + oa;
-        oa += (size_t)p.C * N;
+        float* achan = achan_ext ? achan_ext[i] : sa + oa;
+        if (!achan_ext) oa += (size_t)p.C * N;
         float* amap = J.amap ? J.amap : sm + om;
         if (!J.amap) om += N;
         b.pa.X = J.X; b.pa.C = p.C; b.pa.N = N; b.pa.k = p.k; b.pa.B = p.B;
@@ -860,14 +876,14 @@ qfca_status qfca_score_batch(qfca_ctx ctx, const qfca_job* jobs, int32_t n) {
     HIP_TRY(hipEventRecord(ctx->staged, ctx->stream));
 
     // grid: as many resident blocks as fit
-    int per_cu = 1, ncu = 1;
-    {
+    if (!ctx->ncu) {
         hipDeviceProp_t prop;
         HIP_TRY(hipGetDeviceProperties(&prop, ctx->device));
-        ncu = prop.multiProcessorCount;
-        per_cu = std::max(1, (int)(prop.maxSharedMemoryPerMultiProcessor / std::max<size_t>(lds, 1)));
-        per_cu = std::min(per_cu, 2);
+        ctx->ncu = prop.multiProcessorCount;
+        ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
     }
+    const int ncu = ctx->ncu;
+    const int per_cu = std::min(2, std::max(1, (int)(ctx->lds_per_cu / std::max<size_t>(lds, 1))));
     const int grid = ncu * per_cu;
     int maxn = 1;
     while (maxn < n) maxn <<= 1;
@@ -886,10 +902,16 @@ qfca_status qfca_score_batch(qfca_ctx ctx, const qfca_job* jobs, int32_t n) {
         ge.graph = g;
         HIP_TRY(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0));
     }
-    KernelTimer kt(ctx, K_SCORE);
-    HIP_TRY(hipGraphLaunch(ge.exec, ctx->stream));
+    {
+        KernelTimer kt(ctx, K_SCORE);
+        HIP_TRY(hipGraphLaunch(ge.exec, ctx->stream));
+    }
+    if (err_host)
+        HIP_TRY(hipMemcpyAsync(err_host, &ctx->d_hdr->error, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     return QFCA_OK;
 }
+
+extern "C" {
 
 qfca_status qfca_batch_error(qfca_ctx ctx, int32_t* failed) {
     if (!ctx || !failed) return fail(QFCA_E_ARG, "NULL argument");

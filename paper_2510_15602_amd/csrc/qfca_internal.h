@@ -67,6 +67,15 @@ hipError_t prepare_batch(int T, int CMAX, int KT, int prec, size_t lds);
 hipError_t launch_batch(int T, int CMAX, int KT, int prec, BatchHeader* hdr, const BatchJob* jobs,
                         int wave_lds, size_t lds, int grid, int maxn, hipStream_t st);
 
+// Batched launch (the body of qfca_score_batch).  achan: per-job channel-map
+// buffers of C*H*W floats, or nullptr for context scratch.  err_host: pinned
+// host word that receives the batch's wait-failure flag (stream-ordered after
+// the batch), or nullptr.
+qfca_status score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n, float* const* achan,
+                            int32_t* err_host);
+// Validation of one job against the parameters p of its batch.
+qfca_status batch_job_check(qfca_ctx ctx, const qfca_job& job, const qfca_params& p);
+
 // Per-thread last error message, set by the API layer.
 void set_error(const std::string& msg);
 
