@@ -44,11 +44,18 @@ __device__ int find_job(const int* prefix, int n, int item) {
 }
 
 template <int T, int CMAX, int KT, bool BF>
-__global__ __launch_bounds__(256) void k_batch(BatchHeader* hdr, const BatchJob* jobs, int wave_lds) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* jobs, int wave_lds) {
+    // LDS: the block-shared reciprocal table of the score tiles (it depends
+    // on T only), then either the projection scratch or 4 wave regions
+    extern __shared__ __align__(16) unsigned char smem_all[];
     __shared__ int s_item, s_job, s_ok;
+    constexpr size_t RCP = BLayout<T>::RCP_BYTES;
+    float* rcp4 = (float*)smem_all;
+    unsigned char* smem = smem_all + RCP;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int n = hdr->n, nproj = hdr->nproj, nitems = hdr->nitems;
+    if (n > 0) fill_rcp4<T>(rcp4, jobs[0].sa.rcp, threadIdx.x, 256);
+    __syncthreads();
     for (;;) {
         if (threadIdx.x == 0) {
             const int it = atomicAdd(&hdr->head, 1);
@@ -107,11 +114,33 @@ __global__ __launch_bounds__(256) void k_batch(BatchHeader* hdr, const BatchJob*
                 const int rest = local / J.nstrips;
                 const int by = rest % J.nbands;
                 const int gz = rest / J.nbands;
-                score_tile<T>(J.sa, bx, by, 4 * gz + w, lane, smem + (size_t)w * wave_lds);
+                score_tile<T>(J.sa, bx, by, 4 * gz + w, lane, smem + (size_t)w * wave_lds, rcp4);
             }
         }
         __syncthreads();
     }
+}
+
+// The persistent kernel.  Up to T = 15 the register budget is held to two
+// wavefronts per SIMD (the projection and score tiles then fit without
+// spilling); larger windows keep the full register file.
+constexpr int BATCH_TWO_WAVES_MAX_T = 15;
+
+template <int T, int CMAX, int KT, bool BF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_batch2(
+        BatchHeader* hdr, const BatchJob* jobs, int wave_lds) {
+    batch_body<T, CMAX, KT, BF>(hdr, jobs, wave_lds);
+}
+
+template <int T, int CMAX, int KT, bool BF>
+__global__ __launch_bounds__(256) void k_batch1(BatchHeader* hdr, const BatchJob* jobs, int wave_lds) {
+    batch_body<T, CMAX, KT, BF>(hdr, jobs, wave_lds);
+}
+
+template <int T, int CMAX, int KT, bool BF>
+const void* batch_kernel() {
+    if constexpr (T <= BATCH_TWO_WAVES_MAX_T) return (const void*)k_batch2<T, CMAX, KT, BF>;
+    else return (const void*)k_batch1<T, CMAX, KT, BF>;
 }
 
 // A(x) = (1/C) sum_c achan[c][x] for every image (grid: x chunks, images).
@@ -181,7 +210,10 @@ template <int T, int CMAX, int KT, bool BF>
 hipError_t run_batch(BatchHeader* hdr, const BatchJob* jobs, int wave_lds, size_t lds, int grid,
                      int maxn, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_reset, dim3((maxn + 255) / 256), dim3(256), 0, st, hdr, maxn);
-    hipLaunchKernelGGL((k_batch<T, CMAX, KT, BF>), dim3(grid), dim3(256), lds, st, hdr, jobs, wave_lds);
+    if constexpr (T <= BATCH_TWO_WAVES_MAX_T)
+        hipLaunchKernelGGL((k_batch2<T, CMAX, KT, BF>), dim3(grid), dim3(256), lds, st, hdr, jobs, wave_lds);
+    else
+        hipLaunchKernelGGL((k_batch1<T, CMAX, KT, BF>), dim3(grid), dim3(256), lds, st, hdr, jobs, wave_lds);
     hipLaunchKernelGGL(k_batch_chanmean, dim3(512, maxn), dim3(256), 0, st, (const BatchHeader*)hdr, jobs);
     hipLaunchKernelGGL(k_batch_blur, dim3(256, 1, maxn), dim3(256), 0, st, (const BatchHeader*)hdr, jobs);
     return hipGetLastError();
@@ -211,7 +243,7 @@ hipError_t prepare_batch(int T, int CMAX, int KT, int prec, size_t lds) {
     const bool bf = prec == QFCA_PREC_BF16;
 #define QFCA_PREP_CASE(TT, CM, KK, BFV)                                                    \
     if (T == TT && CMAX == CM && KT == KK && bf == BFV)                                    \
-        return hipFuncSetAttribute((const void*)k_batch<TT, CM, KK, BFV>,                  \
+        return hipFuncSetAttribute(batch_kernel<TT, CM, KK, BFV>(),                         \
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 #define QFCA_PREP_T(TT) QFCA_PREP_CASE(TT, 64, 1, false) QFCA_PREP_CASE(TT, 256, 2, false) \
     QFCA_PREP_CASE(TT, 512, 4, false) QFCA_PREP_CASE(TT, 256, 2, true) QFCA_PREP_CASE(TT, 512, 4, true)

@@ -61,6 +61,7 @@ struct BatchHeader {
     int score_prefix[BATCH_MAXJ + 1];
 };
 size_t batch_wave_lds(int T, int S, int Ws);
+size_t score_rcp_bytes(int T);  // block-shared reciprocal table of the score tiles
 size_t batch_proj_lds(int CMAX, int KT);
 bool batch_supported(int T, int CMAX, int KT, int prec);
 hipError_t prepare_batch(int T, int CMAX, int KT, int prec, size_t lds);

@@ -242,7 +242,9 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
 template <int T>
 __global__ __launch_bounds__(64) void k_score_t(KArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    score_tile<T>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, smem);
+    float* rcp4 = (float*)smem;  // block-shared, at LDS offset 0
+    fill_rcp4<T>(rcp4, a.rcp, threadIdx.x, 64);
+    score_tile<T>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, smem + BLayout<T>::RCP_BYTES, rcp4);
 }
 
 // A(x) = (1/C) sum_c achan[c][x] in double precision, fixed channel order.
@@ -321,7 +323,9 @@ static int alloc_cols(int T, int Ws, int variant) {
 }
 
 template <int T>
-static size_t blayout_bytes(int S, int Ws) { return BLayout<T>(S, Ws).total; }
+static size_t blayout_bytes(int S, int Ws) { return BLayout<T>::RCP_BYTES + BLayout<T>(S, Ws).total; }
+
+size_t score_rcp_bytes(int T) { return align16((size_t)(T * T + 1) * 4); }
 
 size_t score_lds_bytes(int T, int Bp, int S, int Ws, int variant) {
     if (variant == 1 && score_has_block_kernel(T)) {

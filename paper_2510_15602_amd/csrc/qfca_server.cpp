@@ -16,6 +16,8 @@
 #include <thread>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "qfca_internal.h"
 #include "serve_policy.h"
 
@@ -176,6 +178,8 @@ void dispatcher(qfca_server s) {
             const qfca_status st = issue(s, L, L.reqs);
             lk.lock();
             if (st != QFCA_OK) {
+                // work the failed call did enqueue may still use the memory
+                (void)hipStreamSynchronize(L.stream);
                 retire(s, L, st);
                 s->cv_done.notify_all();
             } else {
@@ -246,9 +250,20 @@ qfca_status qfca_server_create(int32_t device, const qfca_server_config* cfg, qf
     }
     s->arena.reset(budget);
     s->st.arena_bytes = budget;
+    // Each slot's stream is created with a CU mask covering every compute
+    // unit: such a stream gets a hardware queue of its own, so launches of
+    // different slots are never serialised behind one another in a shared
+    // queue (ordinary streams are spread over a small pool of queues).
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 1) {
+        teardown(s);
+        return srv_fail(QFCA_E_DEVICE, "could not read the compute-unit count");
+    }
+    std::vector<uint32_t> cu_mask((size_t)(ncu + 31) / 32, 0xFFFFFFFFu);
+    if (ncu % 32) cu_mask.back() = (1u << (ncu % 32)) - 1u;
     s->slots.resize(cfg->max_inflight);
     for (LaunchSlot& L : s->slots) {
-        if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
+        if (hipExtStreamCreateWithCUMask(&L.stream, (uint32_t)cu_mask.size(), cu_mask.data()) != hipSuccess ||
             hipEventCreate(&L.ev0) != hipSuccess || hipEventCreate(&L.ev1) != hipSuccess ||
             hipHostMalloc((void**)&L.h_err, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
             teardown(s);

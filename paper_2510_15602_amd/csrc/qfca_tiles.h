@@ -8,11 +8,22 @@ namespace qfca {
 namespace tiles {
 
 __device__ __forceinline__ int lane_prev(int v) {
-    // Value held by lane-1 (DPP wave_shr:1); lane 0 receives 0.
-    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+    // Value held by lane-1 (DPP wave_shr:1); lane 0 receives 0 (bound_ctrl).
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
 }
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+// LDS (address space 3) views: loads through these take a 32-bit LDS byte
+// address held in a register, so constant parts of an address fold into the
+// instruction's offset field.
+typedef __attribute__((address_space(3))) const char* lds_cptr;
+typedef __attribute__((address_space(3))) const int* lds_iptr;
+typedef __attribute__((address_space(3))) const float* lds_fptr;
+
+__device__ __forceinline__ int lds_addr(const void* p) { return (int)(uintptr_t)(lds_cptr)(const char*)p; }
+__device__ __forceinline__ int lds_load_i(int addr) { return *(lds_iptr)(uintptr_t)addr; }
+__device__ __forceinline__ float lds_load_f(int addr) { return *(lds_fptr)(uintptr_t)addr; }
 
 
 // Same computation as k_score with the window side T fixed at compile time,
@@ -20,20 +31,33 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 //   1. the vertical counts vc of every bin column are updated in place (one
 //      pass, dword-wide; the counts of lane (s, j) for a T-column block are
 //      T consecutive bytes padded to a multiple of 4);
-//   2. the row is walked in blocks of T patch columns: the T counts of the
-//      block are read, the running window sums formed in registers, and then
-//      the T table reads, the T neighbour exchanges and the T reciprocal reads
-//      are each issued together; the values leaving the running sums T
-//      columns later (counts, per-bin errors) stay in register rings;
-//   3. the horizontal window sums of the block's T output columns are written
-//      to a small LDS buffer and gathered into the pending rows' accumulators
-//      by all lanes at once, one (channel, column, pending row) triple per
-//      lane.
+//   2. the row is walked in blocks of T patch columns.  Window cumulative
+//      counts are carried times 4 and offset by the LDS address of the
+//      lane's per-channel table psi4[t] = 4 Psi(t), so that they are directly
+//      the addresses of its entries, and differences of two of them are the
+//      addresses of the block-shared table rcp4[P] = 1 / (4 P) at the start
+//      of the block's LDS.  For a full window (n = T*T)
+//      the transport numerator of bin j is, with g(t) = Psi(t) - j t (convex,
+//      smallest at the reference crossing c = cR_{j-1}):
+//        I_j = g(u) + g(v) - 2 min_{[u, v]} g,  u = cP_{j-1}, v = cP_j,
+//      where the minimum is g(u) if c <= u, g(v) if c >= v and g(c) otherwise;
+//      the neighbour lane supplies g(u) (its own g of u, shifted by u).
+//      The T table reads, neighbour exchanges and reciprocal reads of a block
+//      are each issued together;
+//   3. the horizontal window sum of each step is the suffix sum of the
+//      previous block plus the prefix sum of the current one (FP32, in an
+//      order fixed by the block, so deterministic for a given tile); the
+//      sums are written to a small LDS buffer and gathered into the pending
+//      rows' accumulators by all lanes at once, one (channel, column, pending
+//      row) triple per lane.
 template <int T>
 struct BLayout {
     static constexpr int r = T / 2, m = T * T, T1 = T + 1, TP = (T + 3) & ~3;
+    static constexpr int PSI = m + 2;  // psi4 entries per channel (t = 0 .. m + 1)
+    // block-shared 1/(4P) table, P = 0 .. m, at the start of the block's LDS
+    static constexpr size_t RCP_BYTES = ((size_t)(m + 1) * 4 + 15) & ~(size_t)15;
     int nblk, rowb, vs4;
-    size_t vc, ring, acc, hrow, psig, rcp, total;
+    size_t vc, ring, acc, hrow, psi, total;
     __host__ __device__ BLayout(int S, int Ws) {
         nblk = (Ws + 2 * r + T - 1) / T;  // blocks of patch columns
         rowb = (nblk + 1) * TP;           // bin columns [x0-2r, x0-2r+(nblk+1)T)
@@ -44,24 +68,32 @@ struct BLayout {
         ring = off; off += align16((size_t)T1 * S * rowb);
         acc = off;  off += align16((size_t)T * S * Ws * 4 + 64 * 4);
         hrow = off; off += align16((size_t)T * 64 * 4);
-        psig = off; off += align16((size_t)S * (m + 1) * 8);
-        rcp = off;  off += align16((size_t)(m + 1) * 4);
+        psi = off;  off += align16((size_t)S * PSI * 4);
         total = off;
     }
 };
 
+// Fills the block-shared table rcp4[P] = rcp[P] / 4 (exact) for P = 0 .. T*T.
+template <int T>
+__device__ __forceinline__ void fill_rcp4(float* rcp4, const float* rcp, int tid, int nthreads) {
+    for (int t = tid; t <= T * T; t += nthreads) rcp4[t] = 0.25f * rcp[t];
+}
+
 // One (strip bx, band by, channel group bz) tile, run by one wavefront whose
-// lanes are `lane`, with its private LDS region `smem`.  Every wavefront of a
-// block must run a tile of the same geometry (the barriers are block-wide).
+// lanes are `lane`, with its private LDS region `smem` (BLayout) and the
+// block-shared table rcp4 (fill_rcp4, visible to the wave before the call).
+// Every wavefront of a block must run a tile of the same geometry (the
+// barriers are block-wide).
 template <int T>
 __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int bz, int lane,
-                                           unsigned char* smem) {
+                                           unsigned char* smem, const float* rcp4) {
     using BL = BLayout<T>;
-    constexpr int r = BL::r, m = BL::m, T1 = BL::T1, TP = BL::TP;
+    constexpr int r = BL::r, m = BL::m, T1 = BL::T1, TP = BL::TP, PSI = BL::PSI;
     const int Bp = a.Bp, S = a.S, H = a.H, W = a.W, Ws = a.Ws;
     const int s = lane / Bp;
     const int sa = s < S ? s : S - 1;
     const int j = lane - s * Bp;
+    const bool j0 = (j == 0);
     const int x0 = bx * Ws;
     const int xe = min(W, x0 + Ws);
     const int ws = xe - x0;
@@ -83,22 +115,37 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     float* acc = (float*)(smem + L.acc);         // [T][S][Ws] + 64 trash slots
     float* trash = acc + T * S * Ws;
     float* hrow = (float*)(smem + L.hrow);       // [T][64]
-    int2* psig = (int2*)(smem + L.psig);
-    float* rcp = (float*)(smem + L.rcp);
+    int* psi = (int*)(smem + L.psi);             // [S][PSI]: 4 Psi_c(t)
 
-    for (int t = lane; t < S * (m + 1); t += 64) {
-        const int ss = t / (m + 1), tt = t - ss * (m + 1);
+    // psi4[t] = 4 Psi(t) for t <= m, and 4 Psi(m + 1) = 4 (Psi(m) + sigma(m))
+    for (int t = lane; t < S * PSI; t += 64) {
+        const int ss = t / PSI, tt = t - ss * PSI;
         const int cc = cbase + ss;
-        psig[t] = (cc < a.C) ? a.psig[(size_t)cc * (m + 1) + tt] : make_int2(0, 0);
+        int v = 0;
+        if (cc < a.C) {
+            const int2 p = a.psig[(size_t)cc * (m + 1) + min(tt, m)];
+            v = 4 * (tt <= m ? p.x : p.x + p.y);
+        }
+        psi[t] = v;
     }
-    for (int t = lane; t <= m; t += 64) rcp[t] = a.rcp[t];
     for (int t = lane; t < 64 * L.vs4; t += 64) vc32[t] = 0u;
     for (int t = lane; t < T * S * Ws + 64; t += 64) acc[t] = 0.f;
     const int ci = cval ? c : 0;
     const int crm1 = a.cRm1[ci * Bp + j];
     const int dm1 = a.Dm1[ci * Bp + j];
-    const int crl = a.cRl[ci * Bp + j];
-    const float binf = (cval && (j < a.B)) ? 1.f : 0.f;
+    const int crl4 = 4 * a.cRl[ci * Bp + j];
+    // The running counts carry the LDS address `bias` of this lane's psi4
+    // table: cpb = 4 cP + bias is the address of psi4[cP], and the difference
+    // of two such counts, 4P, is the offset of rcp4[P] from rcp4.  The g
+    // values below are all shifted by the same per-lane constant -j bias,
+    // which cancels in I.
+    const int* psl = psi + sa * PSI;
+    const int bias = lds_addr(psl);
+    const int rbase = lds_addr(rcp4);
+    const int crmb = 4 * crm1 + bias;              // 4 c + bias, c = cR_{j-1}
+    const int gcb = 4 * dm1 - j * (4 * crm1 + bias);  // 4 g(c) - j bias
+    const int dm1_4 = 4 * dm1;
+    const int negj = -j;
     const bool w1ok = cval && (j < a.B - 1);
     const bool want_w1 = a.w1chan != nullptr;
     constexpr float inv_m = 1.0f / (float)m;
@@ -184,58 +231,57 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
         }
         // Step i walks patch column p = x0 - r + i; its window covers bin
         // columns q in [i, i + 2r].  The count entering at step i is vc[i + 2r]
-        // and the one leaving is vc[i - 1], which entered T steps earlier.
-        int vring[T];
-        double ering[T];
-        int cP = 0;
-        vring[0] = 0;
+        // and the one leaving is vc[i - 1].
+        int cpb = 0;
 #pragma unroll
-        for (int k = 1; k < T; ++k) {
-            vring[k] = vcl[k - 1];  // bin columns 0 .. 2r-1 (layout block 0)
-            cP += vring[k];
-        }
+        for (int k = 0; k < T - 1; ++k) cpb += (int)vcl[k];  // bin columns 0 .. 2r-1 (layout block 0)
+        cpb = 4 * cpb + bias;
+        int ent0 = 0;  // count that entered at step k = 0 of the previous block
+        float suf[T];  // suffix sums of the previous block's errors (suf[k] = sum over k' >= k)
 #pragma unroll
-        for (int k = 0; k < T; ++k) ering[k] = 0.0;
-        double hs = 0.0;
+        for (int k = 0; k < T; ++k) suf[k] = 0.f;
         for (int blk = 0; blk < nblk; ++blk) {
             const int i0 = blk * T;
             const int p0 = x0 - r + i0;  // patch column of the block's first step
             const bool full = row_full && (i0 + T <= np) && (p0 >= r) && (p0 + T - 1 <= W - 1 - r);
-            // 1. counts entering the window and the running cumulative counts
-            int cpv[T], cm1[T];
+            // 1. counts entering and leaving the window, running cumulative counts
+            int cpv[T], cmv[T];
             const uint8_t* vb = vcl + blk * TP;
 #pragma unroll
             for (int k = 0; k < T; ++k) {
-                // bin column i0 + k + 2r = (blk + 1) T + k - 1
-                const int v = (k == 0) ? (int)vb[T - 1] : (int)vb[TP + k - 1];
-                cP += v - vring[k];
-                vring[k] = v;
-                cpv[k] = cP;
+                // entering: bin column i0 + k + 2r = (blk + 1) T + k - 1;
+                // leaving:  bin column i0 + k - 1 = blk T + k - 1
+                const int ve = (k == 0) ? (int)vb[T - 1] : (int)vb[TP + k - 1];
+                const int vl = (k == 0) ? ent0 : (int)vb[k - 1];
+                if (k == 0) ent0 = ve;
+                cpb += (ve - vl) << 2;
+                cpv[k] = cpb;
             }
 #pragma unroll
             for (int k = 0; k < T; ++k) {
                 const int u = lane_prev(cpv[k]);
-                cm1[k] = (j == 0) ? 0 : u;
+                cmv[k] = j0 ? bias : u;
             }
             float ev[T];
             if (full) {
-                int psv[T];
-#pragma unroll
-                for (int k = 0; k < T; ++k) psv[k] = psig[sa * (m + 1) + cpv[k]].x;
+                int gv[T];
                 float rc[T];
 #pragma unroll
-                for (int k = 0; k < T; ++k) rc[k] = rcp[cpv[k] - cm1[k]];
+                for (int k = 0; k < T; ++k) gv[k] = lds_load_i(cpv[k]);
+#pragma unroll
+                for (int k = 0; k < T; ++k) rc[k] = lds_load_f(rbase + (cpv[k] - cmv[k]));
+#pragma unroll
+                for (int k = 0; k < T; ++k) gv[k] += __mul24(negj, cpv[k]);  // 4 g(v) - j bias
 #pragma unroll
                 for (int k = 0; k < T; ++k) {
-                    const int pu = lane_prev(psv[k]);
-                    const int psu = (j == 0) ? 0 : pu;
-                    const int u = cm1[k], vv = cpv[k];
-                    const int sc = min(max(crm1, u), vv);
-                    const int pss = (crm1 <= u) ? psu : ((crm1 >= vv) ? psv[k] : dm1);
-                    const int I = (psv[k] - pss) + (psu - pss) + __mul24(j, 2 * sc - u - vv);
-                    ev[k] = (float)I * rc[k] * binf;
+                    const int un = lane_prev(gv[k]);  // the neighbour's 4 g(u) - (j - 1) bias, plus 4u
+                    const int gu = j0 ? 0 : un - cmv[k];
+                    const int mn = (crmb <= cmv[k]) ? gu : ((crmb >= cpv[k]) ? gv[k] : gcb);
+                    const int I4 = (gu + gv[k]) - (mn << 1);
+                    ev[k] = (float)I4 * rc[k];
                 }
             } else {
+                const float* rcf = rcp4;
 #pragma unroll
                 for (int k = 0; k < T; ++k) {
                     const int i = i0 + k;
@@ -243,23 +289,24 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                     const bool pval = (i < np) && (p >= 0) && (p < W);
                     const int nx = max(1, min(W - 1, p + r) - max(0, p - r) + 1);
                     const int n = ny * nx;
-                    const int cPk = cpv[k], cPm1 = cm1[k];
+                    const int cPk = (cpv[k] - bias) >> 2, cPm1 = (cmv[k] - bias) >> 2;
                     const int av = __mul24(cPk, m);
-                    int q0d = (int)((float)av * rcp[min(n, m)]);
+                    int q0d = (int)((float)av * (4.f * rcf[min(n, m)]));
                     q0d = max(0, min(q0d, m));
                     if (q0d < m && __mul24(q0d + 1, n) <= av) q0d++;
                     if (q0d > 0 && __mul24(q0d, n) > av) q0d--;
-                    const int2 ps = psig[sa * (m + 1) + q0d];
-                    const int phia = __mul24(n, ps.x) + __mul24(av - __mul24(q0d, n), ps.y);
+                    const int* pq = psl + q0d;
+                    const int ps0 = pq[0], ps1 = pq[1];  // 4 Psi(q), 4 Psi(q + 1)
+                    const int phia = __mul24(n, ps0) + __mul24(av - __mul24(q0d, n), ps1 - ps0);
                     const int pu = lane_prev(phia);
-                    const int phiu = (j == 0) ? 0 : pu;
+                    const int phiu = j0 ? 0 : pu;
                     const int au = __mul24(cPm1, m);
                     const int cm = __mul24(crm1, n);
                     const int sc = min(max(cm, au), av);
-                    const int phis = (cm <= au) ? phiu : ((cm >= av) ? phia : __mul24(n, dm1));
-                    const int I = (phia - phis) + (phiu - phis) + __mul24(j, 2 * sc - au - av);
+                    const int phis = (cm <= au) ? phiu : ((cm >= av) ? phia : __mul24(n, dm1_4));
+                    const int I4 = (phia - phis) + (phiu - phis) + __mul24(4 * j, 2 * sc - au - av);
                     const int P = min(max(cPk - cPm1, 0), m);
-                    ev[k] = pval ? (float)I * rcp[P] * inv_m * binf : 0.f;
+                    ev[k] = pval ? (float)I4 * rcf[P] * inv_m : 0.f;
                 }
             }
             if (want_w1 && own_row) {
@@ -269,22 +316,30 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                     if (p >= x0 && p < xe) {
                         const int nx = min(W - 1, p + r) - max(0, p - r) + 1;
                         const int n = ny * nx;
-                        int d = w1ok ? abs(cpv[k] * m - crl * n) : 0;
+                        int d = w1ok ? abs((cpv[k] - bias) * m - crl4 * n) : 0;
                         for (int o = Bp >> 1; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
                         if (cval && j == 0)
                             a.w1chan[((size_t)c * H + y) * W + p] =
-                                (float)(a.delta[c] * (double)d / ((double)n * (double)m));
+                                (float)(a.delta[c] * (double)d / (4.0 * (double)n * (double)m));
                     }
                 }
             }
-            // 2. horizontal window sums; after step i the sum covers patch
-            //    steps [i - 2r, i], i.e. output column o = i - 2r
+            // 2. horizontal window sums: after step i0 + k the window holds
+            //    steps [i0 + k - 2r, i0 + k] = previous block's k+1 .. T-1 and
+            //    this block's 0 .. k; output column o = i0 + k - 2r
+            {
+                float pre = 0.f;
 #pragma unroll
-            for (int k = 0; k < T; ++k) {
-                const double ed = (double)ev[k];
-                hs += ed - ering[k];
-                ering[k] = ed;
-                hrow[k * 64 + lane] = (float)hs;
+                for (int k = 0; k < T; ++k) {
+                    pre += ev[k];
+                    hrow[k * 64 + lane] = (k < T - 1) ? suf[k + 1] + pre : pre;
+                }
+                float sf = 0.f;
+#pragma unroll
+                for (int k = T - 1; k >= 1; --k) {
+                    sf += ev[k];
+                    suf[k] = sf;
+                }
             }
             __syncthreads();
             // 3. gather the pixel's own bin into the accumulators of the T
