@@ -15,8 +15,10 @@ Prints one JSON line.  --gpus above 1 is refused: this benchmark measures one
 GPU.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -34,6 +36,37 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # (10), the per-bin error I / P (4) and the separable box association (4).
 SCORE_OPS_PER_PCB = 22
 METRIC = "score Mpixel/s at 256\u00b2\u00d7256ch (FP32 vs BF16-batched); p50/p99 latency"
+
+
+# HBM traffic of the score kernel on this workload comes from rocprofv3 byte
+# counters (FETCH_SIZE and WRITE_SIZE, scaled by what they read for an
+# elementwise kernel of known size), recorded in this summary together with a
+# hash of the sources the counters were taken on; it is reported only while
+# the sources are unchanged.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_score_t15_256x256_C256_B32.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_15602_amd", "csrc", f)
+                  for f in ("qfca_tiles.h", "qfca_score.hip", "qfca_api.cpp")]
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per launch (read + write) of k_score_t<15> on the 256x256 x 256
+    workload, or None if no summary matches the current kernel sources."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic: sources_sha256=([0-9a-f]+) read_bytes=(\d+) write_bytes=(\d+)", text)
+    if not m or m.group(1) != kernel_sources_sha256():
+        return None
+    return int(m.group(2)) + int(m.group(3))
 
 
 def parse():
@@ -285,8 +318,10 @@ def main():
     score_ops = float(H) * W * C * p["B"] * SCORE_OPS_PER_PCB
     achieved = score_ops / (score_ms * 1e-3) / 1e12
     proj_bytes = float(H) * W * (4 * C + C)
+    default_workload = (H, W, C, p["B"], p["T"]) == (256, 256, 256, 32, 15)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": measured_traffic() if default_workload else None, "traffic_unit": "bytes/launch",
                 "kernel": "k_score", "avg_ms": round(score_ms, 4),
                 "ops_per_launch": score_ops}
     kernels = {

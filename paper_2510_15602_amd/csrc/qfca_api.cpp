@@ -72,6 +72,7 @@ struct qfca_model_s {
     float* d_edges = nullptr;
     float* d_lo = nullptr;
     float* d_invd = nullptr;
+    float* d_fastd = nullptr;
     double* d_delta = nullptr;
     int32_t* d_cR = nullptr;
     ScoreTables tab;
@@ -224,13 +225,31 @@ qfca_status upload_quant(qfca_model m) {
         lof[c] = (float)m->lo[c];
         invd[c] = m->delta[c] > 0.0 ? (float)(1.0 / m->delta[c]) : 0.f;
     }
+    // Margin of the arithmetic bin guess t = (r - lo) * (1/delta) (FP32 on the
+    // device, three roundings: relative error below 3.1e-7 of |t|): with
+    // dev = max_m |(e_m - lo) / delta - m| over the stored edges, a value
+    // whose t lies farther than dev + (B + 2) * 2.4e-7 from every integer
+    // has bin floor(t) (clamped).  A margin of one half or more disables the
+    // shortcut for the channel.
+    std::vector<float> fastd(C, 1.f);
+    for (int c = 0; c < C; ++c) {
+        const double dl = m->delta[c];
+        if (!(dl > 0.0) || B < 2) continue;
+        double dev = 0.0;
+        for (int mm = 1; mm < B; ++mm) {
+            const double e = (double)m->edges[(size_t)c * (B - 1) + mm - 1];
+            dev = std::max(dev, fabs((e - (double)lof[c]) / dl - (double)mm));
+        }
+        const double fd = dev + (double)(B + 2) * 2.4e-7 + 1e-6;
+        if (fd < 0.5) fastd[c] = nextafterf((float)fd, 1.f);
+    }
     std::vector<float> e = m->edges;
     if (e.empty()) e.push_back(0.f);
     HIP_TRY(upload(m, &m->d_edges, e.data(), e.size()));
     HIP_TRY(upload(m, &m->d_lo, lof.data(), lof.size()));
     HIP_TRY(upload(m, &m->d_invd, invd.data(), invd.size()));
+    HIP_TRY(upload(m, &m->d_fastd, fastd.data(), fastd.size()));
     HIP_TRY(upload(m, &m->d_delta, m->delta.data(), m->delta.size()));
-    (void)B;
     return QFCA_OK;
 }
 
@@ -556,7 +575,7 @@ qfca_status qfca_quantize(qfca_ctx ctx, qfca_model m, const float* X, int32_t H,
     L.X = X; L.C = m->p.C; L.N = H * W; L.k = m->p.k; L.B = m->p.B;
     L.preproc = m->p.preproc; L.prec = m->p.proj_prec;
     L.mu = m->d_mu; L.V = m->d_V; L.Vbf = m->d_Vbf; L.edges = m->d_edges; L.lo = m->d_lo;
-    L.inv_delta = m->d_invd; L.bins = bins; L.resid = resid;
+    L.inv_delta = m->d_invd; L.fastd = m->d_fastd; L.bins = bins; L.resid = resid;
     L.V1 = m->d_V1; L.V2 = m->d_V2;
     KernelTimer kt(ctx, K_PROJ);
     HIP_TRY(launch_proj(L, ctx->stream));
@@ -635,7 +654,8 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
         ProjLaunch L;
         L.X = X; L.C = C; L.N = (int)N; L.k = k; L.B = B; L.preproc = p->preproc;
         L.prec = p->proj_prec; L.mu = m->d_mu; L.V = m->d_V; L.Vbf = m->d_Vbf;
-        L.edges = nullptr; L.lo = nullptr; L.inv_delta = nullptr; L.bins = nullptr; L.resid = resid;
+        L.edges = nullptr; L.lo = nullptr; L.inv_delta = nullptr; L.fastd = nullptr; L.bins = nullptr;
+        L.resid = resid;
         L.V1 = m->d_V1; L.V2 = m->d_V2;
         HIP_TRY(launch_proj(L, s));
     }
@@ -846,7 +866,8 @@ qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n,
         if (!J.amap) om += N;
         b.pa.X = J.X; b.pa.C = p.C; b.pa.N = N; b.pa.k = p.k; b.pa.B = p.B;
         b.pa.mu = m->d_mu; b.pa.V1 = m->d_V1; b.pa.V2 = m->d_V2; b.pa.edges = m->d_edges;
-        b.pa.lo = m->d_lo; b.pa.inv_delta = m->d_invd; b.pa.bins = bins; b.pa.resid = nullptr;
+        b.pa.lo = m->d_lo; b.pa.inv_delta = m->d_invd; b.pa.fastd = m->d_fastd; b.pa.bins = bins;
+        b.pa.resid = nullptr;
         b.pa.ntiles = (N + 15) / 16;
         b.sa.bins = bins; b.sa.C = p.C; b.sa.H = J.H; b.sa.W = J.W; b.sa.T = p.T; b.sa.B = p.B;
         b.sa.Bp = Bp; b.sa.S = S; b.sa.r = p.T / 2; b.sa.m = p.T * p.T; b.sa.Ws = tile.Ws;

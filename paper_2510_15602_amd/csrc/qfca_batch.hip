@@ -72,20 +72,27 @@ __device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* job
             float* smu = (float*)smem;
             float* slo = smu + CMAX;
             float* sid = slo + CMAX;
-            float* zp = sid + CMAX;
+            float* sfd = sid + CMAX;
+            float* zp = sfd + CMAX;
             for (int i = threadIdx.x; i < CMAX; i += 256) {
                 const bool ok = i < J.pa.C;
                 smu[i] = ok ? J.pa.mu[i] : 0.f;
                 slo[i] = ok ? J.pa.lo[i] : 0.f;
                 sid[i] = ok ? J.pa.inv_delta[i] : 0.f;
+                sfd[i] = ok ? J.pa.fastd[i] : 1.f;
             }
             __syncthreads();
-            if constexpr (BF)
+            if constexpr (BF) {
+                float x[CMAX / 128][8];
+                proj_load_bf16<CMAX>(J.pa, tile, w, lane, x);
                 proj_tile_bf16<CMAX, KT>(J.pa, tile, w, lane, (const bf16x8*)J.pa.V1, (const bf16x8*)J.pa.V2,
-                                         smu, slo, sid, zp);
-            else
+                                         smu, slo, sid, sfd, zp, x, J.pa.edges, nullptr);
+            } else {
+                float x[CMAX / 16];
+                proj_load_f32<CMAX>(J.pa, tile, w, lane, x);
                 proj_tile_f32<CMAX, KT>(J.pa, tile, w, lane, (const float*)J.pa.V1, (const float*)J.pa.V2,
-                                        smu, slo, sid, zp);
+                                        smu, slo, sid, sfd, zp, x, J.pa.edges, nullptr);
+            }
             __syncthreads();
             if (threadIdx.x == 0) {
                 __threadfence();
@@ -237,7 +244,7 @@ bool batch_supported(int T, int CMAX, int KT, int prec) {
     return (CMAX == 64 && KT == 1) || (CMAX == 256 && KT == 2) || (CMAX == 512 && KT == 4);
 }
 
-size_t batch_proj_lds(int CMAX, int KT) { return (size_t)3 * CMAX * 4 + (size_t)4 * KT * 4 * 64 * 4; }
+size_t batch_proj_lds(int CMAX, int KT) { return (size_t)4 * CMAX * 4 + (size_t)4 * KT * 4 * 64 * 4; }
 
 hipError_t prepare_batch(int T, int CMAX, int KT, int prec, size_t lds) {
     const bool bf = prec == QFCA_PREC_BF16;

@@ -35,6 +35,7 @@ struct MArgs {
     const float* edges;
     const float* lo;
     const float* inv_delta;
+    const float* fastd;  // [C] margin of the arithmetic bin guess (see ProjLaunch)
     uint8_t* bins;
     float* resid;
     int ntiles;
@@ -148,6 +149,11 @@ struct ProjLaunch {
     const float* edges;     // [C][B-1]
     const float* lo;        // [C]
     const float* inv_delta; // [C] (0 for a degenerate channel)
+    // [C] margin, in bin units, beyond which t = (r - lo) * inv_delta in FP32
+    // determines the bin on its own: the largest distance of a stored edge
+    // from the grid lo + m delta plus the rounding bound of t; >= 0.5 when
+    // the edges must always be consulted
+    const float* fastd;
     uint8_t* bins;          // [C][N] or nullptr
     float* resid;           // [C][N] or nullptr
     const void* V1 = nullptr;  // MFMA operand tables (precision of prec), or nullptr

@@ -32,28 +32,67 @@ namespace {
 using namespace tiles;
 
 // ------------------------------------------------------------------------
-// The four wavefronts of a block share one 16-pixel tile: wave w owns the
-// channel quarter [w CMAX/4, (w+1) CMAX/4) in both products.  Partial Z of the
-// four quarters are added through LDS in a fixed order.
-template <int CMAX, int KT, bool VLDS>
-__global__ __launch_bounds__(256) void k_proj_f32_mfma(MArgs a) {
-    constexpr int NSW = CMAX / 16;   // GEMM1 K steps per wave (4 channels each)
-    constexpr int NTW = CMAX / 64;   // GEMM2 channel tiles per wave (16 channels each)
-    constexpr int NU = 4 * KT;       // GEMM2 K steps
-    constexpr int VSZ = CMAX * KT * 16;
-    extern __shared__ __align__(16) float lds[];
-    float* smu = lds;
-    float* slo = smu + CMAX;
-    float* sid = slo + CMAX;
-    float* zp = sid + CMAX;              // [4 waves][KT][4][64]
-    float* sv1 = zp + 4 * KT * 4 * 64;
-    float* sv2 = sv1 + (VLDS ? VSZ : 0);
-    for (int i = threadIdx.x; i < CMAX; i += 256) {
+// Standalone kernels.  The four wavefronts of a block share one 16-pixel
+// tile: wave w owns the channel quarter [w CMAX/4, (w+1) CMAX/4) in both
+// products, and the partial Z of the four quarters are added through LDS in
+// a fixed order.  The blocks are persistent: a block copies the operand
+// tables (VLDS) and the edge table (ELDS) into LDS once, when they fit, then
+// walks tiles blockIdx.x, blockIdx.x + gridDim.x, ..., loading the next
+// tile's features into registers while it computes the current one.  The
+// bins of a tile are staged in LDS and written one 16-byte channel row per
+// thread.
+//
+// LDS: mu, lo, 1/delta, bin margin [CMAX] each; Z partials [4 waves][KT][4]
+// [64]; bin staging [CMAX][16] bytes; the two operand tables (VLDS); the
+// edges [C][B-1] (ELDS).
+struct ProjLds {
+    size_t stg, tab, edges, total;
+};
+
+__host__ __device__ inline ProjLds proj_lds(int CMAX, int KT, int elt, bool vlds, bool elds, int C, int B) {
+    ProjLds L;
+    size_t off = ((size_t)4 * CMAX + (size_t)4 * KT * 4 * 64) * 4;
+    L.stg = off;
+    off += (size_t)CMAX * 16;
+    L.tab = off;
+    if (vlds) off += (size_t)2 * CMAX * KT * 16 * elt;
+    L.edges = off;
+    if (elds) off += (size_t)C * (B > 1 ? B - 1 : 0) * 4;
+    L.total = (off + 15) & ~(size_t)15;
+    return L;
+}
+
+__device__ __forceinline__ void proj_prologue(const MArgs& a, int CMAX, float* smu, float* slo, float* sid,
+                                              float* sfd, float* sedge, bool elds) {
+    for (int i = threadIdx.x; i < CMAX; i += blockDim.x) {
         const bool ok = i < a.C;
         smu[i] = ok ? a.mu[i] : 0.f;
         slo[i] = ok && a.lo ? a.lo[i] : 0.f;
         sid[i] = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
+        sfd[i] = ok && a.fastd ? a.fastd[i] : 1.f;
     }
+    if (elds && a.bins) {
+        const int ne = a.C * (a.B > 1 ? a.B - 1 : 0);
+        for (int i = threadIdx.x; i < ne; i += blockDim.x) sedge[i] = a.edges[i];
+    }
+}
+
+template <int CMAX, int KT, bool VLDS, bool ELDS>
+__device__ __forceinline__ void proj_f32_body(const MArgs& a) {
+    constexpr int NSW = CMAX / 16;   // GEMM1 K steps per wave (4 channels each)
+    constexpr int VSZ = CMAX * KT * 16;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const ProjLds L = proj_lds(CMAX, KT, 4, VLDS, ELDS, a.C, a.B);
+    float* smu = (float*)lds_raw;
+    float* slo = smu + CMAX;
+    float* sid = slo + CMAX;
+    float* sfd = sid + CMAX;
+    float* zp = sfd + CMAX;              // [4 waves][KT][4][64]
+    uint8_t* stg = lds_raw + L.stg;
+    float* sv1 = (float*)(lds_raw + L.tab);
+    float* sv2 = sv1 + VSZ;
+    float* sedge = (float*)(lds_raw + L.edges);
+    proj_prologue(a, CMAX, smu, slo, sid, sfd, sedge, ELDS);
     const float* V1 = (const float*)a.V1;
     const float* V2 = (const float*)a.V2;
     if (VLDS) {
@@ -64,30 +103,42 @@ __global__ __launch_bounds__(256) void k_proj_f32_mfma(MArgs a) {
         V1 = sv1;
         V2 = sv2;
     }
+    const float* edges = ELDS ? (const float*)sedge : a.edges;
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
-        proj_tile_f32<CMAX, KT>(a, tile, w, lane, V1, V2, smu, slo, sid, zp);
+    float x[NSW];
+    int tile = blockIdx.x;
+    if (tile < a.ntiles) proj_load_f32<CMAX>(a, tile, w, lane, x);
+    for (; tile < a.ntiles; tile += gridDim.x) {
+        float xn[NSW];
+        const int nt = tile + gridDim.x;
+        if (nt < a.ntiles) proj_load_f32<CMAX>(a, nt, w, lane, xn);
+        proj_tile_f32<CMAX, KT>(a, tile, w, lane, V1, V2, smu, slo, sid, sfd, zp, x, edges, stg);
+        if (a.bins) {
+            block_sync_lds();
+            proj_store_bins(a, tile, CMAX, stg);
+        }
+#pragma unroll
+        for (int i = 0; i < NSW; ++i) x[i] = xn[i];
+    }
 }
 
-template <int CMAX, int KT, bool VLDS>
-__global__ __launch_bounds__(256) void k_proj_bf16_mfma(MArgs a) {
+template <int CMAX, int KT, bool VLDS, bool ELDS>
+__device__ __forceinline__ void proj_bf16_body(const MArgs& a) {
     constexpr int NSW = CMAX / 128;  // GEMM1 K steps per wave (32 channels each)
-    constexpr int NU = KT / 2;       // GEMM2 K steps (32 components each)
     constexpr int VSZ = CMAX * KT * 16;  // bf16 elements per table
-    extern __shared__ __align__(16) float lds[];
-    float* smu = lds;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const ProjLds L = proj_lds(CMAX, KT, 2, VLDS, ELDS, a.C, a.B);
+    float* smu = (float*)lds_raw;
     float* slo = smu + CMAX;
     float* sid = slo + CMAX;
-    float* zp = sid + CMAX;              // [4 waves][KT][4][64]
-    bf16x8* sv1 = (bf16x8*)(zp + 4 * KT * 4 * 64);
-    bf16x8* sv2 = sv1 + (VLDS ? VSZ / 8 : 0);
-    for (int i = threadIdx.x; i < CMAX; i += 256) {
-        const bool ok = i < a.C;
-        smu[i] = ok ? a.mu[i] : 0.f;
-        slo[i] = ok && a.lo ? a.lo[i] : 0.f;
-        sid[i] = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
-    }
+    float* sfd = sid + CMAX;
+    float* zp = sfd + CMAX;              // [4 waves][KT][4][64]
+    uint8_t* stg = lds_raw + L.stg;
+    bf16x8* sv1 = (bf16x8*)(lds_raw + L.tab);
+    bf16x8* sv2 = sv1 + VSZ / 8;
+    float* sedge = (float*)(lds_raw + L.edges);
+    proj_prologue(a, CMAX, smu, slo, sid, sfd, sedge, ELDS);
     const bf16x8* V1 = (const bf16x8*)a.V1;
     const bf16x8* V2 = (const bf16x8*)a.V2;
     if (VLDS) {
@@ -98,17 +149,68 @@ __global__ __launch_bounds__(256) void k_proj_bf16_mfma(MArgs a) {
         V1 = sv1;
         V2 = sv2;
     }
+    const float* edges = ELDS ? (const float*)sedge : a.edges;
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
-        proj_tile_bf16<CMAX, KT>(a, tile, w, lane, V1, V2, smu, slo, sid, zp);
+    float x[NSW][8];
+    int tile = blockIdx.x;
+    if (tile < a.ntiles) proj_load_bf16<CMAX>(a, tile, w, lane, x);
+    for (; tile < a.ntiles; tile += gridDim.x) {
+        float xn[NSW][8];
+        const int nt = tile + gridDim.x;
+        if (nt < a.ntiles) proj_load_bf16<CMAX>(a, nt, w, lane, xn);
+        proj_tile_bf16<CMAX, KT>(a, tile, w, lane, V1, V2, smu, slo, sid, sfd, zp, x, edges, stg);
+        if (a.bins) {
+            block_sync_lds();
+            proj_store_bins(a, tile, CMAX, stg);
+        }
+#pragma unroll
+        for (int i = 0; i < NSW; ++i)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) x[i][t] = xn[i][t];
+    }
 }
 
+// Up to 256 channels the kernels are compiled for two wavefronts per SIMD;
+// 512 channels keep the full register file (they would spill otherwise).
+template <int CMAX, int KT, bool VLDS, bool ELDS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_proj_f32_mfma(MArgs a) {
+    proj_f32_body<CMAX, KT, VLDS, ELDS>(a);
+}
+template <int CMAX, int KT, bool VLDS, bool ELDS>
+__global__ __launch_bounds__(256) void k_proj_f32_mfma_wide(MArgs a) {
+    proj_f32_body<CMAX, KT, VLDS, ELDS>(a);
+}
+template <int CMAX, int KT, bool VLDS, bool ELDS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_proj_bf16_mfma(MArgs a) {
+    proj_bf16_body<CMAX, KT, VLDS, ELDS>(a);
+}
+template <int CMAX, int KT, bool VLDS, bool ELDS>
+__global__ __launch_bounds__(256) void k_proj_bf16_mfma_wide(MArgs a) {
+    proj_bf16_body<CMAX, KT, VLDS, ELDS>(a);
+}
 
+constexpr size_t LDS_MAX = 160 * 1024;
+constexpr size_t LDS_TWO_BLOCKS = 80 * 1024;
+
+// Launches a persistent grid: as many blocks as fit on the device (at most
+// two per compute unit, the register limit), never more than there are tiles.
 template <class K>
 hipError_t go(K kern, const MArgs& a, size_t lds, hipStream_t st) {
-    const int blocks = std::max(1, std::min(a.ntiles, 4096));
-    if (lds > 65536) return hipErrorInvalidValue;
+    static int ncu = 0;
+    if (!ncu) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess || ncu < 1) return e != hipSuccess ? e : hipErrorInvalidValue;
+    }
+    if (lds > LDS_MAX) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const int per_cu = lds <= LDS_TWO_BLOCKS ? 2 : 1;
+    const int blocks = std::max(1, std::min(a.ntiles, ncu * per_cu));
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a);
     return hipGetLastError();
 }
@@ -171,32 +273,41 @@ hipError_t launch_proj_mfma(const ProjLaunch& L, const void* V1, const void* V2,
     MArgs a;
     a.X = L.X; a.C = L.C; a.N = L.N; a.k = L.k; a.B = L.B;
     a.mu = L.mu; a.V1 = V1; a.V2 = V2;
-    a.edges = L.edges; a.lo = L.lo; a.inv_delta = L.inv_delta;
+    a.edges = L.edges; a.lo = L.lo; a.inv_delta = L.inv_delta; a.fastd = L.fastd;
     a.bins = L.bins; a.resid = L.resid;
     a.ntiles = (L.N + 15) / 16;
     const int CM = mfma_cmax(L.C, L.prec), KT = mfma_kt(L.k, L.prec);
     if (!CM || !KT) return hipErrorInvalidValue;
-    const size_t base = (size_t)3 * CM * 4 + (size_t)4 * KT * 4 * 64 * 4;
     const bool bf = L.prec == QFCA_PREC_BF16;
-    const size_t tab = (size_t)2 * CM * KT * 16 * (bf ? 2 : 4);
-    const bool vl = base + tab <= 65536;
-    const size_t lds = base + (vl ? tab : 0);
-#define QFCA_F32_CASE(CMV, KTV)                                                       \
-    if (!bf && CM == CMV && KT == KTV)                                                 \
-        return vl ? go(k_proj_f32_mfma<CMV, KTV, true>, a, lds, st)                    \
-                  : go(k_proj_f32_mfma<CMV, KTV, false>, a, lds, st);
-#define QFCA_BF_CASE(CMV, KTV)                                                        \
-    if (bf && CM == CMV && KT == KTV)                                                  \
-        return vl ? go(k_proj_bf16_mfma<CMV, KTV, true>, a, lds, st)                   \
-                  : go(k_proj_bf16_mfma<CMV, KTV, false>, a, lds, st);
+    const int elt = bf ? 2 : 4;
+    // tables in LDS when they fit; the edges are read through the cache
+    // (bin_margin needs them only for values next to an edge)
+    const bool vl = proj_lds(CM, KT, elt, true, false, L.C, L.B).total <= LDS_MAX;
+    const bool el = false;
+    (void)el;
+    const size_t lds = proj_lds(CM, KT, elt, vl, el, L.C, L.B).total;
+#define QFCA_PJ(KERN, CMV, KTV)                                                          \
+    {                                                                                    \
+        if (vl) return go(KERN<CMV, KTV, true, false>, a, lds, st);                      \
+        return go(KERN<CMV, KTV, false, false>, a, lds, st);                             \
+    }
+#define QFCA_F32_CASE(CMV, KTV) if (!bf && CM == CMV && KT == KTV) QFCA_PJ(k_proj_f32_mfma, CMV, KTV)
+#define QFCA_BF_CASE(CMV, KTV) if (bf && CM == CMV && KT == KTV) QFCA_PJ(k_proj_bf16_mfma, CMV, KTV)
 #define QFCA_F32_CM(CMV) QFCA_F32_CASE(CMV, 1) QFCA_F32_CASE(CMV, 2) QFCA_F32_CASE(CMV, 4)
 #define QFCA_BF_CM(CMV) QFCA_BF_CASE(CMV, 2) QFCA_BF_CASE(CMV, 4)
-    QFCA_F32_CM(64) QFCA_F32_CM(128) QFCA_F32_CM(256) QFCA_F32_CM(512)
-    QFCA_BF_CM(128) QFCA_BF_CM(256) QFCA_BF_CM(512)
+#define QFCA_F32W_CASE(CMV, KTV) if (!bf && CM == CMV && KT == KTV) QFCA_PJ(k_proj_f32_mfma_wide, CMV, KTV)
+#define QFCA_BFW_CASE(CMV, KTV) if (bf && CM == CMV && KT == KTV) QFCA_PJ(k_proj_bf16_mfma_wide, CMV, KTV)
+    QFCA_F32_CM(64) QFCA_F32_CM(128) QFCA_F32_CM(256)
+    QFCA_F32W_CASE(512, 1) QFCA_F32W_CASE(512, 2) QFCA_F32W_CASE(512, 4)
+    QFCA_BF_CM(128) QFCA_BF_CM(256)
+    QFCA_BFW_CASE(512, 2) QFCA_BFW_CASE(512, 4)
+#undef QFCA_BFW_CASE
+#undef QFCA_F32W_CASE
 #undef QFCA_BF_CM
 #undef QFCA_F32_CM
 #undef QFCA_BF_CASE
 #undef QFCA_F32_CASE
+#undef QFCA_PJ
     return hipErrorInvalidValue;
 }
 

@@ -21,9 +21,35 @@ typedef __attribute__((address_space(3))) const char* lds_cptr;
 typedef __attribute__((address_space(3))) const int* lds_iptr;
 typedef __attribute__((address_space(3))) const float* lds_fptr;
 
+// Orders one wavefront's LDS accesses before it against those after it.  A
+// score tile's LDS region is private to its wavefront, and the LDS performs
+// the operations of one wavefront in program order, so a wavefront-scope
+// fence (which keeps the compiler from moving accesses across it) is all
+// the synchronisation the tile needs.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Block barrier for data exchanged through LDS only: this wavefront's LDS
+// operations complete (lgkmcnt 0), then s_barrier.  Unlike __syncthreads it
+// does not wait for outstanding global loads, so a prefetch stays in flight
+// across it.  The signal fences keep the compiler from moving memory
+// accesses across the barrier.
+__device__ __forceinline__ void block_sync_lds() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt 63, expcnt 7, lgkmcnt 0
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 __device__ __forceinline__ int lds_addr(const void* p) { return (int)(uintptr_t)(lds_cptr)(const char*)p; }
 __device__ __forceinline__ int lds_load_i(int addr) { return *(lds_iptr)(uintptr_t)addr; }
 __device__ __forceinline__ float lds_load_f(int addr) { return *(lds_fptr)(uintptr_t)addr; }
+__device__ __forceinline__ void lds_store_f(int addr, float v) {
+    *(__attribute__((address_space(3))) float*)(uintptr_t)addr = v;
+}
 
 
 // Same computation as k_score with the window side T fixed at compile time,
@@ -48,12 +74,13 @@ __device__ __forceinline__ float lds_load_f(int addr) { return *(lds_fptr)(uintp
 //      previous block plus the prefix sum of the current one (FP32, in an
 //      order fixed by the block, so deterministic for a given tile); the
 //      sums are written to a small LDS buffer and gathered into the pending
-//      rows' accumulators by all lanes at once, one (channel, column, pending
-//      row) triple per lane.
+//      rows' accumulators by all lanes at once, one (channel, pending row,
+//      column) triple per lane.
 template <int T>
 struct BLayout {
     static constexpr int r = T / 2, m = T * T, T1 = T + 1, TP = (T + 3) & ~3;
     static constexpr int PSI = m + 2;  // psi4 entries per channel (t = 0 .. m + 1)
+    static constexpr int HS = T + 2;   // odd row stride of the horizontal-sum buffer [64][HS]
     // block-shared 1/(4P) table, P = 0 .. m, at the start of the block's LDS
     static constexpr size_t RCP_BYTES = ((size_t)(m + 1) * 4 + 15) & ~(size_t)15;
     int nblk, rowb, vs4;
@@ -67,7 +94,7 @@ struct BLayout {
         vc = off;   off += align16((size_t)64 * vs4 * 4);
         ring = off; off += align16((size_t)T1 * S * rowb);
         acc = off;  off += align16((size_t)T * S * Ws * 4 + 64 * 4);
-        hrow = off; off += align16((size_t)T * 64 * 4);
+        hrow = off; off += align16((size_t)64 * HS * 4);
         psi = off;  off += align16((size_t)S * PSI * 4);
         total = off;
     }
@@ -82,13 +109,13 @@ __device__ __forceinline__ void fill_rcp4(float* rcp4, const float* rcp, int tid
 // One (strip bx, band by, channel group bz) tile, run by one wavefront whose
 // lanes are `lane`, with its private LDS region `smem` (BLayout) and the
 // block-shared table rcp4 (fill_rcp4, visible to the wave before the call).
-// Every wavefront of a block must run a tile of the same geometry (the
-// barriers are block-wide).
+// The tile synchronises only its own wavefront, so the wavefronts of a block
+// may run tiles of different geometry.
 template <int T>
 __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int bz, int lane,
                                            unsigned char* smem, const float* rcp4) {
     using BL = BLayout<T>;
-    constexpr int r = BL::r, m = BL::m, T1 = BL::T1, TP = BL::TP, PSI = BL::PSI;
+    constexpr int r = BL::r, m = BL::m, T1 = BL::T1, TP = BL::TP, PSI = BL::PSI, HS = BL::HS;
     const int Bp = a.Bp, S = a.S, H = a.H, W = a.W, Ws = a.Ws;
     const int s = lane / Bp;
     const int sa = s < S ? s : S - 1;
@@ -114,7 +141,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     uint8_t* ring = smem + L.ring;               // [T1][S][rowb]
     float* acc = (float*)(smem + L.acc);         // [T][S][Ws] + 64 trash slots
     float* trash = acc + T * S * Ws;
-    float* hrow = (float*)(smem + L.hrow);       // [T][64]
+    float* hrow = (float*)(smem + L.hrow);       // [64 lanes][HS]: the block's T window sums per lane
     int* psi = (int*)(smem + L.psi);             // [S][PSI]: 4 Psi_c(t)
 
     // psi4[t] = 4 Psi(t) for t <= m, and 4 Psi(m + 1) = 4 (Psi(m) + sigma(m))
@@ -149,7 +176,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     const bool w1ok = cval && (j < a.B - 1);
     const bool want_w1 = a.w1chan != nullptr;
     constexpr float inv_m = 1.0f / (float)m;
-    __syncthreads();
+    wave_sync();
 
     // bin column q sits at byte (q / T) * TP + q % T of a row
     auto load_row = [&](int yy) {
@@ -186,6 +213,10 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     // gather work items of a block: item it*64+lane -> (channel slot, column k, pending row t)
     constexpr int SMAX = (T <= 9) ? 4 : 2;  // channels per wavefront the gather budget covers
     constexpr int NIT = (T * T * SMAX + 63) / 64;
+    // read the gather's operands ahead of each block where the extra
+    // registers leave the occupancy unchanged (T = 13 and T >= 17 would lose
+    // a wavefront per SIMD)
+    constexpr bool GATHER_AHEAD = (T <= 11) || (T == 15);
     const int nit = (S * T * T + 63) / 64;
 
     const int ys = max(0, y0 - r);
@@ -194,22 +225,24 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     const int hi_add = min(H, ys + r);
     for (int yy = lo_add; yy < hi_add; ++yy) {
         load_row(yy);
-        __syncthreads();
+        wave_sync();
         update_vc(yy, yy, true, false);
-        __syncthreads();
+        wave_sync();
     }
 
     for (int y = ys; y < yend; ++y) {
         const bool add = (y + r) < H;
         const bool rem = (y - r - 1) >= lo_add;
         if (add) load_row(y + r);
-        __syncthreads();
+        wave_sync();
         update_vc(y + r, y - r - 1, add, rem);
         const int ny = min(H - 1, y + r) - max(0, y - r) + 1;
         const bool row_full = (ny == T);
         const bool own_row = (y >= y0) && (y < ye);
-        // gather items of this row: item it*64+lane = (channel slot, step k,
-        // pending row t); their LDS offsets do not change along the row
+        // gather items of this row: item it*64+lane = (channel slot, pending
+        // row t, step k), k fastest, so that neighbouring lanes read
+        // neighbouring bin bytes of one ring row and neighbouring
+        // accumulators; their LDS offsets do not change along the row
         // packed: w0 = ring offset | hrow offset << 16,
         //         w1 = (acc offset + 64) | k << 16 | ok << 31
         uint32_t g_w0[NIT], g_w1[NIT];
@@ -218,13 +251,13 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
             const int idx = it * 64 + lane;
             const int ss = idx / (T * T);
             const int rem2 = idx - ss * (T * T);
-            const int k = rem2 / T, t = rem2 - k * T;
+            const int t = rem2 / T, k = rem2 - t * T;
             const int yo = y - r + t;
             const bool ok = (it < nit) && (ss < S) && (cbase + ss < a.C) && (yo >= y0) && (yo < ye);
             const int ssc = (ss < S) ? ss : 0;
             const int yoc = ok ? yo : y0;
             const uint32_t ro = (uint32_t)((yoc % T1) * S * rowb + ssc * rowb + k);
-            const uint32_t ho = (uint32_t)(k * 64 + ssc * Bp);
+            const uint32_t ho = (uint32_t)(ssc * Bp * HS + k);
             const uint32_t ao = (uint32_t)(((yoc % T) * S + ssc) * Ws + k - 2 * r + 64);
             g_w0[it] = ro | (ho << 16);
             g_w1[it] = ao | ((uint32_t)k << 16) | (ok ? 0x80000000u : 0u);
@@ -244,6 +277,27 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
             const int i0 = blk * T;
             const int p0 = x0 - r + i0;  // patch column of the block's first step
             const bool full = row_full && (i0 + T <= np) && (p0 >= r) && (p0 + T - 1 <= W - 1 - r);
+            // 0. the gather's bin bytes and accumulators, read ahead: neither
+            //    is written during the block (the ring rows are fixed within a
+            //    row, and the accumulator columns of different blocks are
+            //    disjoint), so their latency hides behind steps 1 and 2.
+            //    The output column of step k is o = i0 + k - 2r, whose bin
+            //    column i0 + k sits at byte blk*TP + k.
+            const bool gat = (i0 + T - 1 >= 2 * r);
+            int gbin[NIT], gdst[NIT];
+            float gacc[NIT];
+            if (GATHER_AHEAD && gat) {
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const uint32_t w0 = g_w0[it], w1 = g_w1[it];
+                    const int xo = i0 + (int)((w1 >> 16) & 0x7FFFu) - 2 * r;
+                    const bool ok = (w1 >> 31) && (xo >= 0) && (xo < ws);
+                    const float* dst = ok ? (acc + (int)(w1 & 0xFFFFu) - 64 + i0) : (trash + lane);
+                    gbin[it] = ring[(w0 & 0xFFFFu) + blk * TP];
+                    gdst[it] = lds_addr(dst);
+                    gacc[it] = *dst;
+                }
+            }
             // 1. counts entering and leaving the window, running cumulative counts
             int cpv[T], cmv[T];
             const uint8_t* vb = vcl + blk * TP;
@@ -332,7 +386,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
 #pragma unroll
                 for (int k = 0; k < T; ++k) {
                     pre += ev[k];
-                    hrow[k * 64 + lane] = (k < T - 1) ? suf[k + 1] + pre : pre;
+                    hrow[lane * HS + k] = (k < T - 1) ? suf[k + 1] + pre : pre;
                 }
                 float sf = 0.f;
 #pragma unroll
@@ -341,23 +395,28 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                     suf[k] = sf;
                 }
             }
-            __syncthreads();
+            wave_sync();
             // 3. gather the pixel's own bin into the accumulators of the T
-            //    pending output rows; the output column of step k is
-            //    o = i0 + k - 2r, whose bin column i0 + k sits at byte blk*TP + k
-            if (i0 + T - 1 >= 2 * r) {
+            //    pending output rows
+            if (GATHER_AHEAD && gat) {
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const float h = hrow[(g_w0[it] >> 16) + (gbin[it] & (Bp - 1)) * HS];
+                    lds_store_f(gdst[it], gacc[it] + h);
+                }
+            } else if (gat) {
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
                     const uint32_t w0 = g_w0[it], w1 = g_w1[it];
                     const int xo = i0 + (int)((w1 >> 16) & 0x7FFFu) - 2 * r;
                     const bool ok = (w1 >> 31) && (xo >= 0) && (xo < ws);
                     const int b = ring[(w0 & 0xFFFFu) + blk * TP];
-                    const float h = hrow[(w0 >> 16) + (b & (Bp - 1))];
+                    const float h = hrow[(w0 >> 16) + (b & (Bp - 1)) * HS];
                     float* dst = ok ? (acc + (int)(w1 & 0xFFFFu) - 64 + i0) : (trash + lane);
                     *dst += h;
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
         int yo_lo = y - r, yo_hi = (y < H - 1) ? y - r : H - 1;
         yo_lo = max(yo_lo, y0);
@@ -377,7 +436,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                 *ap = 0.f;
             }
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -395,18 +454,118 @@ __device__ __forceinline__ int bin_of_m(float rr, const float* __restrict__ e, f
     return b;
 }
 
+// bin = #{m : rr >= e[m]} (B >= 2): the arithmetic guess from (rr - lo) / delta
+// is checked against its two neighbouring edges (read together); only when
+// that moves it is the search continued edge by edge.
+__device__ __forceinline__ int bin_fast(float rr, const float* __restrict__ e, float lo, float idl, int B) {
+    if (idl == 0.f) return 0;
+    int b = (int)floorf((rr - lo) * idl);
+    b = b < 0 ? 0 : (b > B - 1 ? B - 1 : b);
+    const float el = e[b > 0 ? b - 1 : 0];
+    const float eh = e[b < B - 1 ? b : B - 2];
+    const int b1 = b - ((b > 0 && rr < el) ? 1 : 0) + ((b < B - 1 && rr >= eh) ? 1 : 0);
+    if (b1 != b) {
+        b = b1;
+        while (b > 0 && rr < e[b - 1]) --b;
+        while (b < B - 1 && rr >= e[b]) ++b;
+    }
+    return b;
+}
+
+// bin = #{m : rr >= e[m]} (B >= 2).  t = (rr - lo) * idl decides on its own
+// when it lies farther than the channel's margin dl from every integer (dl
+// bounds the stored edges' distance from the grid lo + m delta plus the
+// FP32 rounding of t); otherwise, and for channels whose margin is one half
+// or more, the edges around floor(t) are consulted.
+__device__ __forceinline__ int bin_margin(float rr, const float* __restrict__ e, float lo, float idl, float dl,
+                                          int B) {
+    if (idl == 0.f) return 0;
+    if (dl < 0.5f) {
+        const float t = (rr - lo) * idl;
+        if (t < 0.f) return 0;
+        const float top = (float)(B - 1);
+        if (t >= top + dl) return B - 1;
+        if (t < top) {  // NaN falls through to the search
+            const float fl = floorf(t);
+            const float f = t - fl;
+            const int b0 = (int)fl;
+            if ((b0 == 0 || f >= dl) && f <= 1.f - dl) return b0;
+        }
+    }
+    return bin_fast(rr, e, lo, idl, B);
+}
+
+// edges: the [C][B-1] edge table, in LDS or global memory.  sfd: the
+// per-channel margins of bin_margin (LDS or global).  stg: the
+// block's bin staging area [CMAX][16] in LDS (the caller writes it out), or
+// nullptr to store each bin directly.
 __device__ __forceinline__ void emit(const MArgs& a, int c, int px, float r, const float* slo,
-                                     const float* sid) {
+                                     const float* sid, const float* sfd, const float* edges, uint8_t* stg) {
     if (a.resid) a.resid[(size_t)c * a.N + px] = r;
-    if (a.bins)
-        a.bins[(size_t)c * a.N + px] =
-            (uint8_t)bin_of_m(r, a.edges + (size_t)c * (a.B - 1), slo[c], sid[c], a.B);
+    if (a.bins) {
+        const uint8_t b = a.B > 1
+                              ? (uint8_t)bin_margin(r, edges + (size_t)c * (a.B - 1), slo[c], sid[c], sfd[c], a.B)
+                              : (uint8_t)0;
+        if (stg)
+            stg[c * 16 + (px & 15)] = b;
+        else
+            a.bins[(size_t)c * a.N + px] = b;
+    }
+}
+
+// Writes a block's staged bins of one 16-pixel tile: one 16-byte channel row
+// per thread (byte by byte for a ragged last tile or a width that is not a
+// multiple of 16).  Called by all threads of the block after a barrier.
+__device__ __forceinline__ void proj_store_bins(const MArgs& a, int tile, int CMAX, const uint8_t* stg) {
+    const int p0 = tile * 16;
+    const bool whole = (p0 + 16 <= a.N) && ((a.N & 15) == 0);
+    for (int c = threadIdx.x; c < CMAX && c < a.C; c += blockDim.x) {
+        uint8_t* dst = a.bins + (size_t)c * a.N + p0;
+        if (whole) {
+            *(uint4*)dst = *(const uint4*)(stg + c * 16);
+        } else {
+            for (int q = 0; q < 16 && p0 + q < a.N; ++q) dst[q] = stg[c * 16 + q];
+        }
+    }
+}
+
+// Features of one 16-pixel tile for wave w: the FP32 tile's GEMM1 B operands
+// (channel 4 s + g, s = w NSW + i, pixel n) and the BF16 tile's (channels
+// 32 s + 8 g + t).  Loaded separately so that a caller can prefetch them.
+template <int CMAX>
+__device__ __forceinline__ void proj_load_f32(const MArgs& a, int tile, int w, int lane, float (&x)[CMAX / 16]) {
+    constexpr int NSW = CMAX / 16;
+    const int g = lane >> 4, n = lane & 15;
+    const int px = tile * 16 + n;
+    const bool pxok = px < a.N;
+#pragma unroll
+    for (int i = 0; i < NSW; ++i) {
+        const int c = 4 * (w * NSW + i) + g;
+        x[i] = (pxok && c < a.C) ? a.X[(size_t)c * a.N + px] : 0.f;
+    }
+}
+
+template <int CMAX>
+__device__ __forceinline__ void proj_load_bf16(const MArgs& a, int tile, int w, int lane,
+                                               float (&x)[CMAX / 128][8]) {
+    constexpr int NSW = CMAX / 128;
+    const int g = lane >> 4, n = lane & 15;
+    const int px = tile * 16 + n;
+    const bool pxok = px < a.N;
+#pragma unroll
+    for (int i = 0; i < NSW; ++i)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int c = 32 * (w * NSW + i) + 8 * g + t;
+            x[i][t] = (pxok && c < a.C) ? a.X[(size_t)c * a.N + px] : 0.f;
+        }
 }
 
 template <int CMAX, int KT>
 __device__ __forceinline__ void proj_tile_f32(const MArgs& a, int tile, int w, int lane,
         const float* __restrict__ V1, const float* __restrict__ V2, const float* smu, const float* slo,
-        const float* sid, float* zp) {
+        const float* sid, const float* sfd, float* zp, const float (&x)[CMAX / 16], const float* edges,
+        uint8_t* stg) {
     constexpr int NSW = CMAX / 16;
     constexpr int NTW = CMAX / 64;
     constexpr int NU = 4 * KT;
@@ -421,8 +580,7 @@ __device__ __forceinline__ void proj_tile_f32(const MArgs& a, int tile, int w, i
     for (int i = 0; i < NSW; ++i) {
         const int s = w * NSW + i;
         const int c = 4 * s + g;
-        const float x = (pxok && c < a.C) ? a.X[(size_t)c * a.N + px] : 0.f;
-        d[i] = (c < a.C) ? x - smu[c] : 0.f;
+        d[i] = (c < a.C) ? x[i] - smu[c] : 0.f;
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
             z[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(V1[((s * KT + kt) * 4 + g) * 16 + n], d[i],
@@ -433,7 +591,7 @@ __device__ __forceinline__ void proj_tile_f32(const MArgs& a, int tile, int w, i
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) zp[((w * KT + kt) * 4 + v) * 64 + lane] = z[kt][v];
-    __syncthreads();
+    block_sync_lds();
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
@@ -444,7 +602,7 @@ __device__ __forceinline__ void proj_tile_f32(const MArgs& a, int tile, int w, i
             acc += zp[((3 * KT + kt) * 4 + v) * 64 + lane];
             z[kt][v] = acc;
         }
-    __syncthreads();
+    block_sync_lds();
 #pragma unroll
     for (int i = 0; i < NTW; ++i) {
         const int t = w * NTW + i;
@@ -457,7 +615,7 @@ __device__ __forceinline__ void proj_tile_f32(const MArgs& a, int tile, int w, i
         for (int v = 0; v < 4; ++v) {
             const int c = 16 * t + 4 * v + g;
             const float r = d[4 * i + v] - acc[v];
-            if (pxok && c < a.C) emit(a, c, px, r, slo, sid);
+            if (pxok && c < a.C) emit(a, c, px, r, slo, sid, sfd, edges, stg);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -466,7 +624,8 @@ __device__ __forceinline__ void proj_tile_f32(const MArgs& a, int tile, int w, i
 template <int CMAX, int KT>
 __device__ __forceinline__ void proj_tile_bf16(const MArgs& a, int tile, int w, int lane,
         const bf16x8* __restrict__ V1, const bf16x8* __restrict__ V2, const float* smu, const float* slo,
-        const float* sid, float* zp) {
+        const float* sid, const float* sfd, float* zp, const float (&x)[CMAX / 128][8], const float* edges,
+        uint8_t* stg) {
     constexpr int NSW = CMAX / 128;
     constexpr int NU = KT / 2;
     const int g = lane >> 4, n = lane & 15;
@@ -483,8 +642,7 @@ __device__ __forceinline__ void proj_tile_bf16(const MArgs& a, int tile, int w, 
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int c = 32 * s + 8 * g + t;
-            const float x = (pxok && c < a.C) ? a.X[(size_t)c * a.N + px] : 0.f;
-            d[i][t] = (c < a.C) ? x - smu[c] : 0.f;
+            d[i][t] = (c < a.C) ? x[i][t] - smu[c] : 0.f;
             bv[t] = (__bf16)d[i][t];
         }
 #pragma unroll
@@ -497,7 +655,7 @@ __device__ __forceinline__ void proj_tile_bf16(const MArgs& a, int tile, int w, 
     for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) zp[((w * KT + kt) * 4 + v) * 64 + lane] = z[kt][v];
-    __syncthreads();
+    block_sync_lds();
     bf16x8 zb[NU];
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt)
@@ -509,7 +667,7 @@ __device__ __forceinline__ void proj_tile_bf16(const MArgs& a, int tile, int w, 
             acc += zp[((3 * KT + kt) * 4 + v) * 64 + lane];
             zb[kt >> 1][4 * (kt & 1) + v] = (__bf16)acc;
         }
-    __syncthreads();
+    block_sync_lds();
 #pragma unroll
     for (int i = 0; i < NSW; ++i) {
         const int s = w * NSW + i;
@@ -525,7 +683,7 @@ __device__ __forceinline__ void proj_tile_bf16(const MArgs& a, int tile, int w, 
             for (int v = 0; v < 4; ++v) {
                 const int c = 32 * s + 8 * g + 4 * h + v;
                 const float r = d[i][4 * h + v] - acc[v];
-                if (pxok && c < a.C) emit(a, c, px, r, slo, sid);
+                if (pxok && c < a.C) emit(a, c, px, r, slo, sid, sfd, edges, stg);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
