@@ -770,6 +770,10 @@ ScoreTile batch_tile(qfca_ctx ctx, const qfca_params& p) {
     t.variant = 1;
     t.S = std::min(std::min(t.S, 64 / Bp), score_block_max_S(p.T));
     if (t.S < 1) t.S = 1;
+    // four wavefront regions and the shared reciprocal table must fit in LDS:
+    // narrow the strip one window width at a time (keeping whole blocks)
+    while (score_rcp_bytes(p.T) + 4 * align16c(batch_wave_lds(p.T, t.S, t.Ws)) > 160 * 1024 && t.Ws > p.T + 1)
+        t.Ws -= p.T;
     return t;
 }
 
