@@ -23,6 +23,11 @@ HIPCC_FLAGS = [
 ]
 
 
+# Sources with host code only, compiled by the host C++ compiler.
+HOST_ONLY = {"qfca_eig.cpp"}
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall"]
+
+
 def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) +
                   glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
@@ -30,7 +35,11 @@ def sources():
 
 def _compile(hipcc, src, verbose):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+    if os.path.basename(src) in HOST_ONLY:
+        cmd = [os.environ.get("CXX", "g++"), *HOST_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src,
+               "-o", obj]
+    else:
+        cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

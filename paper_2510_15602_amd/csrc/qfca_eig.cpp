@@ -3,16 +3,20 @@
 // so it runs on the host: Householder reduction to tridiagonal form, then the
 // implicit QL iteration with shifts (Bowdler, Martin, Reinsch and Wilkinson,
 // 1968) applied to the accumulated orthogonal transform.
+//
+// Host code only, compiled as plain C++ (no device pass).
 #include <math.h>
+#include <stdint.h>
 #include <string.h>
 
 #include <algorithm>
 #include <numeric>
 #include <vector>
 
-#include "qfca_internal.h"
-
 namespace qfca {
+
+// Declared for the library in qfca_internal.h.
+int sym_eig(double* A, int n, double* evals, double* vecs);
 
 namespace {
 
@@ -76,9 +80,11 @@ void householder_tridiag(double* A, int n, double* d, double* e, double* Q) {
     }
 }
 
-// Implicit QL on the tridiagonal (d, e); Z (row-major) accumulates the
-// rotations.  Returns 0 on success, -1 if an eigenvalue fails to converge.
-int tridiag_ql(double* d, double* e, int n, double* Z) {
+// Implicit QL on the tridiagonal (d, e); ZT accumulates the rotations, held
+// transposed (row i of ZT is column i of the transform) so that each
+// rotation updates two contiguous rows.  Returns 0 on success, -1 if an
+// eigenvalue fails to converge.
+int tridiag_ql(double* d, double* e, int n, double* ZT) {
     const double eps = 2.220446049250313e-16;
     for (int l = 0; l < n; ++l) {
         int iter = 0;
@@ -114,11 +120,12 @@ int tridiag_ql(double* d, double* e, int n, double* Z) {
                 p = s * rr;
                 d[i + 1] = g + p;
                 g = c * rr - b;
+                double* __restrict__ zi = ZT + (size_t)i * n;
+                double* __restrict__ zj = ZT + (size_t)(i + 1) * n;
                 for (int k = 0; k < n; ++k) {
-                    double* zr = Z + (size_t)k * n;
-                    const double t = zr[i + 1];
-                    zr[i + 1] = s * zr[i] + c * t;
-                    zr[i] = c * zr[i] - s * t;
+                    const double t = zj[k];
+                    zj[k] = s * zi[k] + c * t;
+                    zi[k] = c * zi[k] - s * t;
                 }
             }
             if (early) continue;
@@ -136,7 +143,10 @@ int sym_eig(double* A, int n, double* evals, double* vecs) {
     if (n <= 0) return -1;
     std::vector<double> d(n), e(n), Q((size_t)n * n);
     householder_tridiag(A, n, d.data(), e.data(), Q.data());
-    if (tridiag_ql(d.data(), e.data(), n, Q.data()) != 0) return -1;
+    std::vector<double> QT((size_t)n * n);
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) QT[(size_t)c * n + r] = Q[(size_t)r * n + c];
+    if (tridiag_ql(d.data(), e.data(), n, QT.data()) != 0) return -1;
     std::vector<int> idx(n);
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] > d[b]; });
@@ -144,11 +154,12 @@ int sym_eig(double* A, int n, double* evals, double* vecs) {
         const int col = idx[j];
         evals[j] = d[col];
         // sign convention: the entry of largest magnitude is positive
+        const double* q = QT.data() + (size_t)col * n;  // eigenvector `col`, contiguous
         int arg = 0;
         for (int rI = 1; rI < n; ++rI)
-            if (fabs(Q[(size_t)rI * n + col]) > fabs(Q[(size_t)arg * n + col])) arg = rI;
-        const double sg = Q[(size_t)arg * n + col] < 0.0 ? -1.0 : 1.0;
-        for (int rI = 0; rI < n; ++rI) vecs[(size_t)rI * n + j] = sg * Q[(size_t)rI * n + col];
+            if (fabs(q[rI]) > fabs(q[arg])) arg = rI;
+        const double sg = q[arg] < 0.0 ? -1.0 : 1.0;
+        for (int rI = 0; rI < n; ++rI) vecs[(size_t)rI * n + j] = sg * q[rI];
     }
     return 0;
 }
