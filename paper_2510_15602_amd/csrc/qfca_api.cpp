@@ -349,6 +349,8 @@ ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
     // block walk: strips of n T - 2r columns fill whole blocks of T patch columns
     t.Ws = t.variant ? std::max(8, 4 * T - (T - 1)) : 64;
     t.Hb = 128;
+    // prefer at most 64 KiB per wavefront (occupancy); very large windows may
+    // use up to the 160 KiB of a compute unit
     while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.S > 1) t.S >>= 1;
     while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.Ws > 8) t.Ws >>= 1;
     (void)C;
@@ -737,7 +739,7 @@ qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int3
         if (L.tile.S * m->Bp > 64) return fail(QFCA_E_UNSUPPORTED, "S * lanes per channel exceeds 64");
         if (L.tile.variant == 1 && (!score_has_block_kernel(m->p.T) || L.tile.S > score_block_max_S(m->p.T)))
             L.tile.variant = 0;
-        if (score_lds_bytes(m->p.T, m->Bp, L.tile.S, L.tile.Ws, L.tile.variant) > 65536)
+        if (score_lds_bytes(m->p.T, m->Bp, L.tile.S, L.tile.Ws, L.tile.variant) > 160 * 1024)
             return fail(QFCA_E_UNSUPPORTED, "tile does not fit in LDS");
     } else {
         L.tile = choose_tile(ctx, C, H, W, m->p.T, m->p.B, m->Bp);

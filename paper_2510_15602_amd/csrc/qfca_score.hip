@@ -359,15 +359,26 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     a.achan = L.achan; a.w1chan = L.w1chan;
     if (a.S < 1 || a.S * a.Bp > 64) return hipErrorInvalidValue;
     const size_t lds = score_lds_bytes(a.T, a.Bp, a.S, a.Ws, variant);
-    if (lds > 65536) return hipErrorInvalidValue;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     dim3 grid((L.W + a.Ws - 1) / a.Ws, (L.H + a.Hb - 1) / a.Hb, (L.C + a.S - 1) / a.S);
+    // more than 64 KiB of dynamic LDS has to be allowed per kernel
+    auto allow = [&](const void* k) -> hipError_t {
+        return lds > 65536 ? hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                           : hipSuccess;
+    };
     if (variant == 0) {
+        hipError_t e = allow((const void*)k_score);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_score, grid, dim3(64), lds, st, a);
         return hipGetLastError();
     }
     switch (a.T) {
-#define QFCA_T_CASE(TT) \
-        case TT: hipLaunchKernelGGL(k_score_t<TT>, grid, dim3(64), lds, st, a); break;
+#define QFCA_T_CASE(TT)                                                          \
+        case TT: {                                                               \
+            hipError_t e = allow((const void*)k_score_t<TT>);                    \
+            if (e != hipSuccess) return e;                                       \
+            hipLaunchKernelGGL(k_score_t<TT>, grid, dim3(64), lds, st, a);       \
+        } break;
         QFCA_T_CASE(3) QFCA_T_CASE(5) QFCA_T_CASE(7) QFCA_T_CASE(9) QFCA_T_CASE(11)
         QFCA_T_CASE(13) QFCA_T_CASE(15) QFCA_T_CASE(17) QFCA_T_CASE(19) QFCA_T_CASE(21)
         QFCA_T_CASE(23) QFCA_T_CASE(25) QFCA_T_CASE(27) QFCA_T_CASE(29) QFCA_T_CASE(31)
