@@ -397,6 +397,7 @@ class Server:
         _check(lib().qfca_server_create(int(device), ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
         self._buf = (Completion * 1024)()
+        self._live = {}  # ticket -> (X, score): kept alive until the ticket completes
 
     def submit(self, model: "Model", X, score) -> int:
         """X: [C, H, W] float32 and score: [H, W] float32 on the device; both
@@ -409,6 +410,7 @@ class Server:
             raise ValueError("request shapes do not match")
         t = ctypes.c_uint64()
         _check(lib().qfca_server_submit(self.handle, model.handle, _ptr(X), H, W, _ptr(score), ctypes.byref(t)))
+        self._live[t.value] = (model, X, score)
         return t.value
 
     def poll(self):
@@ -420,6 +422,7 @@ class Server:
             for i in range(n.value):
                 c = self._buf[i]
                 out.append({f: getattr(c, f) for f, _ in Completion._fields_})
+                self._live.pop(c.ticket, None)
             if n.value < len(self._buf):
                 return out
 
@@ -433,8 +436,9 @@ class Server:
 
     def close(self):
         if getattr(self, "handle", None):
-            lib().qfca_server_destroy(self.handle)
+            lib().qfca_server_destroy(self.handle)  # drains first
             self.handle = None
+            self._live.clear()
 
     def __del__(self):
         try:

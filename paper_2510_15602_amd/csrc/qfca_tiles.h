@@ -518,7 +518,7 @@ __device__ __forceinline__ void emit(const MArgs& a, int c, int px, float r, con
 // multiple of 16).  Called by all threads of the block after a barrier.
 __device__ __forceinline__ void proj_store_bins(const MArgs& a, int tile, int CMAX, const uint8_t* stg) {
     const int p0 = tile * 16;
-    const bool whole = (p0 + 16 <= a.N) && ((a.N & 15) == 0);
+    const bool whole = (p0 + 16 <= a.N) && ((a.N & 15) == 0) && (((uintptr_t)a.bins & 15) == 0);
     for (int c = threadIdx.x; c < CMAX && c < a.C; c += blockDim.x) {
         uint8_t* dst = a.bins + (size_t)c * a.N + p0;
         if (whole) {
