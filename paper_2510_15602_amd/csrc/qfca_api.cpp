@@ -353,6 +353,7 @@ ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
     // use up to the 160 KiB of a compute unit
     while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.S > 1) t.S >>= 1;
     while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.Ws > 8) t.Ws >>= 1;
+    if (t.variant == 1 && t.Ws < T) t.variant = 0;  // the block walk needs strips of at least T columns
     (void)C;
     ctx->tiles[key] = t;
     return t;
@@ -737,7 +738,8 @@ qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int3
     if (ctx->tile_override.Ws > 0) {
         L.tile = ctx->tile_override;
         if (L.tile.S * m->Bp > 64) return fail(QFCA_E_UNSUPPORTED, "S * lanes per channel exceeds 64");
-        if (L.tile.variant == 1 && (!score_has_block_kernel(m->p.T) || L.tile.S > score_block_max_S(m->p.T)))
+        if (L.tile.variant == 1 && (!score_has_block_kernel(m->p.T) || L.tile.S > score_block_max_S(m->p.T) ||
+                                    L.tile.Ws < m->p.T))
             L.tile.variant = 0;
         if (score_lds_bytes(m->p.T, m->Bp, L.tile.S, L.tile.Ws, L.tile.variant) > 160 * 1024)
             return fail(QFCA_E_UNSUPPORTED, "tile does not fit in LDS");

@@ -352,7 +352,8 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     a.Ws = L.tile.Ws;
     a.Hb = L.tile.Hb;
     const int variant =
-        (L.tile.variant == 1 && score_has_block_kernel(L.T) && L.tile.S <= score_block_max_S(L.T)) ? 1 : 0;
+        (L.tile.variant == 1 && score_has_block_kernel(L.T) && L.tile.S <= score_block_max_S(L.T) &&
+         L.tile.Ws >= L.T) ? 1 : 0;
     a.WbA = alloc_cols(L.T, a.Ws, variant);
     a.psig = L.tab.psig; a.cRm1 = L.tab.cRm1; a.Dm1 = L.tab.Dm1; a.cRl = L.tab.cRl;
     a.rcp = L.tab.rcp; a.delta = L.tab.delta;

@@ -14,6 +14,12 @@ __device__ __forceinline__ int lane_prev(int v) {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
+// A compile-time boolean passed as a value (selects code paths of a lambda).
+template <bool V>
+struct bconst {
+    static constexpr bool value = V;
+};
+
 // LDS (address space 3) views: loads through these take a 32-bit LDS byte
 // address held in a register, so constant parts of an address fold into the
 // instruction's offset field.
@@ -97,6 +103,12 @@ struct BLayout {
         hrow = off; off += align16((size_t)64 * HS * 4);
         psi = off;  off += align16((size_t)S * PSI * 4);
         total = off;
+        // the gather packs ring and accumulator offsets, one row past their
+        // ring's end included, into 16 bits, and tells accumulator rows apart
+        // only when a strip is at least T columns wide: a layout beyond that
+        // reports a size no LDS limit admits
+        if ((size_t)(T1 + 1) * S * rowb >= 65536 || (size_t)(T + 1) * S * Ws >= 65536 || Ws < T)
+            total = (size_t)1 << 30;
     }
 };
 
@@ -178,16 +190,43 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     constexpr float inv_m = 1.0f / (float)m;
     wave_sync();
 
-    // bin column q sits at byte (q / T) * TP + q % T of a row
+    // bin column q sits at byte (q / T) * TP + q % T of a ring row; a ring
+    // row holds the S channels' rows back to back (nlb bytes).  Bins are
+    // < 64; 0x7F marks columns outside the image or padding (never counted
+    // by the 7-bit comparison below).  When the row fits LRN bytes per lane,
+    // each lane's source offsets (relative to the group's first channel at
+    // the row) are fixed for the tile: s H W + x, or -1 for a marker byte.
+    const int nlb = S * rowb;
+    constexpr int LRN = 4;
+    const bool lfast = (nlb <= 64 * LRN) && ((long long)S * H * W < 0x7FFFFFFFLL);
+    int loff[LRN];
+#pragma unroll
+    for (int i = 0; i < LRN; ++i) {
+        const int t = lane + 64 * i;
+        const int ss = t / rowb, o = t - ss * rowb;
+        const int blk = o / TP, k = o - blk * TP;
+        const int q = blk * T + k;
+        const int cc = cbase + ss, xx = xb0 + q;
+        const bool v = lfast && t < nlb && k < T && cc < a.C && q < Wb && xx >= 0 && xx < W;
+        loff[i] = v ? ss * H * W + xx : -1;
+    }
     auto load_row = [&](int yy) {
-        uint8_t* dst = ring + (size_t)(yy % T1) * S * rowb;
-        for (int t = lane; t < S * rowb; t += 64) {
+        uint8_t* dst = ring + (size_t)(yy % T1) * nlb;
+        if (lfast) {
+            const uint8_t* rowp = a.bins + ((size_t)cbase * H + yy) * W;
+            uint8_t v[LRN];
+#pragma unroll
+            for (int i = 0; i < LRN; ++i) v[i] = (loff[i] >= 0) ? (uint8_t)(rowp[loff[i]] & 0x7F) : (uint8_t)0x7F;
+#pragma unroll
+            for (int i = 0; i < LRN; ++i)
+                if (lane + 64 * i < nlb) dst[lane + 64 * i] = v[i];
+            return;
+        }
+        for (int t = lane; t < nlb; t += 64) {
             const int ss = t / rowb, o = t - ss * rowb;
             const int blk = o / TP, k = o - blk * TP;
             const int q = blk * T + k;
             const int cc = cbase + ss, xx = xb0 + q;
-            // bins are < 64; 0x7F marks columns outside the image or padding
-            // (never counted by the 7-bit comparison below)
             uint8_t v = 0x7F;
             if (k < T && cc < a.C && q < Wb && xx >= 0 && xx < W)
                 v = a.bins[((size_t)cc * H + yy) * W + xx] & 0x7F;
@@ -196,17 +235,19 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     };
     // vc[q] += [bin(row ya, q) <= j] - [bin(row yr, q) <= j], four columns per
     // dword: for 7-bit bytes b and j < 64, 0x80 + j - b never borrows across
-    // bytes and its top bit is set exactly when b <= j.
+    // bytes and its top bit is set exactly when b <= j.  ADD / REM select at
+    // compile time whether a row enters and whether one leaves.
     const uint32_t jhi = ((uint32_t)j * 0x01010101u) | 0x80808080u;
-    auto update_vc = [&](int ya, int yr, bool add, bool rem) {
-        const uint32_t* ra = (const uint32_t*)(ring + (size_t)(ya % T1) * S * rowb + sa * rowb);
-        const uint32_t* rr = (const uint32_t*)(ring + (size_t)((yr + T1) % T1) * S * rowb + sa * rowb);
+    auto update_vc = [&](int ya, int yr, auto addc, auto remc) {
+        constexpr bool ADD = decltype(addc)::value, REM = decltype(remc)::value;
+        const uint32_t* ra = (const uint32_t*)(ring + (size_t)(ya % T1) * nlb + sa * rowb);
+        const uint32_t* rr = (const uint32_t*)(ring + (size_t)((yr + T1) % T1) * nlb + sa * rowb);
         uint32_t* v = vc32 + lane * L.vs4;
-        const uint32_t ma = add ? 0xFFFFFFFFu : 0u, mr = rem ? 0xFFFFFFFFu : 0u;
         for (int d = 0; d < rowb / 4; ++d) {
-            const uint32_t ia = (((jhi - ra[d]) & 0x80808080u) >> 7) & ma;
-            const uint32_t ir = (((jhi - rr[d]) & 0x80808080u) >> 7) & mr;
-            v[d] = v[d] + ia - ir;
+            uint32_t x = v[d];
+            if (ADD) x += ((jhi - ra[d]) & 0x80808080u) >> 7;
+            if (REM) x -= ((jhi - rr[d]) & 0x80808080u) >> 7;
+            v[d] = x;
         }
     };
 
@@ -217,16 +258,51 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     // registers leave the occupancy unchanged (T = 13 and T >= 17 would lose
     // a wavefront per SIMD)
     constexpr bool GATHER_AHEAD = (T <= 11) || (T == 15);
-    const int nit = (S * T * T + 63) / 64;
 
     const int ys = max(0, y0 - r);
     const int yend = min(H, ye + r);
     const int lo_add = max(0, ys - r);
     const int hi_add = min(H, ys + r);
+
+    // Gather items of a row: item it*64+lane = (channel slot ss, pending row
+    // t, step k), k fastest, so that neighbouring lanes read neighbouring
+    // bin bytes of one ring row and neighbouring accumulators.  Pending row
+    // t of image row y is output row yo = y - r + t, whose bins sit in ring
+    // row yo mod T1 and whose sums go to accumulator row yo mod T.  Packed:
+    //   w0 = ring offset (block 0) << 16 | hrow offset
+    //   w1 = (accumulator row + channel offset + k) << 16 | valid << 15 | k
+    // where step k of the block starting at step i0 adds to output column
+    // i0 + k - 2r of that row.
+    // From one image row to the next both offsets move by one row, minus a
+    // whole ring (accumulator) period when they pass its end: the smaller of
+    // the two unsigned candidates, because the other one wraps below zero.
+    // Rows outside the band accumulate too: those above it are cleared once
+    // complete, those below are never output (the accumulator ring of T rows
+    // holds exactly the T pending rows).
+    uint32_t g_w0[NIT], g_w1[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = it * 64 + lane;
+        const int ss = idx / (T * T);
+        const int rem2 = idx - ss * (T * T);
+        const int t = rem2 / T, k = rem2 - t * T;
+        const bool ok = (ss < S) && (cbase + ss < a.C);
+        const int ssc = (ss < S) ? ss : 0;
+        const int yo = ys - r + t;
+        const int rrow = ((yo % T1) + T1) % T1, arow = ((yo % T) + T) % T;
+        const uint32_t ro = (uint32_t)(rrow * nlb + ssc * rowb + k);
+        const uint32_t ho = (uint32_t)(ssc * Bp * HS + k);
+        const uint32_t ao = (uint32_t)((arow * S + ssc) * Ws + k);
+        g_w0[it] = (ro << 16) | ho;
+        g_w1[it] = (ao << 16) | (ok ? 0x8000u : 0u) | (uint32_t)k;
+    }
+    const uint32_t gstep0 = (uint32_t)nlb << 16, gwrap0 = (uint32_t)(T1 * nlb) << 16;
+    const uint32_t gstep1 = (uint32_t)(S * Ws) << 16, gwrap1 = (uint32_t)(T * S * Ws) << 16;
+
     for (int yy = lo_add; yy < hi_add; ++yy) {
         load_row(yy);
         wave_sync();
-        update_vc(yy, yy, true, false);
+        update_vc(yy, yy, bconst<true>(), bconst<false>());
         wave_sync();
     }
 
@@ -235,40 +311,28 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
         const bool rem = (y - r - 1) >= lo_add;
         if (add) load_row(y + r);
         wave_sync();
-        update_vc(y + r, y - r - 1, add, rem);
+        if (add && rem)
+            update_vc(y + r, y - r - 1, bconst<true>(), bconst<true>());
+        else if (add)
+            update_vc(y + r, y - r - 1, bconst<true>(), bconst<false>());
+        else if (rem)
+            update_vc(y + r, y - r - 1, bconst<false>(), bconst<true>());
         const int ny = min(H - 1, y + r) - max(0, y - r) + 1;
         const bool row_full = (ny == T);
         const bool own_row = (y >= y0) && (y < ye);
-        // gather items of this row: item it*64+lane = (channel slot, pending
-        // row t, step k), k fastest, so that neighbouring lanes read
-        // neighbouring bin bytes of one ring row and neighbouring
-        // accumulators; their LDS offsets do not change along the row
-        // packed: w0 = ring offset | hrow offset << 16,
-        //         w1 = (acc offset + 64) | k << 16 | ok << 31
-        uint32_t g_w0[NIT], g_w1[NIT];
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int idx = it * 64 + lane;
-            const int ss = idx / (T * T);
-            const int rem2 = idx - ss * (T * T);
-            const int t = rem2 / T, k = rem2 - t * T;
-            const int yo = y - r + t;
-            const bool ok = (it < nit) && (ss < S) && (cbase + ss < a.C) && (yo >= y0) && (yo < ye);
-            const int ssc = (ss < S) ? ss : 0;
-            const int yoc = ok ? yo : y0;
-            const uint32_t ro = (uint32_t)((yoc % T1) * S * rowb + ssc * rowb + k);
-            const uint32_t ho = (uint32_t)(ssc * Bp * HS + k);
-            const uint32_t ao = (uint32_t)(((yoc % T) * S + ssc) * Ws + k - 2 * r + 64);
-            g_w0[it] = ro | (ho << 16);
-            g_w1[it] = ao | ((uint32_t)k << 16) | (ok ? 0x80000000u : 0u);
-        }
         // Step i walks patch column p = x0 - r + i; its window covers bin
         // columns q in [i, i + 2r].  The count entering at step i is vc[i + 2r]
         // and the one leaving is vc[i - 1].
-        int cpb = 0;
+        // bin columns 0 .. 2r-1 (layout block 0): byte sums of whole dwords
+        uint32_t c0 = 0;
+        {
+            const uint32_t* vw = vc32 + lane * L.vs4;
 #pragma unroll
-        for (int k = 0; k < T - 1; ++k) cpb += (int)vcl[k];  // bin columns 0 .. 2r-1 (layout block 0)
-        cpb = 4 * cpb + bias;
+            for (int d = 0; d < (T - 1) / 4; ++d) c0 = __builtin_amdgcn_sad_u8(vw[d], 0u, c0);
+            if ((T - 1) % 4)
+                c0 = __builtin_amdgcn_sad_u8(vw[(T - 1) / 4] & ((1u << (8 * ((T - 1) % 4))) - 1u), 0u, c0);
+        }
+        int cpb = 4 * (int)c0 + bias;
         int ent0 = 0;  // count that entered at step k = 0 of the previous block
         float suf[T];  // suffix sums of the previous block's errors (suf[k] = sum over k' >= k)
 #pragma unroll
@@ -290,10 +354,10 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
                     const uint32_t w0 = g_w0[it], w1 = g_w1[it];
-                    const int xo = i0 + (int)((w1 >> 16) & 0x7FFFu) - 2 * r;
-                    const bool ok = (w1 >> 31) && (xo >= 0) && (xo < ws);
-                    const float* dst = ok ? (acc + (int)(w1 & 0xFFFFu) - 64 + i0) : (trash + lane);
-                    gbin[it] = ring[(w0 & 0xFFFFu) + blk * TP];
+                    const int xo = i0 + (int)(w1 & 63u) - 2 * r;
+                    const bool ok = (w1 & 0x8000u) && (xo >= 0) && (xo < ws);
+                    const float* dst = ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : (trash + lane);
+                    gbin[it] = ring[(w0 >> 16) + blk * TP];
                     gdst[it] = lds_addr(dst);
                     gacc[it] = *dst;
                 }
@@ -401,22 +465,34 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
             if (GATHER_AHEAD && gat) {
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
-                    const float h = hrow[(g_w0[it] >> 16) + (gbin[it] & (Bp - 1)) * HS];
+                    const float h = hrow[(g_w0[it] & 0xFFFFu) + (gbin[it] & (Bp - 1)) * HS];
                     lds_store_f(gdst[it], gacc[it] + h);
                 }
             } else if (gat) {
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
                     const uint32_t w0 = g_w0[it], w1 = g_w1[it];
-                    const int xo = i0 + (int)((w1 >> 16) & 0x7FFFu) - 2 * r;
-                    const bool ok = (w1 >> 31) && (xo >= 0) && (xo < ws);
-                    const int b = ring[(w0 & 0xFFFFu) + blk * TP];
-                    const float h = hrow[(w0 >> 16) + (b & (Bp - 1)) * HS];
-                    float* dst = ok ? (acc + (int)(w1 & 0xFFFFu) - 64 + i0) : (trash + lane);
+                    const int xo = i0 + (int)(w1 & 63u) - 2 * r;
+                    const bool ok = (w1 & 0x8000u) && (xo >= 0) && (xo < ws);
+                    const int b = ring[(w0 >> 16) + blk * TP];
+                    const float h = hrow[(w0 & 0xFFFFu) + (b & (Bp - 1)) * HS];
+                    float* dst = ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : (trash + lane);
                     *dst += h;
                 }
             }
             wave_sync();
+        }
+        // the pending rows move down by one
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const uint32_t u0 = g_w0[it] + gstep0, u1 = g_w1[it] + gstep1;
+            g_w0[it] = min(u0, u0 - gwrap0);
+            g_w1[it] = min(u1, u1 - gwrap1);
+        }
+        // row y - r is complete: above the band it is only cleared
+        if (y - r < y0) {
+            float* ap = acc + ((((y - r) % T) + T) % T) * S * Ws;
+            for (int t = lane; t < S * Ws; t += 64) ap[t] = 0.f;
         }
         int yo_lo = y - r, yo_hi = (y < H - 1) ? y - r : H - 1;
         yo_lo = max(yo_lo, y0);
