@@ -150,18 +150,15 @@ const void* batch_kernel() {
     else return (const void*)k_batch1<T, CMAX, KT, BF>;
 }
 
-// A(x) = (1/C) sum_c achan[c][x] for every image (grid: x chunks, images).
-__global__ void k_batch_chanmean(const BatchHeader* hdr, const BatchJob* jobs) {
+// A(x) = (1/C) sum_c achan[c][x] for every image (grid: pixel chunks of 128, images).
+__global__ __launch_bounds__(256) void k_batch_chanmean(const BatchHeader* hdr, const BatchJob* jobs) {
+    __shared__ double red[2][8][32][4];
     const int jb = blockIdx.y;
     if (jb >= hdr->n) return;
     const BatchJob& J = jobs[jb];
     const int N = J.sa.H * J.sa.W;
-    const int C = J.sa.C;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int c = 0; c < C; ++c) s += (double)J.sa.achan[(size_t)c * N + i];
-        J.amap[i] = (float)(s / (double)C);
-    }
+    for (int q = blockIdx.x; q * 128 < N; q += gridDim.x)
+        chanmean_chunk(J.sa.achan, nullptr, J.sa.C, N, q, J.amap, nullptr, red);
 }
 
 // Separable Gaussian (radius R <= 16) for every image (grid: tiles, images).

@@ -247,18 +247,13 @@ __global__ __launch_bounds__(64) void k_score_t(KArgs a) {
     score_tile<T>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, smem + BLayout<T>::RCP_BYTES, rcp4);
 }
 
-// A(x) = (1/C) sum_c achan[c][x] in double precision, fixed channel order.
-__global__ void k_chanmean(const float* __restrict__ achan, const float* __restrict__ w1chan,
-                           int C, int N, float* __restrict__ amap, float* __restrict__ w1) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    double s = 0.0, t = 0.0;
-    for (int c = 0; c < C; ++c) {
-        s += (double)achan[(size_t)c * N + i];
-        if (w1chan) t += (double)w1chan[(size_t)c * N + i];
-    }
-    amap[i] = (float)(s / (double)C);
-    if (w1chan) w1[i] = (float)(t / (double)C);
+// A(x) = (1/C) sum_c achan[c][x] in double precision, in a fixed order
+// (eight strided channel slices, then the slices).
+__global__ __launch_bounds__(256) void k_chanmean(const float* __restrict__ achan,
+                                                  const float* __restrict__ w1chan, int C, int N,
+                                                  float* __restrict__ amap, float* __restrict__ w1) {
+    __shared__ double red[2][8][32][4];
+    tiles::chanmean_chunk(achan, w1chan, C, N, blockIdx.x, amap, w1, red);
 }
 
 // Separable Gaussian, radius R, renormalised over in-image taps (the 2-D
@@ -391,7 +386,7 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
 
 hipError_t launch_chanmean(const float* achan, const float* w1chan, int C, int N, float* amap,
                            float* w1, hipStream_t st) {
-    hipLaunchKernelGGL(k_chanmean, dim3((N + 255) / 256), dim3(256), 0, st, achan, w1chan, C, N,
+    hipLaunchKernelGGL(k_chanmean, dim3((N + 127) / 128), dim3(256), 0, st, achan, w1chan, C, N,
                        amap, w1);
     return hipGetLastError();
 }

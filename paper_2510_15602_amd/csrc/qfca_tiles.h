@@ -766,5 +766,67 @@ __device__ __forceinline__ void proj_tile_bf16(const MArgs& a, int tile, int w, 
     }
 }
 
+// Channel mean A(x) = (1/C) sum_c achan[c][x] (and the same for the W1
+// maps when w1chan is given) over the pixel chunk [128 q, 128 q + 128) of a
+// map of N pixels, by a block of 256 threads: thread (g, u) loads pixels
+// 4u .. 4u+3 of the chunk (one 16-byte load when N is a multiple of 4 and
+// the maps are 16-byte aligned) for
+// channels g, g + 8, g + 16, ... and sums them in FP64; the eight slices are
+// then added in the order g = 0 .. 7 through `red`, so the result does not
+// depend on scheduling.
+__device__ __forceinline__ void chanmean_chunk(const float* __restrict__ achan, const float* __restrict__ w1chan,
+                                               int C, int N, int q, float* __restrict__ amap,
+                                               float* __restrict__ w1, double (*red)[8][32][4]) {
+    const int tid = threadIdx.x;
+    const int u = tid & 31, g = tid >> 5;
+    const int i0 = q * 128 + 4 * u;
+    double s[4] = {0.0, 0.0, 0.0, 0.0}, t[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i0 < N) {
+        const bool vec = ((N & 3) == 0) && (((uintptr_t)achan & 15) == 0) && (((uintptr_t)w1chan & 15) == 0);
+        if (vec) {
+#pragma unroll 4
+            for (int c = g; c < C; c += 8) {
+                const float4 v = *(const float4*)(achan + (size_t)c * N + i0);
+                s[0] += (double)v.x; s[1] += (double)v.y; s[2] += (double)v.z; s[3] += (double)v.w;
+                if (w1chan) {
+                    const float4 w = *(const float4*)(w1chan + (size_t)c * N + i0);
+                    t[0] += (double)w.x; t[1] += (double)w.y; t[2] += (double)w.z; t[3] += (double)w.w;
+                }
+            }
+        } else {
+            for (int c = g; c < C; c += 8) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (i0 + e < N) {
+                        s[e] += (double)achan[(size_t)c * N + i0 + e];
+                        if (w1chan) t[e] += (double)w1chan[(size_t)c * N + i0 + e];
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        red[0][g][u][e] = s[e];
+        red[1][g][u][e] = t[e];
+    }
+    __syncthreads();
+    if (tid < 128) {
+        const int uu = tid >> 2, e = tid & 3;
+        const int i = q * 128 + tid;
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < 8; ++gg) {
+            a += red[0][gg][uu][e];
+            b += red[1][gg][uu][e];
+        }
+        if (i < N) {
+            amap[i] = (float)(a / (double)C);
+            if (w1chan) w1[i] = (float)(b / (double)C);
+        }
+    }
+    __syncthreads();
+}
+
 }  // namespace tiles
 }  // namespace qfca
