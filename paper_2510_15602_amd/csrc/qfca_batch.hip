@@ -52,7 +52,9 @@ __device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* job
     constexpr size_t RCP = BLayout<T>::RCP_BYTES;
     float* rcp4 = (float*)smem_all;
     unsigned char* smem = smem_all + RCP;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wavefront index is uniform across the wavefront: held in a scalar
+    // register, offsets derived from it fold into instruction offsets
+    const int lane0 = threadIdx.x & 63, w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = hdr->n, nproj = hdr->nproj, nitems = hdr->nitems;
     if (n > 0) fill_rcp4<T>(rcp4, jobs[0].sa.rcp, threadIdx.x, 256);
     __syncthreads();
@@ -66,6 +68,10 @@ __device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* job
         __syncthreads();
         const int item = s_item, jb = s_job;
         if (item >= nitems) break;
+        // lane-derived values are recomputed per item rather than held in
+        // registers across items (the hidden copies keep them from being hoisted)
+        int lane = lane0, w = w0;
+        asm volatile("" : "+v"(lane), "+s"(w));
         const BatchJob& J = jobs[jb];
         if (item < nproj) {
             const int tile = item - hdr->proj_prefix[jb];

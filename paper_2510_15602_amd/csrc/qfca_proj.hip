@@ -77,6 +77,39 @@ __device__ __forceinline__ void proj_prologue(const MArgs& a, int CMAX, float* s
     }
 }
 
+// Copies two operand tables of NU 16-byte units each into LDS: every thread
+// issues up to eight loads of each table before it stores any, so the copy
+// costs about one memory latency per eight units instead of one per unit.
+template <int NU>
+__device__ __forceinline__ void copy_tables(const void* g1, const void* g2, void* s1, void* s2) {
+    const uint4* a1 = (const uint4*)g1;
+    const uint4* a2 = (const uint4*)g2;
+    uint4* d1 = (uint4*)s1;
+    uint4* d2 = (uint4*)s2;
+    constexpr int PER = (NU + 255) / 256;
+    constexpr int G = PER < 8 ? PER : 8;
+#pragma unroll
+    for (int i0 = 0; i0 < PER; i0 += G) {
+        uint4 t1[G], t2[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int u = threadIdx.x + 256 * (i0 + i);
+            if (i0 + i < PER && u < NU) {
+                t1[i] = a1[u];
+                t2[i] = a2[u];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int u = threadIdx.x + 256 * (i0 + i);
+            if (i0 + i < PER && u < NU) {
+                d1[u] = t1[i];
+                d2[u] = t2[i];
+            }
+        }
+    }
+}
+
 template <int CMAX, int KT, bool VLDS, bool ELDS>
 __device__ __forceinline__ void proj_f32_body(const MArgs& a) {
     constexpr int NSW = CMAX / 16;   // GEMM1 K steps per wave (4 channels each)
@@ -96,27 +129,39 @@ __device__ __forceinline__ void proj_f32_body(const MArgs& a) {
     const float* V1 = (const float*)a.V1;
     const float* V2 = (const float*)a.V2;
     if (VLDS) {
-        for (int i = threadIdx.x; i < VSZ; i += 256) {
-            sv1[i] = V1[i];
-            sv2[i] = V2[i];
-        }
+        copy_tables<VSZ / 4>(V1, V2, sv1, sv2);
         V1 = sv1;
         V2 = sv2;
     }
     const float* edges = ELDS ? (const float*)sedge : a.edges;
     __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wavefront index is uniform across the wavefront: held in a scalar
+    // register, offsets derived from it fold into instruction offsets
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float x[NSW];
-    int tile = blockIdx.x;
-    if (tile < a.ntiles) proj_load_f32<CMAX>(a, tile, w, lane, x);
-    for (; tile < a.ntiles; tile += gridDim.x) {
+    // a contiguous run of tiles per block: neighbouring tiles share cache
+    // lines, which then stay in one L2
+    const int per = (a.ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    int tile = blockIdx.x * per;
+    const int tend = min(a.ntiles, tile + per);
+    if (tile < tend) proj_load_f32<CMAX>(a, tile, w, lane, x);
+    for (; tile < tend; ++tile) {
+        // Everything a tile derives from the lane and wavefront indices
+        // (channels, masks, addresses) and the tables it reads are computed
+        // and re-read per tile rather than held in registers across tiles:
+        // the hidden copies below keep the compiler from hoisting them.
+        int lt = lane, wt = w;
+        asm volatile("" : "+v"(lt), "+s"(wt));
         float xn[NSW];
-        const int nt = tile + gridDim.x;
-        if (nt < a.ntiles) proj_load_f32<CMAX>(a, nt, w, lane, xn);
-        proj_tile_f32<CMAX, KT>(a, tile, w, lane, V1, V2, smu, slo, sid, sfd, zp, x, edges, stg);
+        const int nt = tile + 1;
+        proj_load_f32<CMAX>(a, nt < tend ? nt : tend - 1, wt, lt, xn);  // the last one repeats a tile
+        const float* V1t = VLDS ? opaque_lds(V1) : V1;
+        const float* V2t = VLDS ? opaque_lds(V2) : V2;
+        proj_tile_f32<CMAX, KT>(a, tile, wt, lt, V1t, V2t, opaque_lds(smu), opaque_lds(slo), opaque_lds(sid),
+                                opaque_lds(sfd), zp, x, edges, stg);
         if (a.bins) {
             block_sync_lds();
-            proj_store_bins(a, tile, CMAX, stg);
+            proj_store_bins<CMAX>(a, tile, stg);
         }
 #pragma unroll
         for (int i = 0; i < NSW; ++i) x[i] = xn[i];
@@ -142,27 +187,33 @@ __device__ __forceinline__ void proj_bf16_body(const MArgs& a) {
     const bf16x8* V1 = (const bf16x8*)a.V1;
     const bf16x8* V2 = (const bf16x8*)a.V2;
     if (VLDS) {
-        for (int i = threadIdx.x; i < VSZ / 8; i += 256) {
-            sv1[i] = V1[i];
-            sv2[i] = V2[i];
-        }
+        copy_tables<VSZ / 8>(V1, V2, sv1, sv2);
         V1 = sv1;
         V2 = sv2;
     }
     const float* edges = ELDS ? (const float*)sedge : a.edges;
     __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wavefront index is uniform across the wavefront: held in a scalar
+    // register, offsets derived from it fold into instruction offsets
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float x[NSW][8];
-    int tile = blockIdx.x;
-    if (tile < a.ntiles) proj_load_bf16<CMAX>(a, tile, w, lane, x);
-    for (; tile < a.ntiles; tile += gridDim.x) {
+    const int per = (a.ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    int tile = blockIdx.x * per;
+    const int tend = min(a.ntiles, tile + per);
+    if (tile < tend) proj_load_bf16<CMAX>(a, tile, w, lane, x);
+    for (; tile < tend; ++tile) {
+        int lt = lane, wt = w;
+        asm volatile("" : "+v"(lt), "+s"(wt));
         float xn[NSW][8];
-        const int nt = tile + gridDim.x;
-        if (nt < a.ntiles) proj_load_bf16<CMAX>(a, nt, w, lane, xn);
-        proj_tile_bf16<CMAX, KT>(a, tile, w, lane, V1, V2, smu, slo, sid, sfd, zp, x, edges, stg);
+        const int nt = tile + 1;
+        proj_load_bf16<CMAX>(a, nt < tend ? nt : tend - 1, wt, lt, xn);  // the last one repeats a tile
+        const bf16x8* V1t = VLDS ? opaque_lds(V1) : V1;
+        const bf16x8* V2t = VLDS ? opaque_lds(V2) : V2;
+        proj_tile_bf16<CMAX, KT>(a, tile, wt, lt, V1t, V2t, opaque_lds(smu), opaque_lds(slo), opaque_lds(sid),
+                                 opaque_lds(sfd), zp, x, edges, stg);
         if (a.bins) {
             block_sync_lds();
-            proj_store_bins(a, tile, CMAX, stg);
+            proj_store_bins<CMAX>(a, tile, stg);
         }
 #pragma unroll
         for (int i = 0; i < NSW; ++i)
@@ -281,7 +332,7 @@ hipError_t launch_proj_mfma(const ProjLaunch& L, const void* V1, const void* V2,
     const bool bf = L.prec == QFCA_PREC_BF16;
     const int elt = bf ? 2 : 4;
     // tables in LDS when they fit; the edges are read through the cache
-    // (bin_margin needs them only for values next to an edge)
+    // (the bin decision needs them only for values next to an edge)
     const bool vl = proj_lds(CM, KT, elt, true, false, L.C, L.B).total <= LDS_MAX;
     const bool el = false;
     (void)el;
@@ -291,8 +342,17 @@ hipError_t launch_proj_mfma(const ProjLaunch& L, const void* V1, const void* V2,
         if (vl) return go(KERN<CMV, KTV, true, false>, a, lds, st);                      \
         return go(KERN<CMV, KTV, false, false>, a, lds, st);                             \
     }
-#define QFCA_F32_CASE(CMV, KTV) if (!bf && CM == CMV && KT == KTV) QFCA_PJ(k_proj_f32_mfma, CMV, KTV)
-#define QFCA_BF_CASE(CMV, KTV) if (bf && CM == CMV && KT == KTV) QFCA_PJ(k_proj_bf16_mfma, CMV, KTV)
+    // one block per compute unit (one wavefront per SIMD) when the LDS allows
+    // no second: the register file is then the wavefront's alone, so the
+    // variant without the two-wavefront register cap runs
+    const bool one_block = lds > LDS_TWO_BLOCKS;
+#define QFCA_PJ2(KERN, CMV, KTV)                                                         \
+    {                                                                                    \
+        if (one_block) QFCA_PJ(KERN##_wide, CMV, KTV)                                    \
+        QFCA_PJ(KERN, CMV, KTV)                                                          \
+    }
+#define QFCA_F32_CASE(CMV, KTV) if (!bf && CM == CMV && KT == KTV) QFCA_PJ2(k_proj_f32_mfma, CMV, KTV)
+#define QFCA_BF_CASE(CMV, KTV) if (bf && CM == CMV && KT == KTV) QFCA_PJ2(k_proj_bf16_mfma, CMV, KTV)
 #define QFCA_F32_CM(CMV) QFCA_F32_CASE(CMV, 1) QFCA_F32_CASE(CMV, 2) QFCA_F32_CASE(CMV, 4)
 #define QFCA_BF_CM(CMV) QFCA_BF_CASE(CMV, 2) QFCA_BF_CASE(CMV, 4)
 #define QFCA_F32W_CASE(CMV, KTV) if (!bf && CM == CMV && KT == KTV) QFCA_PJ(k_proj_f32_mfma_wide, CMV, KTV)
@@ -302,6 +362,7 @@ hipError_t launch_proj_mfma(const ProjLaunch& L, const void* V1, const void* V2,
     QFCA_BF_CM(128) QFCA_BF_CM(256)
     QFCA_BFW_CASE(512, 2) QFCA_BFW_CASE(512, 4)
 #undef QFCA_BFW_CASE
+#undef QFCA_PJ2
 #undef QFCA_F32W_CASE
 #undef QFCA_BF_CM
 #undef QFCA_F32_CM

@@ -548,58 +548,101 @@ __device__ __forceinline__ int bin_fast(float rr, const float* __restrict__ e, f
     return b;
 }
 
-// bin = #{m : rr >= e[m]} (B >= 2).  t = (rr - lo) * idl decides on its own
-// when it lies farther than the channel's margin dl from every integer (dl
-// bounds the stored edges' distance from the grid lo + m delta plus the
-// FP32 rounding of t); otherwise, and for channels whose margin is one half
-// or more, the edges around floor(t) are consulted.
-__device__ __forceinline__ int bin_margin(float rr, const float* __restrict__ e, float lo, float idl, float dl,
-                                          int B) {
-    if (idl == 0.f) return 0;
-    if (dl < 0.5f) {
-        const float t = (rr - lo) * idl;
-        if (t < 0.f) return 0;
+// Residuals and bins of NE values of one pixel px (channels cs[e], residuals
+// rv[e]); `valid` marks the values whose pixel and channel exist.  edges:
+// the [C][B-1] edge table (read only for values next to an edge).  slo, sid,
+// sfd: per-channel lo, 1/delta and margin dl in LDS (arrays of the block's
+// channel capacity, so every cs[e] may be read).  stg: the block's bin
+// staging area [CMAX][16] in LDS (the caller writes it out; bytes of invalid
+// values are never stored), or nullptr to store each bin directly.
+// bin = #{m : r >= e[m]}: t = (r - lo) / delta decides it on its own when t
+// lies farther than dl from every integer edge position 1 .. B-1 (dl bounds
+// the stored edges' distance from the grid lo + m delta plus the FP32
+// rounding of t; a margin of one half or more disables this): floor(t) in
+// range, 0 below the grid, B-1 above it.  The test is made without branches
+// for all NE values; the edge search (bin_fast) runs only when some lane of
+// the wavefront has a value next to an edge, and then only for such values.
+template <int NE>
+__device__ __forceinline__ void emit_values(const MArgs& a, int px, const int (&cs)[NE], const float (&rv)[NE],
+                                            const bool (&valid)[NE], const float* slo, const float* sid,
+                                            const float* sfd, const float* edges, uint8_t* stg) {
+    if (a.resid) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            if (valid[e]) a.resid[(size_t)cs[e] * a.N + px] = rv[e];
+    }
+    if (!a.bins) return;
+    const int B = a.B;
+    int bq[NE];
+    uint32_t need = 0;
+    if (B > 1) {
         const float top = (float)(B - 1);
-        if (t >= top + dl) return B - 1;
-        if (t < top) {  // NaN falls through to the search
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int c = cs[e];
+            const float lo = slo[c], idl = sid[c], dl = sfd[c];
+            const float t = (rv[e] - lo) * idl;
             const float fl = floorf(t);
             const float f = t - fl;
-            const int b0 = (int)fl;
-            if ((b0 == 0 || f >= dl) && f <= 1.f - dl) return b0;
+            const int b = (int)fl;
+            const bool neg = t < 0.f;
+            const bool hi = t >= top + dl;
+            const bool mid = (t >= 0.f) && (t < top) && (b == 0 || f >= dl) && (f <= 1.f - dl);
+            const bool dec = (dl < 0.5f) && (idl != 0.f) && (neg || hi || mid);
+            bq[e] = neg ? 0 : (hi ? B - 1 : b);
+            need |= (!dec && valid[e]) ? (1u << e) : 0u;
         }
+        if (__ballot(need != 0u)) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e)
+                if (need & (1u << e)) {
+                    const int c = cs[e];
+                    bq[e] = bin_fast(rv[e], edges + (size_t)c * (B - 1), slo[c], sid[c], B);
+                }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) bq[e] = 0;
     }
-    return bin_fast(rr, e, lo, idl, B);
-}
-
-// edges: the [C][B-1] edge table, in LDS or global memory.  sfd: the
-// per-channel margins of bin_margin (LDS or global).  stg: the
-// block's bin staging area [CMAX][16] in LDS (the caller writes it out), or
-// nullptr to store each bin directly.
-__device__ __forceinline__ void emit(const MArgs& a, int c, int px, float r, const float* slo,
-                                     const float* sid, const float* sfd, const float* edges, uint8_t* stg) {
-    if (a.resid) a.resid[(size_t)c * a.N + px] = r;
-    if (a.bins) {
-        const uint8_t b = a.B > 1
-                              ? (uint8_t)bin_margin(r, edges + (size_t)c * (a.B - 1), slo[c], sid[c], sfd[c], a.B)
-                              : (uint8_t)0;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
         if (stg)
-            stg[c * 16 + (px & 15)] = b;
-        else
-            a.bins[(size_t)c * a.N + px] = b;
+            stg[cs[e] * 16 + (px & 15)] = (uint8_t)bq[e];
+        else if (valid[e])
+            a.bins[(size_t)cs[e] * a.N + px] = (uint8_t)bq[e];
     }
 }
 
-// Writes a block's staged bins of one 16-pixel tile: one 16-byte channel row
-// per thread (byte by byte for a ragged last tile or a width that is not a
-// multiple of 16).  Called by all threads of the block after a barrier.
-__device__ __forceinline__ void proj_store_bins(const MArgs& a, int tile, int CMAX, const uint8_t* stg) {
+// Hides an LDS pointer's value from the optimiser, so that loads through it
+// inside a loop are not hoisted out of it (keeping every table entry of a
+// tile live across iterations would take more registers than reloading).
+template <class T>
+__device__ __forceinline__ const T* opaque_lds(const T* p) {
+    uint32_t v = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const T*)p;
+    asm volatile("" : "+s"(v));
+    return (const T*)(__attribute__((address_space(3))) const T*)(uintptr_t)v;
+}
+
+// Writes a block's (256 threads) staged bins of one 16-pixel tile: one
+// 16-byte channel row per thread, without per-thread branches (threads past
+// the last channel write that channel's row again, the same bytes), so the
+// compiler can count the memory operations in flight exactly; byte by byte
+// for a ragged last tile or a width that is not a multiple of 16.  Called by
+// all threads of the block after a barrier.
+template <int CMAX>
+__device__ __forceinline__ void proj_store_bins(const MArgs& a, int tile, const uint8_t* stg) {
     const int p0 = tile * 16;
     const bool whole = (p0 + 16 <= a.N) && ((a.N & 15) == 0) && (((uintptr_t)a.bins & 15) == 0);
-    for (int c = threadIdx.x; c < CMAX && c < a.C; c += blockDim.x) {
-        uint8_t* dst = a.bins + (size_t)c * a.N + p0;
-        if (whole) {
-            *(uint4*)dst = *(const uint4*)(stg + c * 16);
-        } else {
+    if (whole) {
+#pragma unroll
+        for (int r = 0; r < (CMAX + 255) / 256; ++r) {
+            const int c = threadIdx.x + 256 * r;
+            const int cs = c < a.C ? c : a.C - 1;
+            *(uint4*)(a.bins + (size_t)cs * a.N + p0) = *(const uint4*)(stg + cs * 16);
+        }
+    } else {
+        for (int c = threadIdx.x; c < CMAX && c < a.C; c += blockDim.x) {
+            uint8_t* dst = a.bins + (size_t)c * a.N + p0;
             for (int q = 0; q < 16 && p0 + q < a.N; ++q) dst[q] = stg[c * 16 + q];
         }
     }
@@ -608,16 +651,24 @@ __device__ __forceinline__ void proj_store_bins(const MArgs& a, int tile, int CM
 // Features of one 16-pixel tile for wave w: the FP32 tile's GEMM1 B operands
 // (channel 4 s + g, s = w NSW + i, pixel n) and the BF16 tile's (channels
 // 32 s + 8 g + t).  Loaded separately so that a caller can prefetch them.
+// Every load is issued, from a clamped, valid address, and its value is
+// used as loaded: with no branch around a load the compiler knows how many
+// are in flight and waits only for the ones it needs.  Lanes of pixels past
+// the map compute on a real pixel's features and are never stored; channels
+// past C meet zero rows of the operand tables (and their residuals are never
+// stored), so the features they load do not enter any result.
 template <int CMAX>
 __device__ __forceinline__ void proj_load_f32(const MArgs& a, int tile, int w, int lane, float (&x)[CMAX / 16]) {
     constexpr int NSW = CMAX / 16;
     const int g = lane >> 4, n = lane & 15;
     const int px = tile * 16 + n;
     const bool pxok = px < a.N;
+    const int pxc = pxok ? px : a.N - 1;
 #pragma unroll
     for (int i = 0; i < NSW; ++i) {
         const int c = 4 * (w * NSW + i) + g;
-        x[i] = (pxok && c < a.C) ? a.X[(size_t)c * a.N + px] : 0.f;
+        const int cc = c < a.C ? c : a.C - 1;
+        x[i] = a.X[(size_t)cc * a.N + pxc];
     }
 }
 
@@ -628,12 +679,14 @@ __device__ __forceinline__ void proj_load_bf16(const MArgs& a, int tile, int w, 
     const int g = lane >> 4, n = lane & 15;
     const int px = tile * 16 + n;
     const bool pxok = px < a.N;
+    const int pxc = pxok ? px : a.N - 1;
 #pragma unroll
     for (int i = 0; i < NSW; ++i)
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int c = 32 * (w * NSW + i) + 8 * g + t;
-            x[i][t] = (pxok && c < a.C) ? a.X[(size_t)c * a.N + px] : 0.f;
+            const int cc = c < a.C ? c : a.C - 1;
+            x[i][t] = a.X[(size_t)cc * a.N + pxc];
         }
 }
 
@@ -656,7 +709,7 @@ __device__ __forceinline__ void proj_tile_f32(const MArgs& a, int tile, int w, i
     for (int i = 0; i < NSW; ++i) {
         const int s = w * NSW + i;
         const int c = 4 * s + g;
-        d[i] = (c < a.C) ? x[i] - smu[c] : 0.f;
+        d[i] = x[i] - smu[c];
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
             z[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(V1[((s * KT + kt) * 4 + g) * 16 + n], d[i],
@@ -679,6 +732,9 @@ __device__ __forceinline__ void proj_tile_f32(const MArgs& a, int tile, int w, i
             z[kt][v] = acc;
         }
     block_sync_lds();
+    int cs[NSW];
+    float rv[NSW];
+    bool valid[NSW];
 #pragma unroll
     for (int i = 0; i < NTW; ++i) {
         const int t = w * NTW + i;
@@ -690,11 +746,12 @@ __device__ __forceinline__ void proj_tile_f32(const MArgs& a, int tile, int w, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int c = 16 * t + 4 * v + g;
-            const float r = d[4 * i + v] - acc[v];
-            if (pxok && c < a.C) emit(a, c, px, r, slo, sid, sfd, edges, stg);
+            cs[4 * i + v] = c;
+            rv[4 * i + v] = d[4 * i + v] - acc[v];
+            valid[4 * i + v] = pxok && c < a.C;
         }
-        __builtin_amdgcn_sched_barrier(0);
     }
+    emit_values<NSW>(a, px, cs, rv, valid, slo, sid, sfd, edges, stg);
 }
 
 template <int CMAX, int KT>
@@ -718,7 +775,7 @@ __device__ __forceinline__ void proj_tile_bf16(const MArgs& a, int tile, int w, 
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int c = 32 * s + 8 * g + t;
-            d[i][t] = (c < a.C) ? x[i][t] - smu[c] : 0.f;
+            d[i][t] = x[i][t] - smu[c];
             bv[t] = (__bf16)d[i][t];
         }
 #pragma unroll
@@ -744,6 +801,9 @@ __device__ __forceinline__ void proj_tile_bf16(const MArgs& a, int tile, int w, 
             zb[kt >> 1][4 * (kt & 1) + v] = (__bf16)acc;
         }
     block_sync_lds();
+    int cs[NSW * 8];
+    float rv[NSW * 8];
+    bool valid[NSW * 8];
 #pragma unroll
     for (int i = 0; i < NSW; ++i) {
         const int s = w * NSW + i;
@@ -758,12 +818,14 @@ __device__ __forceinline__ void proj_tile_bf16(const MArgs& a, int tile, int w, 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int c = 32 * s + 8 * g + 4 * h + v;
-                const float r = d[i][4 * h + v] - acc[v];
-                if (pxok && c < a.C) emit(a, c, px, r, slo, sid, sfd, edges, stg);
+                const int e = 8 * i + 4 * h + v;
+                cs[e] = c;
+                rv[e] = d[i][4 * h + v] - acc[v];
+                valid[e] = pxok && c < a.C;
             }
-            __builtin_amdgcn_sched_barrier(0);
         }
     }
+    emit_values<NSW * 8>(a, px, cs, rv, valid, slo, sid, sfd, edges, stg);
 }
 
 // Channel mean A(x) = (1/C) sum_c achan[c][x] (and the same for the W1
