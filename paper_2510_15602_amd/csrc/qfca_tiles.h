@@ -195,11 +195,17 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     // < 64; 0x7F marks columns outside the image or padding (never counted
     // by the 7-bit comparison below).  When the row fits LRN bytes per lane,
     // each lane's source offsets (relative to the group's first channel at
-    // the row) are fixed for the tile: s H W + x, or -1 for a marker byte.
+    // the row) are fixed for the tile: s H W + x, clamped to offset 0 for a
+    // marker byte (bit i of lmark), and the row entering next is loaded into
+    // registers one row ahead (issue_row) and written to the ring when it
+    // enters (commit_row).  Every load is issued and its value used (ORed
+    // with 0x7F for a marker), so no branch hides a load from the compiler's
+    // count of loads in flight.
     const int nlb = S * rowb;
     constexpr int LRN = 4;
     const bool lfast = (nlb <= 64 * LRN) && ((long long)S * H * W < 0x7FFFFFFFLL);
     int loff[LRN];
+    uint32_t lmark = 0;
 #pragma unroll
     for (int i = 0; i < LRN; ++i) {
         const int t = lane + 64 * i;
@@ -208,20 +214,28 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
         const int q = blk * T + k;
         const int cc = cbase + ss, xx = xb0 + q;
         const bool v = lfast && t < nlb && k < T && cc < a.C && q < Wb && xx >= 0 && xx < W;
-        loff[i] = v ? ss * H * W + xx : -1;
+        loff[i] = v ? ss * H * W + xx : 0;
+        lmark |= v ? 0u : (1u << i);
     }
-    auto load_row = [&](int yy) {
+    uint32_t pre[LRN];
+    auto issue_row = [&](int yy) {
+        const uint8_t* rowp = a.bins + ((size_t)cbase * H + yy) * W;
+#pragma unroll
+        for (int i = 0; i < LRN; ++i) pre[i] = (uint32_t)rowp[loff[i]];
+    };
+    auto commit_row = [&](int yy) {
         uint8_t* dst = ring + (size_t)(yy % T1) * nlb;
+#pragma unroll
+        for (int i = 0; i < LRN; ++i)
+            if (lane + 64 * i < nlb) dst[lane + 64 * i] = (uint8_t)((pre[i] | (((lmark >> i) & 1u) * 0x7Fu)) & 0x7Fu);
+    };
+    auto load_row = [&](int yy) {
         if (lfast) {
-            const uint8_t* rowp = a.bins + ((size_t)cbase * H + yy) * W;
-            uint8_t v[LRN];
-#pragma unroll
-            for (int i = 0; i < LRN; ++i) v[i] = (loff[i] >= 0) ? (uint8_t)(rowp[loff[i]] & 0x7F) : (uint8_t)0x7F;
-#pragma unroll
-            for (int i = 0; i < LRN; ++i)
-                if (lane + 64 * i < nlb) dst[lane + 64 * i] = v[i];
+            issue_row(yy);
+            commit_row(yy);
             return;
         }
+        uint8_t* dst = ring + (size_t)(yy % T1) * nlb;
         for (int t = lane; t < nlb; t += 64) {
             const int ss = t / rowb, o = t - ss * rowb;
             const int blk = o / TP, k = o - blk * TP;
@@ -305,11 +319,17 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
         update_vc(yy, yy, bconst<true>(), bconst<false>());
         wave_sync();
     }
+    if (lfast && ys + r < H) issue_row(ys + r);
 
     for (int y = ys; y < yend; ++y) {
         const bool add = (y + r) < H;
         const bool rem = (y - r - 1) >= lo_add;
-        if (add) load_row(y + r);
+        if (add) {
+            if (lfast)
+                commit_row(y + r);  // loaded during the previous row
+            else
+                load_row(y + r);
+        }
         wave_sync();
         if (add && rem)
             update_vc(y + r, y - r - 1, bconst<true>(), bconst<true>());
@@ -317,6 +337,9 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
             update_vc(y + r, y - r - 1, bconst<true>(), bconst<false>());
         else if (rem)
             update_vc(y + r, y - r - 1, bconst<false>(), bconst<true>());
+        // the row entering next goes to the ring slot of row y - r - 1, which
+        // the update above has just consumed; its loads overlap this row
+        if (lfast && y + 1 < yend && y + r + 1 < H) issue_row(y + r + 1);
         const int ny = min(H - 1, y + r) - max(0, y - r) + 1;
         const bool row_full = (ny == T);
         const bool own_row = (y >= y0) && (y < ye);
