@@ -210,6 +210,21 @@ qfca_status qfca_model_params(qfca_model model, qfca_params* out);
 qfca_status qfca_model_read(qfca_model model, int32_t field, void* host_dst, size_t bytes);
 qfca_status qfca_model_destroy(qfca_model model);
 
+/* Model serialisation, for storing fitted models (for instance one per
+ * texture class, Sec. 3.3) and loading them elsewhere.  qfca_model_export
+ * writes the model into host memory: with host_buf NULL it only sets
+ * *inout_bytes to the size needed; otherwise *inout_bytes is the buffer's
+ * size on entry (QFCA_E_ARG if too small, with the size needed set) and the
+ * bytes written on return.  The format holds the parameters, mu and V in
+ * double precision, the float32 edges, delta, and (when set) the reference
+ * cR, the eigenvalues and lo/hi, in host byte order behind a magic and a
+ * version.  qfca_model_import builds a new model on ctx's device from such a
+ * buffer (bytes must be its exact size), validated like qfca_model_create;
+ * the imported model quantises and scores bit for bit like the exported one.
+ * Both are synchronous; the caller owns host_buf. */
+qfca_status qfca_model_export(qfca_model model, void* host_buf, size_t* inout_bytes);
+qfca_status qfca_model_import(qfca_ctx ctx, const void* host_buf, size_t bytes, qfca_model* out);
+
 /* ------------------------------------------------------------------------
  * Serving.  A server scores single images submitted one at a time, each
  * against a resident model (for instance one per texture class), with

@@ -29,7 +29,8 @@ STATUS = {0: "QFCA_OK", 1: "QFCA_E_ARG", 2: "QFCA_E_SHAPE", 3: "QFCA_E_NOMEM", 4
 EXPORTS = ("qfca_status_str", "qfca_last_error", "qfca_version", "qfca_ctx_create",
            "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca", "qfca_model_create",
            "qfca_fit_reference", "qfca_quantize", "qfca_score_map", "qfca_model_params",
-           "qfca_model_read", "qfca_model_destroy", "qfca_host_sym_eig", "qfca_ctx_profile",
+           "qfca_model_read", "qfca_model_destroy", "qfca_model_export", "qfca_model_import",
+           "qfca_host_sym_eig", "qfca_ctx_profile",
            "qfca_ctx_profile_read", "qfca_ctx_set_tile", "qfca_score_batch", "qfca_batch_error",
            "qfca_autotune", "qfca_clock", "qfca_server_create", "qfca_server_submit",
            "qfca_server_poll", "qfca_server_drain", "qfca_server_stats", "qfca_server_destroy")
@@ -113,6 +114,8 @@ def lib():
         L.qfca_model_params.argtypes = [P, ctypes.POINTER(Params)]
         L.qfca_model_read.argtypes = [P, i32, P, sz]
         L.qfca_model_destroy.argtypes = [P]
+        L.qfca_model_export.argtypes = [P, P, ctypes.POINTER(sz)]
+        L.qfca_model_import.argtypes = [P, P, sz, ctypes.POINTER(P)]
         L.qfca_host_sym_eig.argtypes = [P, i32, P, P]
         L.qfca_host_sym_eig.restype = i32
         L.qfca_ctx_profile.argtypes = [P, i32]
@@ -136,7 +139,8 @@ def lib():
             getattr(L, name).restype = i32
         for name in ("qfca_ctx_create", "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca",
                      "qfca_model_create", "qfca_fit_reference", "qfca_quantize", "qfca_score_map",
-                     "qfca_model_params", "qfca_model_read", "qfca_model_destroy",
+                     "qfca_model_params", "qfca_model_read", "qfca_model_destroy", "qfca_model_export",
+                     "qfca_model_import",
                      "qfca_ctx_profile", "qfca_ctx_profile_read", "qfca_ctx_set_tile",
                      "qfca_score_batch", "qfca_batch_error", "qfca_autotune"):
             getattr(L, name).restype = i32
@@ -277,6 +281,22 @@ def qfca_model_create(ctx: Context, params: Params, mu, V, edges, delta, cR=None
     h = ctypes.c_void_p()
     _check(lib().qfca_model_create(ctx.handle, ctypes.byref(params), p(mu), p(V), p(edges), p(delta),
                                    p(cR), ctypes.byref(h)))
+    return Model(h)
+
+
+def qfca_model_export(model: Model) -> bytes:
+    """Serialised model (host bytes); see qfca_model_export in include/qfca.h."""
+    n = ctypes.c_size_t(0)
+    _check(lib().qfca_model_export(model.handle, None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().qfca_model_export(model.handle, buf, ctypes.byref(n)))
+    return buf.raw[: n.value]
+
+
+def qfca_model_import(ctx: Context, blob: bytes) -> Model:
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    h = ctypes.c_void_p()
+    _check(lib().qfca_model_import(ctx.handle, buf, len(blob), ctypes.byref(h)))
     return Model(h)
 
 

@@ -515,9 +515,16 @@ qfca_status qfca_model_read(qfca_model m, int32_t field, void* dst, size_t bytes
     return QFCA_OK;
 }
 
-qfca_status qfca_model_create(qfca_ctx ctx, const qfca_params* p, const float* mu, const float* V,
-                              const float* edges, const double* delta, const int32_t* cR,
-                              qfca_model* out) {
+}  // extern "C"
+
+namespace {
+
+// Builds a model from host arrays (mu and V in double precision); lo, when
+// given, is taken as is (a fitted or exported model), otherwise derived from
+// the first edge.  Validates everything before any allocation.
+qfca_status build_model(qfca_ctx ctx, const qfca_params* p, const double* mu, const double* V,
+                        const float* edges, const double* delta, const int32_t* cR, const double* lo,
+                        qfca_model* out) {
     if (!ctx || !out) return fail(QFCA_E_ARG, "NULL argument");
     *out = nullptr;
     qfca_status st = check_params(p);
@@ -556,7 +563,8 @@ qfca_status qfca_model_create(qfca_ctx ctx, const qfca_params* p, const float* m
     m->delta.assign(delta, delta + C);
     m->lo.assign(C, 0.0);
     for (int c = 0; c < C; ++c)
-        m->lo[c] = (B > 1 && m->delta[c] > 0.0) ? (double)m->edges[(size_t)c * (B - 1)] - m->delta[c] : 0.0;
+        m->lo[c] = lo ? lo[c]
+                      : ((B > 1 && m->delta[c] > 0.0) ? (double)m->edges[(size_t)c * (B - 1)] - m->delta[c] : 0.0);
     if ((st = upload_projection(m.get())) != QFCA_OK) return st;
     if ((st = upload_quant(m.get())) != QFCA_OK) return st;
     if (cR) {
@@ -564,6 +572,162 @@ qfca_status qfca_model_create(qfca_ctx ctx, const qfca_params* p, const float* m
         if ((st = upload_tables(m.get())) != QFCA_OK) return st;
     }
     *out = m.release();
+    return QFCA_OK;
+}
+
+// Serialised model: an 8-byte magic, u32 version, u32 flags (bit 0 reference,
+// bit 1 eigenvalues, bit 2 lo/hi), the parameters (C k B T as int32, q_lo q_hi
+// sigma_s as float32, preproc proj_prec as int32), then mu [C] f64, V [C][k]
+// f64 (residual models only), edges [C][B-1] f32, delta [C] f64, and, by
+// flag, cR [C][B] i32, eigenvalues [C] f64, lo [C] f64 and hi [C] f64.  Host
+// byte order.
+constexpr char kModelMagic[8] = {'Q', 'F', 'C', 'A', 'M', 'D', 'L', '\0'};
+constexpr uint32_t kModelVersion = 1;
+constexpr size_t kModelHeader = 8 + 4 + 4 + 40;
+
+struct ModelBlob {
+    size_t mu, V, edges, delta, cR, evals, lohi, total;
+};
+
+ModelBlob blob_sizes(const qfca_params& p, uint32_t flags) {
+    ModelBlob z;
+    const size_t C = (size_t)p.C;
+    z.mu = C * 8;
+    z.V = p.preproc == QFCA_PRE_RESIDUAL ? C * (size_t)p.k * 8 : 0;
+    z.edges = C * (size_t)(p.B > 1 ? p.B - 1 : 0) * 4;
+    z.delta = C * 8;
+    z.cR = (flags & 1u) ? C * (size_t)p.B * 4 : 0;
+    z.evals = (flags & 2u) ? C * 8 : 0;
+    z.lohi = (flags & 4u) ? C * 16 : 0;
+    z.total = kModelHeader + z.mu + z.V + z.edges + z.delta + z.cR + z.evals + z.lohi;
+    return z;
+}
+
+void put_params(unsigned char* d, const qfca_params& p) {
+    const int32_t iv[4] = {p.C, p.k, p.B, p.T};
+    const float fv[3] = {p.q_lo, p.q_hi, p.sigma_s};
+    const int32_t jv[2] = {p.preproc, p.proj_prec};
+    memcpy(d, iv, 16);
+    memcpy(d + 16, fv, 12);
+    memcpy(d + 28, jv, 8);
+    memset(d + 36, 0, 4);
+}
+
+qfca_params get_params(const unsigned char* d) {
+    int32_t iv[4];
+    float fv[3];
+    int32_t jv[2];
+    memcpy(iv, d, 16);
+    memcpy(fv, d + 16, 12);
+    memcpy(jv, d + 28, 8);
+    qfca_params p{};
+    p.C = iv[0]; p.k = iv[1]; p.B = iv[2]; p.T = iv[3];
+    p.q_lo = fv[0]; p.q_hi = fv[1]; p.sigma_s = fv[2];
+    p.preproc = jv[0]; p.proj_prec = jv[1];
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+qfca_status qfca_model_create(qfca_ctx ctx, const qfca_params* p, const float* mu, const float* V,
+                              const float* edges, const double* delta, const int32_t* cR,
+                              qfca_model* out) {
+    if (!p) return fail(QFCA_E_ARG, "NULL argument");
+    std::vector<double> mud, Vd;
+    if (mu && p->C > 0) mud.assign(mu, mu + p->C);
+    if (V && p->C > 0 && p->k > 0) Vd.assign(V, V + (size_t)p->C * p->k);
+    return build_model(ctx, p, mu ? mud.data() : nullptr, V ? Vd.data() : nullptr, edges, delta, cR, nullptr,
+                       out);
+}
+
+qfca_status qfca_model_export(qfca_model m, void* host_buf, size_t* inout_bytes) {
+    if (!m || !inout_bytes) return fail(QFCA_E_ARG, "NULL argument");
+    const uint32_t flags = (m->has_ref ? 1u : 0u) | (m->has_evals ? 2u : 0u) | (m->has_lohi ? 4u : 0u);
+    const ModelBlob z = blob_sizes(m->p, flags);
+    if (!host_buf) {
+        *inout_bytes = z.total;
+        return QFCA_OK;
+    }
+    if (*inout_bytes < z.total) {
+        *inout_bytes = z.total;
+        return fail(QFCA_E_ARG, "buffer smaller than the serialised model");
+    }
+    unsigned char* d = (unsigned char*)host_buf;
+    memcpy(d, kModelMagic, 8);
+    memcpy(d + 8, &kModelVersion, 4);
+    memcpy(d + 12, &flags, 4);
+    put_params(d + 16, m->p);
+    size_t o = kModelHeader;
+    auto put = [&](const void* src, size_t n) {
+        if (n) memcpy(d + o, src, n);
+        o += n;
+    };
+    std::vector<double> mu(m->p.C, 0.0);
+    for (int c = 0; c < m->p.C && c < (int)m->mu.size(); ++c) mu[c] = m->mu[c];
+    put(mu.data(), z.mu);
+    put(m->V.data(), z.V);
+    put(m->edges.data(), z.edges);
+    put(m->delta.data(), z.delta);
+    put(m->cR.data(), z.cR);
+    put(m->evals.data(), z.evals);
+    if (z.lohi) {
+        put(m->lo.data(), z.lohi / 2);
+        put(m->hi.data(), z.lohi / 2);
+    }
+    *inout_bytes = z.total;
+    return QFCA_OK;
+}
+
+qfca_status qfca_model_import(qfca_ctx ctx, const void* host_buf, size_t bytes, qfca_model* out) {
+    if (!ctx || !host_buf || !out) return fail(QFCA_E_ARG, "NULL argument");
+    *out = nullptr;
+    const unsigned char* d = (const unsigned char*)host_buf;
+    if (bytes < kModelHeader || memcmp(d, kModelMagic, 8) != 0) return fail(QFCA_E_ARG, "not a serialised model");
+    uint32_t version = 0, flags = 0;
+    memcpy(&version, d + 8, 4);
+    memcpy(&flags, d + 12, 4);
+    if (version != kModelVersion) return fail(QFCA_E_UNSUPPORTED, "unknown model format version");
+    if (flags & ~7u) return fail(QFCA_E_ARG, "unknown model flags");
+    const qfca_params p = get_params(d + 16);
+    qfca_status st = check_params(&p);
+    if (st != QFCA_OK) return st;
+    const ModelBlob z = blob_sizes(p, flags);
+    if (bytes != z.total) return fail(QFCA_E_ARG, "byte count does not match the serialised model");
+    size_t o = kModelHeader;
+    auto take = [&](size_t n) {
+        const unsigned char* q = d + o;
+        o += n;
+        return q;
+    };
+    const size_t C = (size_t)p.C;
+    std::vector<double> mu(C), V(z.V / 8), delta(C), evals(z.evals / 8), lo(z.lohi / 16), hi(z.lohi / 16);
+    std::vector<float> edges(z.edges / 4);
+    std::vector<int32_t> cR(z.cR / 4);
+    memcpy(mu.data(), take(z.mu), z.mu);
+    if (z.V) memcpy(V.data(), take(z.V), z.V);
+    if (z.edges) memcpy(edges.data(), take(z.edges), z.edges);
+    memcpy(delta.data(), take(z.delta), z.delta);
+    if (z.cR) memcpy(cR.data(), take(z.cR), z.cR);
+    if (z.evals) memcpy(evals.data(), take(z.evals), z.evals);
+    if (z.lohi) {
+        memcpy(lo.data(), take(z.lohi / 2), z.lohi / 2);
+        memcpy(hi.data(), take(z.lohi / 2), z.lohi / 2);
+    }
+    qfca_model m = nullptr;
+    st = build_model(ctx, &p, mu.data(), z.V ? V.data() : nullptr, z.edges ? edges.data() : nullptr, delta.data(),
+                     z.cR ? cR.data() : nullptr, z.lohi ? lo.data() : nullptr, &m);
+    if (st != QFCA_OK) return st;
+    if (z.evals) {
+        m->evals = evals;
+        m->has_evals = true;
+    }
+    if (z.lohi) {
+        m->hi = hi;
+        m->has_lohi = true;
+    }
+    *out = m;
     return QFCA_OK;
 }
 

@@ -60,3 +60,16 @@ def test_oracle_library_builds_and_is_separate():
     # the product package never imports the oracle
     src = open(os.path.join(ROOT, "paper_2510_15602_amd", "__init__.py")).read()
     assert "import oracle" not in src
+
+
+def test_model_serialisation_rejects_bad_arguments_without_a_gpu():
+    """Argument checks of qfca_model_export / qfca_model_import run before
+    any device call."""
+    import ctypes
+    L = q.lib()
+    n = ctypes.c_size_t(0)
+    assert L.qfca_model_export(None, None, ctypes.byref(n)) == 1
+    h = ctypes.c_void_p()
+    blob = ctypes.create_string_buffer(b"QFCAMDL\0" + bytes(64))
+    assert L.qfca_model_import(None, blob, 72, ctypes.byref(h)) == 1
+    assert not h.value
