@@ -304,6 +304,14 @@ qfca_status qfca_server_destroy(qfca_server server);
  * the iteration fails to converge or n < 1.  Needs no GPU. */
 int qfca_host_sym_eig(double* A, int32_t n, double* evals, double* vecs);
 
+/* The variant qfca_fit_pca uses: all eigenvalues (evals [n], descending) but
+ * only the k leading eigenvectors (vecs: host [n][k] out, row-major, column
+ * j for evals[j], largest-magnitude entry positive), by inverse iteration on
+ * the tridiagonal form (close eigenvalues orthogonalised against each other)
+ * and the stored Householder reflectors.  0 <= k <= n.  Returns 0, or -1 on
+ * failure.  Needs no GPU. */
+int qfca_host_sym_eig_top(double* A, int32_t n, int32_t k, double* evals, double* vecs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,7 +30,7 @@ EXPORTS = ("qfca_status_str", "qfca_last_error", "qfca_version", "qfca_ctx_creat
            "qfca_ctx_set_stream", "qfca_ctx_destroy", "qfca_fit_pca", "qfca_model_create",
            "qfca_fit_reference", "qfca_quantize", "qfca_score_map", "qfca_model_params",
            "qfca_model_read", "qfca_model_destroy", "qfca_model_export", "qfca_model_import",
-           "qfca_host_sym_eig", "qfca_ctx_profile",
+           "qfca_host_sym_eig", "qfca_host_sym_eig_top", "qfca_ctx_profile",
            "qfca_ctx_profile_read", "qfca_ctx_set_tile", "qfca_score_batch", "qfca_batch_error",
            "qfca_autotune", "qfca_clock", "qfca_server_create", "qfca_server_submit",
            "qfca_server_poll", "qfca_server_drain", "qfca_server_stats", "qfca_server_destroy")
@@ -118,6 +118,8 @@ def lib():
         L.qfca_model_import.argtypes = [P, P, sz, ctypes.POINTER(P)]
         L.qfca_host_sym_eig.argtypes = [P, i32, P, P]
         L.qfca_host_sym_eig.restype = i32
+        L.qfca_host_sym_eig_top.argtypes = [P, i32, i32, P, P]
+        L.qfca_host_sym_eig_top.restype = i32
         L.qfca_ctx_profile.argtypes = [P, i32]
         L.qfca_ctx_set_tile.argtypes = [P, i32, i32, i32, i32]
         L.qfca_score_batch.argtypes = [P, ctypes.POINTER(Job), i32]
@@ -475,6 +477,20 @@ def host_sym_eig(A: np.ndarray):
     V = np.zeros((n, n))
     rc = lib().qfca_host_sym_eig(A.ctypes.data_as(ctypes.c_void_p), n, ev.ctypes.data_as(ctypes.c_void_p),
                                  V.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise QfcaError(4, "eigensolver failed")
+    return ev, V
+
+
+def host_sym_eig_top(A: np.ndarray, k: int):
+    """The fit's host eigensolver (no GPU needed): (all evals desc, the k
+    leading eigenvectors as columns)."""
+    A = np.array(A, dtype=np.float64, order="C", copy=True)
+    n = A.shape[0]
+    ev = np.zeros(n)
+    V = np.zeros((n, k))
+    rc = lib().qfca_host_sym_eig_top(A.ctypes.data_as(ctypes.c_void_p), n, k, ev.ctypes.data_as(ctypes.c_void_p),
+                                     V.ctypes.data_as(ctypes.c_void_p))
     if rc != 0:
         raise QfcaError(4, "eigensolver failed")
     return ev, V

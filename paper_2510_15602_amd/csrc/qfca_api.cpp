@@ -795,7 +795,7 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
     for (int c = 0; c < C; ++c)
         if (!isfinite(m->mu[c])) return fail(QFCA_E_NONFINITE, "non-finite value in the features");
     if (pre) {
-        std::vector<double> cov((size_t)C * C), vecs((size_t)C * C);
+        std::vector<double> cov((size_t)C * C), vecs((size_t)C * k);
         double* dcov = nullptr;
         HIP_TRY(scratch(ctx, SL_COV, (size_t)C * C * 8, &dcov));
         HIP_TRY(launch_cov(X, C, N, dmu, dcov, s));
@@ -803,12 +803,10 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
         HIP_TRY(hipStreamSynchronize(s));
         m->evals.assign(C, 0.0);
         // 2. eigenvectors of the k largest eigenvalues (host, FP64)
-        if (sym_eig(cov.data(), C, m->evals.data(), vecs.data()) != 0)
+        if (sym_eig_top(cov.data(), C, k, m->evals.data(), vecs.data()) != 0)
             return fail(QFCA_E_DEVICE, "eigensolver did not converge");
         m->has_evals = true;
-        m->V.assign((size_t)C * k, 0.0);
-        for (int c = 0; c < C; ++c)
-            for (int j = 0; j < k; ++j) m->V[(size_t)c * k + j] = vecs[(size_t)c * C + j];
+        m->V = vecs;  // [C][k], column j the eigenvector of the j-th largest eigenvalue
     } else {
         std::fill(m->mu.begin(), m->mu.end(), 0.0);
     }

@@ -2,7 +2,13 @@
 // step (Sec. 3.3).  The problem is tiny next to the feature map (C <= 2048),
 // so it runs on the host: Householder reduction to tridiagonal form, then the
 // implicit QL iteration with shifts (Bowdler, Martin, Reinsch and Wilkinson,
-// 1968) applied to the accumulated orthogonal transform.
+// 1968).  sym_eig accumulates the whole orthogonal transform; sym_eig_top,
+// which the fit uses, keeps the reflectors instead, takes all eigenvalues
+// from QL without vectors, the k leading eigenvectors of the tridiagonal
+// matrix by inverse iteration (Wilkinson; vectors of close eigenvalues
+// orthogonalised against each other, as in LAPACK's dstein), and applies the
+// reflectors to those k vectors only: O(C^3) for the reduction instead of
+// the several C^3 of accumulating every rotation.
 //
 // Host code only, compiled as plain C++ (no device pass).
 #include <math.h>
@@ -17,14 +23,22 @@ namespace qfca {
 
 // Declared for the library in qfca_internal.h.
 int sym_eig(double* A, int n, double* evals, double* vecs);
+int sym_eig_top(double* A, int n, int k, double* evals, double* vecs);
 
 namespace {
 
 // Reduce symmetric A (n x n, row-major, destroyed) to tridiagonal T = Q^T A Q.
-// d[i] = T[i][i], e[i] = T[i][i+1] (e[n-1] = 0), Q row-major.
-void householder_tridiag(double* A, int n, double* d, double* e, double* Q) {
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) Q[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
+// d[i] = T[i][i], e[i] = T[i][i+1] (e[n-1] = 0).  Q = H_0 H_1 ... H_{n-3},
+// H_k = I - beta_k v_k v_k^T acting on indices k+1 .. n-1: accumulated
+// row-major into Q when Q is given; when H is given, v_k is kept in
+// H[k n + k + 1 ..] and beta_k in beta[k] (0 for a skipped step).
+void householder_tridiag(double* A, int n, double* d, double* e, double* Q, double* H = nullptr,
+                         double* beta_out = nullptr) {
+    if (Q)
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) Q[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
+    if (beta_out)
+        for (int i = 0; i < n; ++i) beta_out[i] = 0.0;
     std::vector<double> v(n), p(n), qv(n);
     for (int k = 0; k + 2 < n; ++k) {
         const int len = n - k - 1;  // entries A[k+1..n-1][k]
@@ -65,6 +79,11 @@ void householder_tridiag(double* A, int n, double* d, double* e, double* Q) {
             A[(size_t)(k + 1 + t) * n + k] = 0.0;
             A[(size_t)k * n + (k + 1 + t)] = 0.0;
         }
+        if (H) {
+            for (int t = 0; t < len; ++t) H[(size_t)k * n + k + 1 + t] = v[t];
+            beta_out[k] = beta;
+        }
+        if (!Q) continue;
         // Q[:, k+1..] <- Q[:, k+1..] (I - beta v v^T)
         for (int rI = 0; rI < n; ++rI) {
             double* row = Q + (size_t)rI * n + (k + 1);
@@ -80,19 +99,25 @@ void householder_tridiag(double* A, int n, double* d, double* e, double* Q) {
     }
 }
 
-// Implicit QL on the tridiagonal (d, e); ZT accumulates the rotations, held
-// transposed (row i of ZT is column i of the transform) so that each
-// rotation updates two contiguous rows.  Returns 0 on success, -1 if an
-// eigenvalue fails to converge.
+// Implicit QL on the tridiagonal (d, e); ZT, when given, accumulates the
+// rotations, held transposed (row i of ZT is column i of the transform) so
+// that each rotation updates two contiguous rows.  Returns 0 on success, -1
+// if an eigenvalue fails to converge.
 int tridiag_ql(double* d, double* e, int n, double* ZT) {
     const double eps = 2.220446049250313e-16;
+    // An off-diagonal entry is negligible next to its diagonal neighbours or,
+    // as in EISPACK's tql2, next to the matrix norm: without the latter a
+    // cluster of (numerically) zero eigenvalues, whose entries are all
+    // rounding noise, never deflates.
+    double tnorm = 0.0;
+    for (int i = 0; i < n; ++i) tnorm = std::max(tnorm, fabs(d[i]) + fabs(e[i]));
     for (int l = 0; l < n; ++l) {
         int iter = 0;
         for (;;) {
             int m = l;
             for (; m + 1 < n; ++m) {
                 const double dd = fabs(d[m]) + fabs(d[m + 1]);
-                if (fabs(e[m]) <= eps * dd) break;
+                if (fabs(e[m]) <= eps * dd || fabs(e[m]) <= eps * tnorm) break;
             }
             if (m == l) break;
             if (++iter > 100) return -1;
@@ -120,6 +145,7 @@ int tridiag_ql(double* d, double* e, int n, double* ZT) {
                 p = s * rr;
                 d[i + 1] = g + p;
                 g = c * rr - b;
+                if (!ZT) continue;
                 double* __restrict__ zi = ZT + (size_t)i * n;
                 double* __restrict__ zj = ZT + (size_t)(i + 1) * n;
                 for (int k = 0; k < n; ++k) {
@@ -137,7 +163,139 @@ int tridiag_ql(double* d, double* e, int n, double* ZT) {
     return 0;
 }
 
+// One solve of (T - sigma I) x = b for the symmetric tridiagonal T = (d, e)
+// by Gaussian elimination with partial pivoting (the factor has up to two
+// superdiagonals); a zero pivot is replaced by `tiny`.  b is overwritten.
+struct TridiagLU {
+    std::vector<double> u0, u1, u2, l;
+    std::vector<char> piv;
+    void factor(const double* d, const double* e, int n, double sigma, double tiny) {
+        u0.assign(n, 0.0); u1.assign(n, 0.0); u2.assign(n, 0.0); l.assign(n, 0.0); piv.assign(n, 0);
+        double ad = d[0] - sigma, au = n > 1 ? e[0] : 0.0;  // the pending row: columns i, i + 1
+        for (int i = 0; i + 1 < n; ++i) {
+            const double cc = e[i], ad1 = d[i + 1] - sigma, au1 = (i + 2 < n) ? e[i + 1] : 0.0;
+            if (fabs(cc) > fabs(ad)) {  // row i + 1 becomes the pivot row
+                const double mult = ad / cc;
+                u0[i] = cc; u1[i] = ad1; u2[i] = au1;
+                l[i] = mult; piv[i] = 1;
+                ad = au - mult * ad1;
+                au = -mult * au1;
+            } else {
+                if (ad == 0.0) ad = tiny;
+                const double mult = cc / ad;
+                u0[i] = ad; u1[i] = au; u2[i] = 0.0;
+                l[i] = mult; piv[i] = 0;
+                ad = ad1 - mult * au;
+                au = au1;
+            }
+        }
+        u0[n - 1] = (ad == 0.0) ? tiny : ad;
+    }
+    void solve(double* b, int n) const {
+        for (int i = 0; i + 1 < n; ++i) {
+            if (piv[i]) {
+                const double bi = b[i];
+                b[i] = b[i + 1];
+                b[i + 1] = bi - l[i] * b[i];
+            } else {
+                b[i + 1] -= l[i] * b[i];
+            }
+        }
+        b[n - 1] /= u0[n - 1];
+        if (n > 1) b[n - 2] = (b[n - 2] - u1[n - 2] * b[n - 1]) / u0[n - 2];
+        for (int i = n - 3; i >= 0; --i) b[i] = (b[i] - u1[i] * b[i + 1] - u2[i] * b[i + 2]) / u0[i];
+    }
+};
+
+double norm2(const double* x, int n) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += x[i] * x[i];
+    return sqrt(s);
+}
+
 }  // namespace
+
+int sym_eig_top(double* A, int n, int k, double* evals, double* vecs) {
+    if (n <= 0 || k < 0 || k > n) return -1;
+    std::vector<double> A0(A, A + (size_t)n * n);  // for the fallback below
+    // When the inverse iteration cannot deliver (a large cluster of zero
+    // eigenvalues among the k leading ones, whose solves overflow), the full
+    // solver runs instead; such a cluster's vectors are any basis of it.
+    auto fallback = [&]() -> int {
+        std::vector<double> all((size_t)n * n);
+        if (sym_eig(A0.data(), n, evals, all.data()) != 0) return -1;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < k; ++j) vecs[(size_t)i * k + j] = all[(size_t)i * n + j];
+        return 0;
+    };
+    std::vector<double> d(n), e(n), H((size_t)n * n, 0.0), beta(n, 0.0);
+    householder_tridiag(A, n, d.data(), e.data(), nullptr, H.data(), beta.data());
+    std::vector<double> dt(d), et(e);  // T, kept for the inverse iteration
+    if (tridiag_ql(d.data(), e.data(), n, nullptr) != 0) return -1;
+    std::sort(d.begin(), d.end(), [](double a, double b) { return a > b; });
+    for (int j = 0; j < n; ++j) evals[j] = d[j];
+    if (k == 0) return 0;
+    double tnorm = 0.0;  // max row sum of |T|
+    for (int i = 0; i < n; ++i)
+        tnorm = std::max(tnorm, fabs(dt[i]) + (i > 0 ? fabs(et[i - 1]) : 0.0) + (i + 1 < n ? fabs(et[i]) : 0.0));
+    if (tnorm == 0.0) tnorm = 1.0;
+    const double eps = 2.220446049250313e-16;
+    const double ortol = 1e-3 * tnorm;  // eigenvalues this close form a cluster
+    const double tiny = eps * tnorm;
+    std::vector<double> X((size_t)k * n);  // eigenvectors of T, one per row
+    TridiagLU lu;
+    int cl0 = 0;  // first vector of the current cluster
+    double sigma_prev = 0.0;
+    uint64_t rng = 0x9E3779B97F4A7C15ull;
+    for (int j = 0; j < k; ++j) {
+        double sigma = d[j];
+        if (j > 0 && d[j - 1] - d[j] > ortol) cl0 = j;
+        // equal eigenvalues get slightly different shifts (then each solve
+        // favours a different direction; the orthogonalisation does the rest)
+        if (j > cl0 && sigma_prev - sigma < 10.0 * eps * std::max(fabs(sigma), tnorm))
+            sigma = sigma_prev - 10.0 * eps * std::max(fabs(sigma), tnorm);
+        sigma_prev = sigma;
+        lu.factor(dt.data(), et.data(), n, sigma, tiny);
+        double* x = X.data() + (size_t)j * n;
+        for (int i = 0; i < n; ++i) {  // fixed pseudo-random start (xorshift)
+            rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17;
+            x[i] = (double)(rng >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        }
+        for (int it = 0; it < 4; ++it) {
+            lu.solve(x, n);
+            for (int q = cl0; q < j; ++q) {  // modified Gram-Schmidt within the cluster
+                const double* y = X.data() + (size_t)q * n;
+                double s = 0.0;
+                for (int i = 0; i < n; ++i) s += y[i] * x[i];
+                for (int i = 0; i < n; ++i) x[i] -= s * y[i];
+            }
+            const double nr = norm2(x, n);
+            if (!(nr > 0.0) || !isfinite(nr)) return fallback();
+            for (int i = 0; i < n; ++i) x[i] /= nr;
+        }
+    }
+    // back to the basis of A: y = H_0 H_1 ... H_{n-3} x, sign fixed so that the
+    // entry of largest magnitude is positive
+    std::vector<double> y(n);
+    for (int j = 0; j < k; ++j) {
+        const double* x = X.data() + (size_t)j * n;
+        for (int i = 0; i < n; ++i) y[i] = x[i];
+        for (int s = n - 3; s >= 0; --s) {
+            if (beta[s] == 0.0) continue;
+            const double* v = H.data() + (size_t)s * n;
+            double dot = 0.0;
+            for (int i = s + 1; i < n; ++i) dot += v[i] * y[i];
+            dot *= beta[s];
+            for (int i = s + 1; i < n; ++i) y[i] -= dot * v[i];
+        }
+        int arg = 0;
+        for (int i = 1; i < n; ++i)
+            if (fabs(y[i]) > fabs(y[arg])) arg = i;
+        const double sg = y[arg] < 0.0 ? -1.0 : 1.0;
+        for (int i = 0; i < n; ++i) vecs[(size_t)i * k + j] = sg * y[i];
+    }
+    return 0;
+}
 
 int sym_eig(double* A, int n, double* evals, double* vecs) {
     if (n <= 0) return -1;
@@ -168,4 +326,8 @@ int sym_eig(double* A, int n, double* evals, double* vecs) {
 
 extern "C" int qfca_host_sym_eig(double* A, int32_t n, double* evals, double* vecs) {
     return qfca::sym_eig(A, n, evals, vecs);
+}
+
+extern "C" int qfca_host_sym_eig_top(double* A, int32_t n, int32_t k, double* evals, double* vecs) {
+    return qfca::sym_eig_top(A, n, k, evals, vecs);
 }

@@ -183,5 +183,7 @@ hipError_t launch_select(const float* vals, int C, long N, const long long* rank
 // Host FP64 symmetric eigensolver: A [n][n] row-major (destroyed); evals
 // descending; vecs [n][n] row-major with column j the j-th eigenvector.
 int sym_eig(double* A, int n, double* evals, double* vecs);
+// The same eigenvalues with only the k leading eigenvectors: vecs [n][k].
+int sym_eig_top(double* A, int n, int k, double* evals, double* vecs);
 
 }  // namespace qfca

@@ -73,3 +73,49 @@ def test_model_serialisation_rejects_bad_arguments_without_a_gpu():
     blob = ctypes.create_string_buffer(b"QFCAMDL\0" + bytes(64))
     assert L.qfca_model_import(None, blob, 72, ctypes.byref(h)) == 1
     assert not h.value
+
+
+def _spectra():
+    g = np.random.Generator(np.random.PCG64(17))
+    n = 96
+    Q, _ = np.linalg.qr(g.standard_normal((n, n)))
+    M = g.standard_normal((n, 3 * n))
+    R = g.standard_normal((n, 10))
+    return {
+        "wishart": (M @ M.T / M.shape[1], 24),
+        "rank 10 < k": (R @ R.T, 24),
+        "equal leading eigenvalues": ((Q * np.r_[[5.0] * 4, [3.0] * 6, np.linspace(2, 0.1, n - 10)]) @ Q.T, 24),
+        "cluster across k": ((Q * np.r_[[5.0] * 30, np.linspace(2, 0.1, n - 30)]) @ Q.T, 24),
+        "near-null tail": ((Q * np.r_[np.linspace(5, 4, 8), [1e-9] * (n - 8)]) @ Q.T, 24),
+        "zero matrix": (np.zeros((6, 6)), 3),
+    }
+
+
+@pytest.mark.parametrize("name", list(_spectra()))
+def test_host_top_k_eigensolver_against_eigh(name):
+    """The fit's eigensolver: all eigenvalues, and k orthonormal vectors that
+    are eigenvectors (A v = lambda v) of the k largest, on spectra with equal
+    eigenvalues, clusters across k and rank below k."""
+    A, k = _spectra()[name]
+    ev, V = q.host_sym_eig_top(A, k)
+    w = np.linalg.eigvalsh(A)[::-1]
+    sc = max(np.abs(w).max(), 1.0)
+    np.testing.assert_allclose(ev, w, atol=1e-12 * sc)
+    np.testing.assert_allclose(V.T @ V, np.eye(k), atol=1e-12)
+    np.testing.assert_allclose(A @ V, V * ev[:k], atol=1e-11 * sc)
+    # the sign convention of the full solver: largest-magnitude entry positive
+    assert np.all(V[np.abs(V).argmax(axis=0), np.arange(k)] > 0)
+
+
+def test_host_full_eigensolver_rank_deficient():
+    """A covariance of rank below its size (fewer pixels than channels): the
+    cluster of zero eigenvalues must deflate (QL tested against the matrix
+    norm as well as the neighbouring diagonal)."""
+    g = np.random.Generator(np.random.PCG64(3))
+    R = g.standard_normal((128, 12))
+    A = R @ R.T
+    ev, V = q.host_sym_eig(A)
+    w = np.linalg.eigvalsh(A)[::-1]
+    np.testing.assert_allclose(ev, w, atol=1e-12 * w[0])
+    np.testing.assert_allclose(V.T @ V, np.eye(128), atol=1e-12)
+    np.testing.assert_allclose(A @ V, V * ev, atol=1e-11 * w[0])

@@ -294,3 +294,25 @@ def test_quantize_bf16_flip_rate_256(ctx, oracle_256):
     err = np.abs(out.score.cpu().numpy() - ref.score).max() / np.abs(ref.score).max()
     say(f"  bf16 flip rate {flips:.4%}, max score error {err:.3e} of max score")
     assert flips < 0.05 and err < 0.05
+
+
+def test_fit_with_fewer_pixels_than_channels(ctx):
+    """C = 256 channels over a 14 x 15 map (210 pixels): the covariance has
+    rank below C, so its eigenvalue tail is a cluster of zeros.  The fit must
+    converge and agree with the oracle's subspace and eigenvalues."""
+    C, H, W, k, B, T = 256, 14, 15, 16, 8, 5
+    g = np.random.Generator(np.random.PCG64(210))
+    X = (g.standard_normal((C, 24)) @ g.standard_normal((24, H * W)) +
+         0.05 * g.standard_normal((C, H * W))).reshape(C, H, W).astype(np.float32)
+    say(f"[fit rank-deficient] C={C} {H}x{W} k={k}")
+    om, R, obins = oracle.fit(X, k, B, T)
+    m = q.qfca_fit_pca(ctx, q.Params.make(C=C, k=k, B=B, T=T), torch.from_numpy(X).cuda())
+    ev = m.read("evals")
+    np.testing.assert_allclose(ev, om.evals, rtol=0, atol=1e-9 * ev[0])
+    V = m.read("V").astype(np.float64)
+    assert om.evals[k - 1] - om.evals[k] > 1e-6 * om.evals[0]
+    assert np.abs(V @ V.T - om.V @ om.V.T).max() <= 1e-5
+    gb, _ = q.qfca_quantize(ctx, m, torch.from_numpy(X).cuda())
+    flips = int((gb.cpu().numpy() != obins).sum())
+    say(f"  bins differing from the FP64 oracle: {flips} of {obins.size}")
+    assert flips <= 1e-3 * obins.size
