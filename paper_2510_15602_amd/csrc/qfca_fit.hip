@@ -174,6 +174,8 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
     const uint8_t* bc = a.bins + (size_t)(cv ? c : 0) * H * W;
     uint8_t* vc = smem;                                          // [WbMax][64]
     uint16_t* cnt = (uint16_t*)(smem + ((WbMax * 64 + 15) & ~15));  // [S][per][m+1]
+    // the rows entering and leaving the windows, staged per row: [2][S][WbMax]
+    uint8_t* rows = (uint8_t*)(cnt + (size_t)S * per * (m + 1));
     for (int t = lane; t < WbMax * 16; t += 64) ((uint32_t*)vc)[t] = 0u;
     for (int t = lane; t < S * per * (m + 1); t += 64) cnt[t] = 0;
     __syncthreads();
@@ -188,16 +190,29 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
                 const int xl = xb0 + q;
                 if (xl >= 0 && xl < W) vc[q * 64 + lane] += (bc[(size_t)yy * W + xl] <= j) ? 1 : 0;
             }
+        const uint8_t* rowa = rows + (size_t)sa * WbMax;
+        const uint8_t* rowr = rows + (size_t)(S + sa) * WbMax;
         for (int yc = ys; yc < yend; ++yc) {
             const int ya = yc + r, yr = yc - r - 1;
             const bool rem = yc > ys;
+            // one coalesced load of both rows for the S channels, then LDS reads
+            __syncthreads();
+            for (int t = lane; t < 2 * S * Wb; t += 64) {
+                const int h = t / (S * Wb), rest = t - h * S * Wb;
+                const int ss = rest / Wb, q = rest - ss * Wb;
+                const int cc = cbase + ss, xl = xb0 + q, yy = h ? yr : ya;
+                uint8_t v = 0;
+                if (cc < a.C && xl >= 0 && xl < W && yy >= 0) v = a.bins[((size_t)cc * H + yy) * W + xl];
+                rows[(size_t)(h * S + ss) * WbMax + q] = v;
+            }
+            __syncthreads();
             int cP = 0;
             for (int q = 0; q < Wb; ++q) {
                 const int xl = xb0 + q;
                 int v = 0;
                 if (xl >= 0 && xl < W) {
-                    v = vc[q * 64 + lane] + ((bc[(size_t)ya * W + xl] <= j) ? 1 : 0);
-                    if (rem) v -= (bc[(size_t)yr * W + xl] <= j) ? 1 : 0;
+                    v = vc[q * 64 + lane] + ((rowa[q] <= j) ? 1 : 0);
+                    if (rem) v -= (rowr[q] <= j) ? 1 : 0;
                     vc[q * 64 + lane] = (uint8_t)v;
                 }
                 const int vold = (q >= T) ? (int)vc[(q - T) * 64 + lane] : 0;
@@ -340,7 +355,7 @@ hipError_t launch_refcount(const uint8_t* bins, int C, int H, int W, int T, int 
     int S = 64 / Bp, nsplit = 1;
     auto lds = [&](int S_, int ns_) {
         const size_t WbMax = (size_t)a.Ws + 2 * a.r;
-        return ((WbMax * 64 + 15) & ~size_t(15)) + (size_t)S_ * (Bp / ns_) * (a.m + 1) * 2;
+        return ((WbMax * 64 + 15) & ~size_t(15)) + (size_t)S_ * (Bp / ns_) * (a.m + 1) * 2 + 2 * (size_t)S_ * WbMax;
     };
     while (lds(S, nsplit) > 60000 && S > 1) S >>= 1;
     while (lds(S, nsplit) > 60000 && nsplit < Bp) nsplit <<= 1;
