@@ -356,6 +356,20 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                 c0 = __builtin_amdgcn_sad_u8(vw[(T - 1) / 4] & ((1u << (8 * ((T - 1) % 4))) - 1u), 0u, c0);
         }
         int cpb = 4 * (int)c0 + bias;
+        // Block blk reads the count bytes [blk TP, blk TP + TP + T - 1) of the
+        // lane's row, which the next block's range overlaps by TP bytes: a
+        // window of 2 TPD dwords is kept in registers, and the TPD dwords the
+        // next block adds are loaded while this block computes (the counts do
+        // not change during the walk).  Windows above T = 21 would not fit the
+        // registers; they read the bytes from LDS in each block.
+        constexpr bool WIN = T <= 21;
+        constexpr int TPD = TP / 4;
+        const uint32_t* vw = vc32 + lane * L.vs4;
+        uint32_t win[WIN ? 2 * TPD : 1], nxt[WIN ? TPD : 1];
+        if constexpr (WIN) {
+#pragma unroll
+            for (int i = 0; i < 2 * TPD; ++i) win[i] = vw[i];
+        }
         int ent0 = 0;  // count that entered at step k = 0 of the previous block
         float suf[T];  // suffix sums of the previous block's errors (suf[k] = sum over k' >= k)
 #pragma unroll
@@ -385,15 +399,25 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                     gacc[it] = *dst;
                 }
             }
+            if (WIN && blk + 1 < nblk) {
+#pragma unroll
+                for (int i = 0; i < TPD; ++i) nxt[WIN ? i : 0] = vw[(blk + 2) * TPD + i];
+            }
             // 1. counts entering and leaving the window, running cumulative counts
             int cpv[T], cmv[T];
             const uint8_t* vb = vcl + blk * TP;
+            auto vbyte = [&](int q) {
+                if constexpr (WIN)
+                    return (int)((win[q >> 2] >> (8 * (q & 3))) & 0xFFu);
+                else
+                    return (int)vb[q];
+            };
 #pragma unroll
             for (int k = 0; k < T; ++k) {
                 // entering: bin column i0 + k + 2r = (blk + 1) T + k - 1;
                 // leaving:  bin column i0 + k - 1 = blk T + k - 1
-                const int ve = (k == 0) ? (int)vb[T - 1] : (int)vb[TP + k - 1];
-                const int vl = (k == 0) ? ent0 : (int)vb[k - 1];
+                const int ve = (k == 0) ? vbyte(T - 1) : vbyte(TP + k - 1);
+                const int vl = (k == 0) ? ent0 : vbyte(k - 1);
                 if (k == 0) ent0 = ve;
                 cpb += (ve - vl) << 2;
                 cpv[k] = cpb;
@@ -504,6 +528,13 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                 }
             }
             wave_sync();
+            if constexpr (WIN) {
+#pragma unroll
+                for (int i = 0; i < TPD; ++i) {
+                    win[i] = win[TPD + i];
+                    win[TPD + i] = nxt[i];
+                }
+            }
         }
         // the pending rows move down by one
 #pragma unroll
