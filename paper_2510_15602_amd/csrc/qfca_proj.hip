@@ -23,6 +23,7 @@
 //   K step u supplies components 16 (2 u + t / 4) + 4 g + (t % 4).
 // The subtraction, the comparisons with the edges and all counting stay FP32.
 #include <algorithm>
+#include <atomic>
 
 #include "qfca_internal.h"
 #include "qfca_tiles.h"
@@ -246,14 +247,35 @@ constexpr size_t LDS_TWO_BLOCKS = 80 * 1024;
 
 // Launches a persistent grid: as many blocks as fit on the device (at most
 // two per compute unit, the register limit), never more than there are tiles.
+// Compute units of the current device, queried once per device; callers may
+// launch from several host threads.
+hipError_t device_cus(int* out) {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev >= 0 && dev < 64) {
+        const int v = cache[dev].load(std::memory_order_relaxed);
+        if (v > 0) {
+            *out = v;
+            return hipSuccess;
+        }
+    }
+    int n = 0;
+    e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    if (n < 1) return hipErrorInvalidValue;
+    if (dev >= 0 && dev < 64) cache[dev].store(n, std::memory_order_relaxed);
+    *out = n;
+    return hipSuccess;
+}
+
 template <class K>
 hipError_t go(K kern, const MArgs& a, size_t lds, hipStream_t st) {
-    static int ncu = 0;
-    if (!ncu) {
-        int dev = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess || ncu < 1) return e != hipSuccess ? e : hipErrorInvalidValue;
+    int ncu = 0;
+    {
+        const hipError_t e = device_cus(&ncu);
+        if (e != hipSuccess) return e;
     }
     if (lds > LDS_MAX) return hipErrorInvalidValue;
     if (lds > 65536) {
