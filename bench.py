@@ -247,8 +247,8 @@ def serving_leg(args, q, torch, np, dev, tile=None):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures a single GPU; run it with --gpus 1 (multi-GPU runs are not part of "
-              "this build).", file=sys.stderr)
+        print("bench.py measures one GPU only (images shard across GPUs with no exchange; there is no "
+              "multi-GPU run): use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

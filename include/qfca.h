@@ -45,7 +45,7 @@ typedef enum {
     QFCA_E_DEVICE = 4,       /* a HIP call failed; recreate the context */
     QFCA_E_STATE = 5,        /* model not ready for this call (e.g. no reference yet) */
     QFCA_E_NONFINITE = 6,    /* NaN or Inf met where the fit needs finite values */
-    QFCA_E_UNSUPPORTED = 7   /* parameters outside what this build implements */
+    QFCA_E_UNSUPPORTED = 7   /* parameters outside what the library implements */
 } qfca_status;
 
 enum { QFCA_PRE_NONE = 0,       /* plain QFCA: histogram the features as given */
