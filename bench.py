@@ -126,7 +126,7 @@ def batched_leg(args, q, torch, np, dev):
         q.qfca_score_batch(ctx, jobs)
     torch.cuda.synchronize()
     ctx.profile_read("score")
-    ctx.profile(True)
+    ctx.profile(True, kernels=["score"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.batch_steps):
@@ -291,7 +291,9 @@ def main():
     torch.cuda.synchronize()
     for k in q.KERNELS:
         ctx.profile_read(k)
-    ctx.profile(True)
+    # HIP events around the dominant kernel only inside the timed region (the
+    # roofline's duration); the other kernels are timed in a pass after it
+    ctx.profile(True, kernels=["score"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -299,7 +301,16 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.profile(False)
-    kt = {k: ctx.profile_read(k) for k in q.KERNELS}
+    kt = {"score": ctx.profile_read("score")}
+    ctx.profile(True)
+    for _ in range(min(args.steps, 20)):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    for k in q.KERNELS:
+        v = ctx.profile_read(k)
+        if k != "score":
+            kt[k] = v
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = H * W / (ms_per_step * 1e-3) / 1e6
 

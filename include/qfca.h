@@ -87,9 +87,11 @@ qfca_status qfca_ctx_create(int32_t device, void* hip_stream, qfca_ctx* out);
 qfca_status qfca_ctx_set_stream(qfca_ctx ctx, void* hip_stream);
 qfca_status qfca_ctx_destroy(qfca_ctx ctx);
 
-/* Per-kernel timing for benchmarking: when enabled, the library records a
- * pair of HIP events on the context's stream around every launch of the
- * kernels below (a few microseconds of overhead per launch).
+/* Per-kernel timing for benchmarking: the library records a pair of HIP
+ * events on the context's stream around every launch of the selected
+ * kernels below (a few microseconds of overhead per launch).  enable: 0
+ * turns timing off, -1 times every kernel, any other value is a bitmask
+ * (bit k selects kernel id k).
  * qfca_ctx_profile_read synchronises on the recorded events and returns the
  * summed duration (ms) and the number of launches of one kernel since the
  * previous read, then resets that kernel's record.  Kernel ids:

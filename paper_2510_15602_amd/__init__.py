@@ -194,8 +194,10 @@ class Context:
         """Pin the score kernel's tile (Ws=0 restores the automatic choice)."""
         _check(lib().qfca_ctx_set_tile(self.handle, int(Ws), int(Hb), int(S), int(variant)))
 
-    def profile(self, enable: bool = True):
-        _check(lib().qfca_ctx_profile(self.handle, int(bool(enable))))
+    def profile(self, enable: bool = True, kernels=None):
+        """Event timing of every kernel, or of the named ones (see KERNELS)."""
+        mask = 0 if not enable else (-1 if kernels is None else sum(1 << KERNELS[k] for k in kernels))
+        _check(lib().qfca_ctx_profile(self.handle, mask))
 
     def profile_read(self, kernel: str):
         """(total_ms, launches) of one kernel since the previous read."""

@@ -38,7 +38,7 @@ struct qfca_ctx_s {
     DevBuf scratch[SL_COUNT];
     std::map<long long, ScoreTile> tiles;  // tile-configuration cache
     ScoreTile tile_override{0, 0, 0, 0};   // Ws == 0: automatic
-    bool profiling = false;
+    uint32_t profile_mask = 0;  // bit k: time kernel k
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[K_COUNT];
     std::vector<hipEvent_t> event_pool;
     // batched path
@@ -319,7 +319,7 @@ struct KernelTimer {
     int kernel;
     hipEvent_t a = nullptr, b = nullptr;
     KernelTimer(qfca_ctx c, int k) : ctx(c), kernel(k) {
-        if (ctx->profiling) {
+        if (ctx->profile_mask & (1u << kernel)) {
             a = take_event(ctx);
             b = take_event(ctx);
             if (a) (void)hipEventRecord(a, ctx->stream);
@@ -422,7 +422,7 @@ qfca_status qfca_ctx_set_tile(qfca_ctx ctx, int32_t Ws, int32_t Hb, int32_t S, i
 
 qfca_status qfca_ctx_profile(qfca_ctx ctx, int32_t enable) {
     if (!ctx) return fail(QFCA_E_ARG, "ctx is NULL");
-    ctx->profiling = enable != 0;
+    ctx->profile_mask = (uint32_t)enable;
     return QFCA_OK;
 }
 
