@@ -252,16 +252,32 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     // bytes and its top bit is set exactly when b <= j.  ADD / REM select at
     // compile time whether a row enters and whether one leaves.
     const uint32_t jhi = ((uint32_t)j * 0x01010101u) | 0x80808080u;
+    // The ring rows and the lane's count row never overlap: declared so, and
+    // taken in chunks whose loads are all issued before any store, so a row
+    // costs a few LDS round trips rather than one per dword.
     auto update_vc = [&](int ya, int yr, auto addc, auto remc) {
         constexpr bool ADD = decltype(addc)::value, REM = decltype(remc)::value;
-        const uint32_t* ra = (const uint32_t*)(ring + (size_t)(ya % T1) * nlb + sa * rowb);
-        const uint32_t* rr = (const uint32_t*)(ring + (size_t)((yr + T1) % T1) * nlb + sa * rowb);
-        uint32_t* v = vc32 + lane * L.vs4;
-        for (int d = 0; d < rowb / 4; ++d) {
-            uint32_t x = v[d];
-            if (ADD) x += ((jhi - ra[d]) & 0x80808080u) >> 7;
-            if (REM) x -= ((jhi - rr[d]) & 0x80808080u) >> 7;
-            v[d] = x;
+        const uint32_t* __restrict__ ra = (const uint32_t*)(ring + (size_t)(ya % T1) * nlb + sa * rowb);
+        const uint32_t* __restrict__ rr = (const uint32_t*)(ring + (size_t)((yr + T1) % T1) * nlb + sa * rowb);
+        uint32_t* __restrict__ v = vc32 + lane * L.vs4;
+        const int nd = rowb / 4;
+        constexpr int CH = 8;
+        for (int d0 = 0; d0 < nd; d0 += CH) {
+            uint32_t xv[CH], xa[CH], xr[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int d = min(d0 + i, nd - 1);  // the tail rereads the last dword
+                xv[i] = v[d];
+                if (ADD) xa[i] = ra[d];
+                if (REM) xr[i] = rr[d];
+            }
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                uint32_t x = xv[i];
+                if (ADD) x += ((jhi - xa[i]) & 0x80808080u) >> 7;
+                if (REM) x -= ((jhi - xr[i]) & 0x80808080u) >> 7;
+                if (d0 + i < nd) v[d0 + i] = x;
+            }
         }
     };
 
