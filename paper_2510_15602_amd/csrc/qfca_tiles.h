@@ -329,6 +329,28 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     const uint32_t gstep0 = (uint32_t)nlb << 16, gwrap0 = (uint32_t)(T1 * nlb) << 16;
     const uint32_t gstep1 = (uint32_t)(S * Ws) << 16, gwrap1 = (uint32_t)(T * S * Ws) << 16;
 
+    // Output slots of a row, t = lane + 64 i over the S x ws outputs, fixed for
+    // the tile: accumulator offset in a row (bit 31: the channel exists),
+    // offset from the group's first channel at the row in achan, and
+    // delta_c / n_x for the slot's column (a row adds 1 / n_y).
+    constexpr int OSL = 4;
+    const int nout = S * ws;
+    const bool ofast = (nout <= 64 * OSL) && ((long long)S * H * W < 0x7FFFFFFFLL);
+    uint32_t oacc[OSL];
+    int oglb[OSL];
+    double osc[OSL];
+#pragma unroll
+    for (int i = 0; i < OSL; ++i) {
+        const int t = lane + 64 * i;
+        const int ss = ofast ? t / ws : 0, xo = t - ss * ws;
+        const int cc = cbase + ss, xg = x0 + xo;
+        const bool ok = ofast && t < nout && cc < a.C;
+        const int nxo = min(W - 1, xg + r) - max(0, xg - r) + 1;
+        oacc[i] = (uint32_t)(ss * Ws + xo) | (ok ? 0x80000000u : 0u);
+        oglb[i] = ss * H * W + xg;
+        osc[i] = ok ? a.delta[cc] / (double)nxo : 0.0;
+    }
+
     for (int yy = lo_add; yy < hi_add; ++yy) {
         load_row(yy);
         wave_sync();
@@ -569,6 +591,20 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
         yo_hi = min(yo_hi, ye - 1);
         for (int yo = yo_lo; yo <= yo_hi; ++yo) {
             const int nyo = min(H - 1, yo + r) - max(0, yo - r) + 1;
+            if (ofast) {
+                float* ar = acc + (yo % T) * S * Ws;
+                float* gr = a.achan + ((size_t)cbase * H + yo) * W;
+                const double rny = 1.0 / (double)nyo;
+#pragma unroll
+                for (int i = 0; i < OSL; ++i) {
+                    if (lane + 64 * i < nout) {
+                        float* ap = ar + (oacc[i] & 0x7FFFFFFFu);
+                        if (oacc[i] >> 31) gr[oglb[i]] = (float)((double)(*ap) * osc[i] * rny);
+                        *ap = 0.f;
+                    }
+                }
+                continue;
+            }
             for (int t = lane; t < S * ws; t += 64) {
                 const int ss = t / ws, xo = t - ss * ws;
                 const int cc = cbase + ss;
