@@ -484,32 +484,64 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                     ev[k] = (float)I4 * rc[k];
                 }
             } else {
+                // Windows clipped at the image border (or rows with fewer than
+                // T window rows): the general equal-mass form.  Columns go in
+                // groups of G whose table reads are issued together, so a group
+                // costs one round of LDS reads instead of several per column;
+                // q = floor(a / n) comes from a reciprocal estimate corrected to
+                // the exact integer (the estimate is within one of it).
                 const float* rcf = rcp4;
+                constexpr int G = (T <= 8) ? T : 5;
 #pragma unroll
-                for (int k = 0; k < T; ++k) {
-                    const int i = i0 + k;
-                    const int p = x0 - r + i;
-                    const bool pval = (i < np) && (p >= 0) && (p < W);
-                    const int nx = max(1, min(W - 1, p + r) - max(0, p - r) + 1);
-                    const int n = ny * nx;
-                    const int cPk = (cpv[k] - bias) >> 2, cPm1 = (cmv[k] - bias) >> 2;
-                    const int av = __mul24(cPk, m);
-                    int q0d = (int)((float)av * (4.f * rcf[min(n, m)]));
-                    q0d = max(0, min(q0d, m));
-                    if (q0d < m && __mul24(q0d + 1, n) <= av) q0d++;
-                    if (q0d > 0 && __mul24(q0d, n) > av) q0d--;
-                    const int* pq = psl + q0d;
-                    const int ps0 = pq[0], ps1 = pq[1];  // 4 Psi(q), 4 Psi(q + 1)
-                    const int phia = __mul24(n, ps0) + __mul24(av - __mul24(q0d, n), ps1 - ps0);
-                    const int pu = lane_prev(phia);
-                    const int phiu = j0 ? 0 : pu;
-                    const int au = __mul24(cPm1, m);
-                    const int cm = __mul24(crm1, n);
-                    const int sc = min(max(cm, au), av);
-                    const int phis = (cm <= au) ? phiu : ((cm >= av) ? phia : __mul24(n, dm1_4));
-                    const int I4 = (phia - phis) + (phiu - phis) + __mul24(4 * j, 2 * sc - au - av);
-                    const int P = min(max(cPk - cPm1, 0), m);
-                    ev[k] = pval ? (float)I4 * rcf[P] * inv_m : 0.f;
+                for (int k0 = 0; k0 < T; k0 += G) {
+                    int gn[G], gav[G], gq[G], gP[G], gau[G], gps0[G], gps1[G];
+                    float grc[G];
+#pragma unroll
+                    for (int kk = 0; kk < G; ++kk) {
+                        const int k = k0 + kk;
+                        if (k < T) {
+                            const int p = x0 - r + i0 + k;
+                            const int nx = max(1, min(W - 1, p + r) - max(0, p - r) + 1);
+                            const int n = ny * nx;
+                            const int cPk = (cpv[k] - bias) >> 2, cPm1 = (cmv[k] - bias) >> 2;
+                            const int av = __mul24(cPk, m);
+                            int q = (int)((float)av * __builtin_amdgcn_rcpf((float)n));
+                            q = max(0, min(q, m));
+                            q += (q < m && __mul24(q + 1, n) <= av) ? 1 : 0;
+                            q -= (q > 0 && __mul24(q, n) > av) ? 1 : 0;
+                            gn[kk] = n;
+                            gav[kk] = av;
+                            gq[kk] = q;
+                            gau[kk] = __mul24(cPm1, m);
+                            gP[kk] = min(max(cPk - cPm1, 0), m);
+                        }
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < G; ++kk) {
+                        if (k0 + kk < T) {
+                            gps0[kk] = psl[gq[kk]];  // 4 Psi(q)
+                            gps1[kk] = psl[gq[kk] + 1];  // 4 Psi(q + 1)
+                            grc[kk] = rcf[gP[kk]];
+                        }
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < G; ++kk) {
+                        const int k = k0 + kk;
+                        if (k < T) {
+                            const int i = i0 + k;
+                            const int p = x0 - r + i;
+                            const bool pval = (i < np) && (p >= 0) && (p < W);
+                            const int n = gn[kk], av = gav[kk], au = gau[kk];
+                            const int phia = __mul24(n, gps0[kk]) + __mul24(av - __mul24(gq[kk], n), gps1[kk] - gps0[kk]);
+                            const int pu = lane_prev(phia);
+                            const int phiu = j0 ? 0 : pu;
+                            const int cm = __mul24(crm1, n);
+                            const int sc = min(max(cm, au), av);
+                            const int phis = (cm <= au) ? phiu : ((cm >= av) ? phia : __mul24(n, dm1_4));
+                            const int I4 = (phia - phis) + (phiu - phis) + __mul24(4 * j, 2 * sc - au - av);
+                            ev[k] = pval ? (float)I4 * grc[kk] * inv_m : 0.f;
+                        }
+                    }
                 }
             }
             if (want_w1 && own_row) {
