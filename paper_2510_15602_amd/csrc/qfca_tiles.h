@@ -491,7 +491,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                 // q = floor(a / n) comes from a reciprocal estimate corrected to
                 // the exact integer (the estimate is within one of it).
                 const float* rcf = rcp4;
-                constexpr int G = (T <= 8) ? T : 5;
+                constexpr int G = (T <= 8) ? 4 : 5;  // keeps T = 7 within three wavefronts per SIMD and T = 15 within two
 #pragma unroll
                 for (int k0 = 0; k0 < T; k0 += G) {
                     int gn[G], gav[G], gq[G], gP[G], gau[G], gps0[G], gps1[G];
