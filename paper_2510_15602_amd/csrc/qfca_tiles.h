@@ -113,9 +113,24 @@ struct BLayout {
 };
 
 // Fills the block-shared table rcp4[P] = rcp[P] / 4 (exact) for P = 0 .. T*T.
+// The loads of a chunk are all issued before its stores (the global source
+// is not known not to alias LDS, so one load per store would each wait).
 template <int T>
 __device__ __forceinline__ void fill_rcp4(float* rcp4, const float* rcp, int tid, int nthreads) {
-    for (int t = tid; t <= T * T; t += nthreads) rcp4[t] = 0.25f * rcp[t];
+    constexpr int N = T * T + 1;
+    for (int t0 = tid; t0 < N; t0 += 8 * nthreads) {
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int t = t0 + i * nthreads;
+            v[i] = t < N ? rcp[t] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int t = t0 + i * nthreads;
+            if (t < N) rcp4[t] = 0.25f * v[i];
+        }
+    }
 }
 
 // One (strip bx, band by, channel group bz) tile, run by one wavefront whose
@@ -156,16 +171,24 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     float* hrow = (float*)(smem + L.hrow);       // [64 lanes][HS]: the block's T window sums per lane
     int* psi = (int*)(smem + L.psi);             // [S][PSI]: 4 Psi_c(t)
 
-    // psi4[t] = 4 Psi(t) for t <= m, and 4 Psi(m + 1) = 4 (Psi(m) + sigma(m))
-    for (int t = lane; t < S * PSI; t += 64) {
-        const int ss = t / PSI, tt = t - ss * PSI;
-        const int cc = cbase + ss;
-        int v = 0;
-        if (cc < a.C) {
-            const int2 p = a.psig[(size_t)cc * (m + 1) + min(tt, m)];
-            v = 4 * (tt <= m ? p.x : p.x + p.y);
+    // psi4[t] = 4 Psi(t) for t <= m, and 4 Psi(m + 1) = 4 (Psi(m) + sigma(m));
+    // eight loads per lane in flight before their stores
+    for (int t0 = lane; t0 < S * PSI; t0 += 8 * 64) {
+        int v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int t = t0 + 64 * i;
+            const int ss = t / PSI, tt = t - ss * PSI;
+            const int cc = cbase + ss;
+            v[i] = 0;
+            if (t < S * PSI && cc < a.C) {
+                const int2 p = a.psig[(size_t)cc * (m + 1) + min(tt, m)];
+                v[i] = 4 * (tt <= m ? p.x : p.x + p.y);
+            }
         }
-        psi[t] = v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (t0 + 64 * i < S * PSI) psi[t0 + 64 * i] = v[i];
     }
     for (int t = lane; t < 64 * L.vs4; t += 64) vc32[t] = 0u;
     for (int t = lane; t < T * S * Ws + 64; t += 64) acc[t] = 0.f;
@@ -579,22 +602,41 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
             wave_sync();
             // 3. gather the pixel's own bin into the accumulators of the T
             //    pending output rows
+            //    (every read is issued before any accumulator store: the
+            //    regions are disjoint, which the compiler cannot see, and one
+            //    item at a time would cost an LDS round trip each)
             if (GATHER_AHEAD && gat) {
+                float hv[NIT];
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    const float h = hrow[(g_w0[it] & 0xFFFFu) + (gbin[it] & (Bp - 1)) * HS];
-                    lds_store_f(gdst[it], gacc[it] + h);
-                }
+                for (int it = 0; it < NIT; ++it) hv[it] = hrow[(g_w0[it] & 0xFFFFu) + (gbin[it] & (Bp - 1)) * HS];
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) lds_store_f(gdst[it], gacc[it] + hv[it]);
             } else if (gat) {
+                constexpr int CHK = 8;  // items per round of reads
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    const uint32_t w0 = g_w0[it], w1 = g_w1[it];
-                    const int xo = i0 + (int)(w1 & 63u) - 2 * r;
-                    const bool ok = (w1 & 0x8000u) && (xo >= 0) && (xo < ws);
-                    const int b = ring[(w0 >> 16) + blk * TP];
-                    const float h = hrow[(w0 & 0xFFFFu) + (b & (Bp - 1)) * HS];
-                    float* dst = ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : (trash + lane);
-                    *dst += h;
+                for (int c0 = 0; c0 < NIT; c0 += CHK) {
+                    int bv[CHK], da[CHK];
+                    float hv[CHK], av[CHK];
+#pragma unroll
+                    for (int q = 0; q < CHK; ++q) {
+                        if (c0 + q < NIT) {
+                            const uint32_t w0 = g_w0[c0 + q], w1 = g_w1[c0 + q];
+                            const int xo = i0 + (int)(w1 & 63u) - 2 * r;
+                            const bool ok = (w1 & 0x8000u) && (xo >= 0) && (xo < ws);
+                            bv[q] = ring[(w0 >> 16) + blk * TP];
+                            da[q] = lds_addr(ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : (trash + lane));
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < CHK; ++q) {
+                        if (c0 + q < NIT) {
+                            hv[q] = hrow[(g_w0[c0 + q] & 0xFFFFu) + (bv[q] & (Bp - 1)) * HS];
+                            av[q] = lds_load_f(da[q]);
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < CHK; ++q)
+                        if (c0 + q < NIT) lds_store_f(da[q], av[q] + hv[q]);
                 }
             }
             wave_sync();
