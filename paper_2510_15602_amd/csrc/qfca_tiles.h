@@ -669,12 +669,15 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                 float* ar = acc + (yo % T) * S * Ws;
                 float* gr = a.achan + ((size_t)cbase * H + yo) * W;
                 const double rny = 1.0 / (double)nyo;
+                float ov[OSL];
+#pragma unroll
+                for (int i = 0; i < OSL; ++i)
+                    ov[i] = (lane + 64 * i < nout) ? ar[oacc[i] & 0x7FFFFFFFu] : 0.f;
 #pragma unroll
                 for (int i = 0; i < OSL; ++i) {
                     if (lane + 64 * i < nout) {
-                        float* ap = ar + (oacc[i] & 0x7FFFFFFFu);
-                        if (oacc[i] >> 31) gr[oglb[i]] = (float)((double)(*ap) * osc[i] * rny);
-                        *ap = 0.f;
+                        if (oacc[i] >> 31) gr[oglb[i]] = (float)((double)ov[i] * osc[i] * rny);
+                        ar[oacc[i] & 0x7FFFFFFFu] = 0.f;
                     }
                 }
                 continue;
