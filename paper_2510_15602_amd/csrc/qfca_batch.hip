@@ -81,11 +81,16 @@ __device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* job
             float* sfd = sid + CMAX;
             float* zp = sfd + CMAX;
             for (int i = threadIdx.x; i < CMAX; i += 256) {
+                // loads before stores (see proj_prologue)
                 const bool ok = i < J.pa.C;
-                smu[i] = ok ? J.pa.mu[i] : 0.f;
-                slo[i] = ok ? J.pa.lo[i] : 0.f;
-                sid[i] = ok ? J.pa.inv_delta[i] : 0.f;
-                sfd[i] = ok ? J.pa.fastd[i] : 1.f;
+                const float vm = ok ? J.pa.mu[i] : 0.f;
+                const float vl = ok ? J.pa.lo[i] : 0.f;
+                const float vi = ok ? J.pa.inv_delta[i] : 0.f;
+                const float vf = ok ? J.pa.fastd[i] : 1.f;
+                smu[i] = vm;
+                slo[i] = vl;
+                sid[i] = vi;
+                sfd[i] = vf;
             }
             __syncthreads();
             if constexpr (BF) {

@@ -66,11 +66,17 @@ __host__ __device__ inline ProjLds proj_lds(int CMAX, int KT, int elt, bool vlds
 __device__ __forceinline__ void proj_prologue(const MArgs& a, int CMAX, float* smu, float* slo, float* sid,
                                               float* sfd, float* sedge, bool elds) {
     for (int i = threadIdx.x; i < CMAX; i += blockDim.x) {
+        // the four loads are issued before the stores (the sources are not
+        // known not to alias LDS, so interleaved each load would wait)
         const bool ok = i < a.C;
-        smu[i] = ok ? a.mu[i] : 0.f;
-        slo[i] = ok && a.lo ? a.lo[i] : 0.f;
-        sid[i] = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
-        sfd[i] = ok && a.fastd ? a.fastd[i] : 1.f;
+        const float vm = ok ? a.mu[i] : 0.f;
+        const float vl = ok && a.lo ? a.lo[i] : 0.f;
+        const float vi = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
+        const float vf = ok && a.fastd ? a.fastd[i] : 1.f;
+        smu[i] = vm;
+        slo[i] = vl;
+        sid[i] = vi;
+        sfd[i] = vf;
     }
     if (elds && a.bins) {
         const int ne = a.C * (a.B > 1 ? a.B - 1 : 0);
