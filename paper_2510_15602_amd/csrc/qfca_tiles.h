@@ -82,6 +82,10 @@ __device__ __forceinline__ void lds_store_f(int addr, float v) {
 //      sums are written to a small LDS buffer and gathered into the pending
 //      rows' accumulators by all lanes at once, one (channel, pending row,
 //      column) triple per lane.
+// Throughout, LDS loads of a step are written before its stores: the regions
+// of a tile never overlap, but the compiler cannot prove it, and a load that
+// follows a store in program order waits for it (one LDS round trip per
+// element instead of one per group).
 template <int T>
 struct BLayout {
     static constexpr int r = T / 2, m = T * T, T1 = T + 1, TP = (T + 3) & ~3;
