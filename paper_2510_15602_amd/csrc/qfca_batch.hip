@@ -132,7 +132,7 @@ __device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* job
                 const int rest = local / J.nstrips;
                 const int by = rest % J.nbands;
                 const int gz = rest / J.nbands;
-                score_tile<T>(J.sa, bx, by, 4 * gz + w, lane, smem + (size_t)w * wave_lds, rcp4);
+                score_tile<T, true, false>(J.sa, bx, by, 4 * gz + w, lane, smem + (size_t)w * wave_lds, rcp4);
             }
         }
         __syncthreads();

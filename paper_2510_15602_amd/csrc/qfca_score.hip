@@ -26,6 +26,8 @@
 //     of the T patch rows that cover it.
 // All counts are exact integers; per-channel results are written to a
 // [C][H][W] buffer and reduced over channels in a fixed order.
+#include <atomic>
+
 #include "qfca_internal.h"
 #include "qfca_tiles.h"
 
@@ -242,9 +244,12 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
 template <int T>
 __global__ __launch_bounds__(64) void k_score_t(KArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    float* rcp4 = (float*)smem;  // block-shared, at LDS offset 0
+    // block-shared, at LDS address 0: the kernel has no static LDS (its
+    // launcher checks that), so the dynamic LDS starts there
+    float* rcp4 = (float*)smem;
     fill_rcp4<T>(rcp4, a.rcp, threadIdx.x, 64);
-    score_tile<T>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, smem + BLayout<T>::RCP_BYTES, rcp4);
+    score_tile<T, false, true>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, smem + BLayout<T>::RCP_BYTES,
+                               rcp4);
 }
 
 // A(x) = (1/C) sum_c achan[c][x] in double precision, in a fixed order
@@ -336,6 +341,23 @@ size_t score_lds_bytes(int T, int Bp, int S, int Ws, int variant) {
     return lds_layout(T, Bp, S, Ws, alloc_cols(T, Ws, 0)).total;
 }
 
+// k_score_t<T> addresses its reciprocal table as LDS address 0, which holds
+// while the kernel has no static LDS: checked once per window size, on the
+// first launch.
+static hipError_t no_static_lds(const void* k, int T) {
+    static std::atomic<int> state[32];  // by T / 2: 0 unknown, 1 none, 2 some
+    std::atomic<int>& s = state[(T / 2) & 31];
+    int v = s.load(std::memory_order_relaxed);
+    if (v == 0) {
+        hipFuncAttributes fa;
+        const hipError_t e = hipFuncGetAttributes(&fa, k);
+        if (e != hipSuccess) return e;
+        v = fa.sharedSizeBytes == 0 ? 1 : 2;
+        s.store(v, std::memory_order_relaxed);
+    }
+    return v == 1 ? hipSuccess : hipErrorInvalidDeviceFunction;
+}
+
 hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     KArgs a;
     a.bins = L.bins;
@@ -371,7 +393,8 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     switch (a.T) {
 #define QFCA_T_CASE(TT)                                                          \
         case TT: {                                                               \
-            hipError_t e = allow((const void*)k_score_t<TT>);                    \
+            hipError_t e = no_static_lds((const void*)k_score_t<TT>, TT);        \
+            if (e == hipSuccess) e = allow((const void*)k_score_t<TT>);          \
             if (e != hipSuccess) return e;                                       \
             hipLaunchKernelGGL(k_score_t<TT>, grid, dim3(64), lds, st, a);       \
         } break;

@@ -142,7 +142,13 @@ __device__ __forceinline__ void fill_rcp4(float* rcp4, const float* rcp, int tid
 // block-shared table rcp4 (fill_rcp4, visible to the wave before the call).
 // The tile synchronises only its own wavefront, so the wavefronts of a block
 // may run tiles of different geometry.
-template <int T>
+//   FASTG: blocks whose output columns all lie inside the strip take a
+//   gather with no column test (a gain in the persistent batch kernel, a
+//   small loss in the one-tile kernel, whose registers it crowds).
+//   RCP0: the caller guarantees that rcp4 sits at LDS address 0 (a kernel
+//   with no static LDS whose dynamic LDS starts with it), so the byte offset
+//   4P of rcp4[P] is its address and costs no add.
+template <int T, bool FASTG, bool RCP0>
 __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int bz, int lane,
                                            unsigned char* smem, const float* rcp4) {
     using BL = BLayout<T>;
@@ -449,20 +455,30 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
             //    disjoint), so their latency hides behind steps 1 and 2.
             //    The output column of step k is o = i0 + k - 2r, whose bin
             //    column i0 + k sits at byte blk*TP + k.
+            //    When every step's output column lies inside the strip (gin),
+            //    only the channel of an item decides whether it is stored.
             const bool gat = (i0 + T - 1 >= 2 * r);
+            const bool gin = (i0 >= 2 * r) && (i0 + T - 1 - 2 * r < ws);
             int gbin[NIT], gdst[NIT];
             float gacc[NIT];
-            if (GATHER_AHEAD && gat) {
+            auto gather_ahead = [&](auto inner) {
+                constexpr bool IN = decltype(inner)::value;
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
                     const uint32_t w0 = g_w0[it], w1 = g_w1[it];
                     const int xo = i0 + (int)(w1 & 63u) - 2 * r;
-                    const bool ok = (w1 & 0x8000u) && (xo >= 0) && (xo < ws);
+                    const bool ok = IN ? (w1 & 0x8000u) != 0u : ((w1 & 0x8000u) && (xo >= 0) && (xo < ws));
                     const float* dst = ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : (trash + lane);
                     gbin[it] = ring[(w0 >> 16) + blk * TP];
                     gdst[it] = lds_addr(dst);
                     gacc[it] = *dst;
                 }
+            };
+            if (GATHER_AHEAD && gat) {
+                if (FASTG && gin)
+                    gather_ahead(bconst<true>());
+                else
+                    gather_ahead(bconst<false>());
             }
             if (WIN && blk + 1 < nblk) {
 #pragma unroll
@@ -499,7 +515,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
 #pragma unroll
                 for (int k = 0; k < T; ++k) gv[k] = lds_load_i(cpv[k]);
 #pragma unroll
-                for (int k = 0; k < T; ++k) rc[k] = lds_load_f(rbase + (cpv[k] - cmv[k]));
+                for (int k = 0; k < T; ++k) rc[k] = lds_load_f(RCP0 ? cpv[k] - cmv[k] : rbase + (cpv[k] - cmv[k]));
 #pragma unroll
                 for (int k = 0; k < T; ++k) gv[k] += __mul24(negj, cpv[k]);  // 4 g(v) - j bias
 #pragma unroll
@@ -617,31 +633,39 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                 for (int it = 0; it < NIT; ++it) lds_store_f(gdst[it], gacc[it] + hv[it]);
             } else if (gat) {
                 constexpr int CHK = 8;  // items per round of reads
+                auto gather_chunks = [&](auto inner) {
+                    constexpr bool IN = decltype(inner)::value;
 #pragma unroll
-                for (int c0 = 0; c0 < NIT; c0 += CHK) {
-                    int bv[CHK], da[CHK];
-                    float hv[CHK], av[CHK];
+                    for (int c0 = 0; c0 < NIT; c0 += CHK) {
+                        int bv[CHK], da[CHK];
+                        float hv[CHK], av[CHK];
 #pragma unroll
-                    for (int q = 0; q < CHK; ++q) {
-                        if (c0 + q < NIT) {
-                            const uint32_t w0 = g_w0[c0 + q], w1 = g_w1[c0 + q];
-                            const int xo = i0 + (int)(w1 & 63u) - 2 * r;
-                            const bool ok = (w1 & 0x8000u) && (xo >= 0) && (xo < ws);
-                            bv[q] = ring[(w0 >> 16) + blk * TP];
-                            da[q] = lds_addr(ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : (trash + lane));
+                        for (int q = 0; q < CHK; ++q) {
+                            if (c0 + q < NIT) {
+                                const uint32_t w0 = g_w0[c0 + q], w1 = g_w1[c0 + q];
+                                const int xo = i0 + (int)(w1 & 63u) - 2 * r;
+                                const bool ok =
+                                    IN ? (w1 & 0x8000u) != 0u : ((w1 & 0x8000u) && (xo >= 0) && (xo < ws));
+                                bv[q] = ring[(w0 >> 16) + blk * TP];
+                                da[q] = lds_addr(ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : (trash + lane));
+                            }
                         }
-                    }
 #pragma unroll
-                    for (int q = 0; q < CHK; ++q) {
-                        if (c0 + q < NIT) {
-                            hv[q] = hrow[(g_w0[c0 + q] & 0xFFFFu) + (bv[q] & (Bp - 1)) * HS];
-                            av[q] = lds_load_f(da[q]);
+                        for (int q = 0; q < CHK; ++q) {
+                            if (c0 + q < NIT) {
+                                hv[q] = hrow[(g_w0[c0 + q] & 0xFFFFu) + (bv[q] & (Bp - 1)) * HS];
+                                av[q] = lds_load_f(da[q]);
+                            }
                         }
-                    }
 #pragma unroll
-                    for (int q = 0; q < CHK; ++q)
-                        if (c0 + q < NIT) lds_store_f(da[q], av[q] + hv[q]);
-                }
+                        for (int q = 0; q < CHK; ++q)
+                            if (c0 + q < NIT) lds_store_f(da[q], av[q] + hv[q]);
+                    }
+                };
+                if (FASTG && gin)
+                    gather_chunks(bconst<true>());
+                else
+                    gather_chunks(bconst<false>());
             }
             wave_sync();
             if constexpr (WIN) {
