@@ -938,7 +938,7 @@ ScoreTile batch_tile(qfca_ctx ctx, const qfca_params& p) {
     if (t.S < 1) t.S = 1;
     // four wavefront regions and the shared reciprocal table must fit in LDS:
     // narrow the strip one window width at a time (keeping whole blocks)
-    while (score_rcp_bytes(p.T) + 4 * align16c(batch_wave_lds(p.T, t.S, t.Ws)) > 160 * 1024 && t.Ws > p.T + 1)
+    while (batch_head_bytes(p.T) + 4 * align16c(batch_wave_lds(p.T, t.S, t.Ws)) > 160 * 1024 && t.Ws > p.T + 1)
         t.Ws -= p.T;
     return t;
 }
@@ -987,7 +987,7 @@ qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n,
     const ScoreTile tile = batch_tile(ctx, p);
     const int Bp = batch_lanes(p.B);
     const size_t wave_lds = align16c(batch_wave_lds(p.T, tile.S, tile.Ws));
-    const size_t lds = score_rcp_bytes(p.T) + std::max((size_t)4 * wave_lds, batch_proj_lds(CM, KT));
+    const size_t lds = batch_head_bytes(p.T) + std::max((size_t)4 * wave_lds, batch_proj_lds(CM, KT));
     if (lds > 160 * 1024) return fail(QFCA_E_UNSUPPORTED, "batch tile does not fit in LDS");
 
     // device + pinned staging buffers
@@ -1137,7 +1137,7 @@ qfca_status qfca_autotune(qfca_ctx ctx, const qfca_job* jobs, int32_t n, int32_t
             t.Hb = Hb;
             t.variant = 1;
             t.S = std::min(64 / Bp, score_block_max_S(T));
-            if (score_rcp_bytes(T) + 4 * align16c(batch_wave_lds(T, t.S, t.Ws)) > 160 * 1024) continue;
+            if (batch_head_bytes(T) + 4 * align16c(batch_wave_lds(T, t.S, t.Ws)) > 160 * 1024) continue;
             ctx->tile_override = t;
             qfca_status st = qfca_score_batch(ctx, jobs, n);  // warm-up (and graph capture)
             if (st != QFCA_OK) continue;

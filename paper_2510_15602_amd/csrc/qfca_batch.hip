@@ -46,12 +46,18 @@ __device__ int find_job(const int* prefix, int n, int item) {
 template <int T, int CMAX, int KT, bool BF>
 __device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* jobs, int wave_lds) {
     // LDS: the block-shared reciprocal table of the score tiles (it depends
-    // on T only), then either the projection scratch or 4 wave regions
+    // on T only), the block's control words (item, job, ready flag), then
+    // either the projection scratch or 4 wave regions.  The kernel declares
+    // no static LDS (prepare_batch checks it), so the table sits at LDS
+    // address 0.
     extern __shared__ __align__(16) unsigned char smem_all[];
-    __shared__ int s_item, s_job, s_ok;
     constexpr size_t RCP = BLayout<T>::RCP_BYTES;
     float* rcp4 = (float*)smem_all;
-    unsigned char* smem = smem_all + RCP;
+    int* ctl = (int*)(smem_all + RCP);
+    int& s_item = ctl[0];
+    int& s_job = ctl[1];
+    int& s_ok = ctl[2];
+    unsigned char* smem = smem_all + RCP + BATCH_CTL_BYTES;
     // the wavefront index is uniform across the wavefront: held in a scalar
     // register, offsets derived from it fold into instruction offsets
     const int lane0 = threadIdx.x & 63, w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -132,7 +138,7 @@ __device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* job
                 const int rest = local / J.nstrips;
                 const int by = rest % J.nbands;
                 const int gz = rest / J.nbands;
-                score_tile<T, true, false>(J.sa, bx, by, 4 * gz + w, lane, smem + (size_t)w * wave_lds, rcp4);
+                score_tile<T, true, true>(J.sa, bx, by, 4 * gz + w, lane, smem + (size_t)w * wave_lds, rcp4);
             }
         }
         __syncthreads();
@@ -254,12 +260,24 @@ bool batch_supported(int T, int CMAX, int KT, int prec) {
 
 size_t batch_proj_lds(int CMAX, int KT) { return (size_t)4 * CMAX * 4 + (size_t)4 * KT * 4 * 64 * 4; }
 
+// Allows the kernel's dynamic LDS and checks that it has no static LDS (its
+// reciprocal table is addressed as LDS address 0).
+static hipError_t prepare_kernel(const void* k, size_t lds) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipFuncAttributes fa;
+    e = hipFuncGetAttributes(&fa, k);
+    if (e != hipSuccess) return e;
+    return fa.sharedSizeBytes == 0 ? hipSuccess : hipErrorInvalidDeviceFunction;
+}
+
+size_t batch_head_bytes(int T) { return score_rcp_bytes(T) + BATCH_CTL_BYTES; }
+
 hipError_t prepare_batch(int T, int CMAX, int KT, int prec, size_t lds) {
     const bool bf = prec == QFCA_PREC_BF16;
 #define QFCA_PREP_CASE(TT, CM, KK, BFV)                                                    \
     if (T == TT && CMAX == CM && KT == KK && bf == BFV)                                    \
-        return hipFuncSetAttribute(batch_kernel<TT, CM, KK, BFV>(),                         \
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        return prepare_kernel(batch_kernel<TT, CM, KK, BFV>(), lds);
 #define QFCA_PREP_T(TT) QFCA_PREP_CASE(TT, 64, 1, false) QFCA_PREP_CASE(TT, 256, 2, false) \
     QFCA_PREP_CASE(TT, 512, 4, false) QFCA_PREP_CASE(TT, 256, 2, true) QFCA_PREP_CASE(TT, 512, 4, true)
     QFCA_PREP_T(5) QFCA_PREP_T(7) QFCA_PREP_T(9) QFCA_PREP_T(11) QFCA_PREP_T(15) QFCA_PREP_T(31)

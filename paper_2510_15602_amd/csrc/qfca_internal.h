@@ -63,6 +63,8 @@ struct BatchHeader {
 };
 size_t batch_wave_lds(int T, int S, int Ws);
 size_t score_rcp_bytes(int T);  // block-shared reciprocal table of the score tiles
+constexpr size_t BATCH_CTL_BYTES = 16;  // batch kernel: control words after the table
+size_t batch_head_bytes(int T);  // batch kernel: table and control words, before the wave regions
 size_t batch_proj_lds(int CMAX, int KT);
 bool batch_supported(int T, int CMAX, int KT, int prec);
 hipError_t prepare_batch(int T, int CMAX, int KT, int prec, size_t lds);
