@@ -145,13 +145,40 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ vals, 
 
 // ------------------------------------------------------------------------
 // Reference: count table counts[c][i][t] = #{full windows p : cP_p(i) = t}.
-// Same lane layout and running sums as the score kernel (lane (s, j) owns bin
-// j of channel s); every lane keeps a private uint16 histogram in LDS for the
-// bins of its split, flushed with global atomics at the end of the tile.
+// Lane (s, j) owns bin j of channel s.  Per row of window centres:
+//   1. the entering and leaving image rows of the S channels are staged in
+//      LDS (0x7F outside the image, never counted);
+//   2. each lane's vertical counts #{rows of the window : bin <= j} of every
+//      column, four columns per dword, are updated with one SWAR step per
+//      dword: for 7-bit bytes b and j < 64, 0x80 + j - b never borrows across
+//      bytes and its top bit is set exactly when b <= j;
+//   3. the lane walks the columns with a running window sum cP and counts
+//      each full window's cP in its private table of uint16 counters, two per
+//      word, by LDS atomic adds that return nothing (no wait per window).
+// The counts of a tile (at most Ws * Hb = 4096 windows) fit in 16 bits; they
+// are flushed with global atomics at the end.
 struct RArgs {
     const uint8_t* bins;
     int C, H, W, T, B, Bp, S, r, m, Ws, Hb, nsplit;
     uint32_t* counts;
+};
+
+__host__ __device__ inline size_t ralign16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+struct RefLayout {
+    int WbP, vsd, mw;
+    size_t vc, cnt, rows, total;
+    __host__ __device__ RefLayout(int Ws, int r, int S, int per, int m) {
+        const int WbMax = Ws + 2 * r;       // bin columns of the widest tile
+        WbP = (WbMax + 3) & ~3;
+        vsd = WbP / 4;
+        if ((vsd & 1) == 0) vsd += 1;       // odd dword stride between lanes
+        mw = (m + 2) / 2;                   // words holding counters 0 .. m
+        vc = 0;
+        cnt = ralign16((size_t)64 * vsd * 4);
+        rows = cnt + ralign16((size_t)S * per * mw * 4);
+        total = rows + ralign16((size_t)2 * S * WbP);
+    }
 };
 
 __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
@@ -169,68 +196,112 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
     const int per = Bp / a.nsplit;
     const int jlo = split * per;
     const bool counting = cv && (j < a.B) && (j >= jlo) && (j < jlo + per);
-    const int WbMax = a.Ws + 2 * r, Wb = ws + 2 * r;  // bin columns [x0-r, xe+r)
+    const RefLayout L(a.Ws, r, S, per, m);
+    const int WbP = L.WbP;
+    const int Wb = ws + 2 * r;  // bin columns [x0-r, xe+r)
     const int xb0 = x0 - r;
-    const uint8_t* bc = a.bins + (size_t)(cv ? c : 0) * H * W;
-    uint8_t* vc = smem;                                          // [WbMax][64]
-    uint16_t* cnt = (uint16_t*)(smem + ((WbMax * 64 + 15) & ~15));  // [S][per][m+1]
-    // the rows entering and leaving the windows, staged per row: [2][S][WbMax]
-    uint8_t* rows = (uint8_t*)(cnt + (size_t)S * per * (m + 1));
-    for (int t = lane; t < WbMax * 16; t += 64) ((uint32_t*)vc)[t] = 0u;
-    for (int t = lane; t < S * per * (m + 1); t += 64) cnt[t] = 0;
+    uint32_t* vc32 = (uint32_t*)(smem + L.vc);  // [64 lanes][vsd]
+    uint32_t* cnt = (uint32_t*)(smem + L.cnt);  // [S][per][mw]
+    uint8_t* rows = smem + L.rows;              // [2][S][WbP]
+    for (int t = lane; t < 64 * L.vsd; t += 64) vc32[t] = 0u;
+    for (int t = lane; t < S * per * L.mw; t += 64) cnt[t] = 0u;
     __syncthreads();
-    uint16_t* mycnt = cnt + ((size_t)sa * per + (counting ? j - jlo : 0)) * (m + 1);
+    uint32_t* mycnt = cnt + ((size_t)sa * per + (counting ? j - jlo : 0)) * L.mw;
+    const uint32_t jhi = ((uint32_t)j * 0x01010101u) | 0x80808080u;
     // Full-window centres owned by this tile: rows [ys, yend), columns
     // [max(x0, r), min(xe, W - r)).
     const int ys = max(y0, r), yend = min(ye, H - r);
     const int pxlo = max(x0, r), pxhi = min(xe, W - r);
     if (ys < yend && pxlo < pxhi) {
-        for (int yy = ys - r; yy < ys + r; ++yy)
-            for (int q = 0; q < Wb; ++q) {
-                const int xl = xb0 + q;
-                if (xl >= 0 && xl < W) vc[q * 64 + lane] += (bc[(size_t)yy * W + xl] <= j) ? 1 : 0;
+        // image row yy into staging slot h (0 entering, 1 leaving); one
+        // coalesced pass for the S channels
+        auto stage = [&](int h, int yy) {
+            for (int t = lane; t < S * WbP; t += 64) {
+                const int ss = t / WbP, q = t - ss * WbP;
+                const int cc = cbase + ss, xl = xb0 + q;
+                uint8_t v = 0x7F;
+                if (q < Wb && cc < a.C && xl >= 0 && xl < W && yy >= 0 && yy < H)
+                    v = a.bins[((size_t)cc * H + yy) * W + xl] & 0x7F;
+                rows[(size_t)(h * S + ss) * WbP + q] = v;
             }
-        const uint8_t* rowa = rows + (size_t)sa * WbMax;
-        const uint8_t* rowr = rows + (size_t)(S + sa) * WbMax;
-        for (int yc = ys; yc < yend; ++yc) {
-            const int ya = yc + r, yr = yc - r - 1;
-            const bool rem = yc > ys;
-            // one coalesced load of both rows for the S channels, then LDS reads
-            __syncthreads();
-            for (int t = lane; t < 2 * S * Wb; t += 64) {
-                const int h = t / (S * Wb), rest = t - h * S * Wb;
-                const int ss = rest / Wb, q = rest - ss * Wb;
-                const int cc = cbase + ss, xl = xb0 + q, yy = h ? yr : ya;
-                uint8_t v = 0;
-                if (cc < a.C && xl >= 0 && xl < W && yy >= 0) v = a.bins[((size_t)cc * H + yy) * W + xl];
-                rows[(size_t)(h * S + ss) * WbMax + q] = v;
-            }
-            __syncthreads();
-            int cP = 0;
-            for (int q = 0; q < Wb; ++q) {
-                const int xl = xb0 + q;
-                int v = 0;
-                if (xl >= 0 && xl < W) {
-                    v = vc[q * 64 + lane] + ((rowa[q] <= j) ? 1 : 0);
-                    if (rem) v -= (rowr[q] <= j) ? 1 : 0;
-                    vc[q * 64 + lane] = (uint8_t)v;
+        };
+        // the lane's counts += [entering bin <= j] (ADD), -= [leaving bin <= j]
+        // (REM); the loads of a chunk are issued before its stores
+        auto update = [&](bool add, bool rem) {
+            const uint32_t* __restrict__ ra = (const uint32_t*)(rows + (size_t)sa * WbP);
+            const uint32_t* __restrict__ rr = (const uint32_t*)(rows + (size_t)(S + sa) * WbP);
+            uint32_t* __restrict__ v = vc32 + lane * L.vsd;
+            const int nd = WbP / 4;
+            constexpr int CH = 8;
+            for (int d0 = 0; d0 < nd; d0 += CH) {
+                uint32_t xv[CH], xa[CH], xr[CH];
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    const int d = min(d0 + i, nd - 1);
+                    xv[i] = v[d];
+                    xa[i] = ra[d];
+                    xr[i] = rr[d];
                 }
-                const int vold = (q >= T) ? (int)vc[(q - T) * 64 + lane] : 0;
-                cP += v - vold;
-                const int px = xl - r;
-                if (counting && q >= T - 1 && px >= pxlo && px < pxhi) mycnt[cP] += 1;
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    uint32_t x = xv[i];
+                    if (add) x += ((jhi - xa[i]) & 0x80808080u) >> 7;
+                    if (rem) x -= ((jhi - xr[i]) & 0x80808080u) >> 7;
+                    if (d0 + i < nd) v[d0 + i] = x;
+                }
+            }
+        };
+        for (int yy = ys - r; yy < ys + r; ++yy) {
+            __syncthreads();
+            stage(0, yy);
+            __syncthreads();
+            update(true, false);
+        }
+        const uint8_t* __restrict__ vb = (const uint8_t*)(vc32 + lane * L.vsd);
+        for (int yc = ys; yc < yend; ++yc) {
+            const bool rem = yc > ys;
+            __syncthreads();
+            stage(0, yc + r);
+            if (rem) stage(1, yc - r - 1);
+            __syncthreads();
+            update(true, rem);
+            __syncthreads();
+            // window sums along the row: cP = sum of the counts of columns
+            // [q - T + 1, q]; the window ending at column q is centred on
+            // image column xb0 + q - r
+            int cP = 0;
+            constexpr int CW = 8;
+            for (int q0 = 0; q0 < Wb; q0 += CW) {
+                int vn[CW], vo[CW];
+#pragma unroll
+                for (int i = 0; i < CW; ++i) {
+                    const int q = q0 + i;
+                    vn[i] = q < Wb ? (int)vb[q] : 0;
+                    vo[i] = (q >= T && q < Wb) ? (int)vb[q - T] : 0;
+                }
+#pragma unroll
+                for (int i = 0; i < CW; ++i) {
+                    const int q = q0 + i;
+                    cP += vn[i] - vo[i];
+                    const int px = xb0 + q - r;
+                    if (counting && q < Wb && q >= T - 1 && px >= pxlo && px < pxhi)
+                        atomicAdd(mycnt + (cP >> 1), 1u << ((cP & 1) << 4));
+                }
             }
         }
     }
     __syncthreads();
-    for (int t = lane; t < S * per * (m + 1); t += 64) {
-        const int ss = t / (per * (m + 1));
-        const int rest = t - ss * per * (m + 1);
-        const int jj = rest / (m + 1) + jlo, tt = rest - (rest / (m + 1)) * (m + 1);
+    for (int t = lane; t < S * per * L.mw; t += 64) {
+        const int ss = t / (per * L.mw);
+        const int rest = t - ss * per * L.mw;
+        const int jj = rest / L.mw + jlo, w = rest - (rest / L.mw) * L.mw;
         const int cc = cbase + ss;
         const uint32_t v = cnt[t];
-        if (v && cc < a.C && jj < a.B)
-            atomicAdd(&a.counts[((size_t)cc * a.B + jj) * (m + 1) + tt], v);
+        if (v && cc < a.C && jj < a.B) {
+            uint32_t* dst = a.counts + ((size_t)cc * a.B + jj) * (m + 1) + 2 * w;
+            if (v & 0xFFFFu) atomicAdd(dst, v & 0xFFFFu);
+            if ((v >> 16) && 2 * w + 1 <= m) atomicAdd(dst + 1, v >> 16);
+        }
     }
 }
 
@@ -351,12 +422,11 @@ hipError_t launch_refcount(const uint8_t* bins, int C, int H, int W, int T, int 
     a.counts = counts;
     hipError_t e = hipMemsetAsync(counts, 0, (size_t)C * B * (a.m + 1) * sizeof(uint32_t), st);
     if (e != hipSuccess) return e;
-    // channels per wave and bin splits so the private histograms fit in LDS
+    // channels per wave and bin splits so the private histograms fit in LDS;
+    // a tile's counters are 16 bits wide
+    if (a.Ws * a.Hb >= 65536) return hipErrorInvalidValue;
     int S = 64 / Bp, nsplit = 1;
-    auto lds = [&](int S_, int ns_) {
-        const size_t WbMax = (size_t)a.Ws + 2 * a.r;
-        return ((WbMax * 64 + 15) & ~size_t(15)) + (size_t)S_ * (Bp / ns_) * (a.m + 1) * 2 + 2 * (size_t)S_ * WbMax;
-    };
+    auto lds = [&](int S_, int ns_) { return RefLayout(a.Ws, a.r, S_, Bp / ns_, a.m).total; };
     while (lds(S, nsplit) > 60000 && S > 1) S >>= 1;
     while (lds(S, nsplit) > 60000 && nsplit < Bp) nsplit <<= 1;
     if (lds(S, nsplit) > 65536) return hipErrorInvalidValue;
