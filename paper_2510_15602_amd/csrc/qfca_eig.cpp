@@ -99,6 +99,94 @@ void householder_tridiag(double* A, int n, double* d, double* e, double* Q, doub
     }
 }
 
+// The same reduction working on the lower triangle of A only (A[i][j],
+// j <= i, row-major; the upper triangle is neither read nor written), with the
+// reflectors kept in H and beta: the symmetric product p = beta A v reads each
+// stored entry once (a dot product along the row and an update of p along
+// the same row), and the rank-2 update A -= v q^T + q v^T touches the stored
+// half only, so a step costs about 4 len^2 operations instead of 6.  The
+// row loops are contiguous; the dot products keep four partial sums.
+void householder_tridiag_lower(double* A, int n, double* d, double* e, double* H, double* beta_out) {
+    for (int i = 0; i < n; ++i) beta_out[i] = 0.0;
+    for (int i = 0; i < n; ++i) e[i] = 0.0;
+    std::vector<double> v(n), p(n), qv(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const int len = n - k - 1;  // entries A[k+1..n-1][k]
+        double nrm2 = 0.0;
+        for (int t = 0; t < len; ++t) {
+            const double x = A[(size_t)(k + 1 + t) * n + k];
+            nrm2 += x * x;
+        }
+        if (nrm2 == 0.0) {
+            e[k] = 0.0;
+            continue;
+        }
+        const double x0 = A[(size_t)(k + 1) * n + k];
+        const double alpha = (x0 > 0.0) ? -sqrt(nrm2) : sqrt(nrm2);
+        for (int t = 0; t < len; ++t) v[t] = A[(size_t)(k + 1 + t) * n + k];
+        v[0] -= alpha;
+        double vn2 = 0.0;
+        for (int t = 0; t < len; ++t) vn2 += v[t] * v[t];
+        e[k] = alpha;
+        if (vn2 == 0.0) continue;
+        const double beta = 2.0 / vn2;
+        // p = A_sub v from the lower triangle: row a contributes
+        // sum_{b<a} A[a][b] v[b] to p[a] and A[a][b] v[a] to every p[b], b < a
+        double* __restrict__ pp = p.data();
+        const double* __restrict__ vv = v.data();
+        for (int a = 0; a < len; ++a) pp[a] = 0.0;
+        for (int a = 0; a < len; ++a) {
+            const double* __restrict__ row = A + (size_t)(k + 1 + a) * n + (k + 1);
+            const double va = vv[a];
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int b = 0;
+            for (; b + 4 <= a; b += 4) {
+                s0 += row[b] * vv[b];
+                s1 += row[b + 1] * vv[b + 1];
+                s2 += row[b + 2] * vv[b + 2];
+                s3 += row[b + 3] * vv[b + 3];
+                pp[b] += row[b] * va;
+                pp[b + 1] += row[b + 1] * va;
+                pp[b + 2] += row[b + 2] * va;
+                pp[b + 3] += row[b + 3] * va;
+            }
+            for (; b < a; ++b) {
+                s0 += row[b] * vv[b];
+                pp[b] += row[b] * va;
+            }
+            pp[a] += (s0 + s1) + (s2 + s3) + row[a] * va;
+        }
+        double vp = 0.0;
+        for (int a = 0; a < len; ++a) {
+            pp[a] *= beta;
+            vp += vv[a] * pp[a];
+        }
+        const double K = 0.5 * beta * vp;
+        double* __restrict__ qq = qv.data();
+        for (int a = 0; a < len; ++a) qq[a] = pp[a] - K * vv[a];
+        // A_sub <- A_sub - v q^T - q v^T, lower triangle
+        for (int a = 0; a < len; ++a) {
+            double* __restrict__ row = A + (size_t)(k + 1 + a) * n + (k + 1);
+            const double va = vv[a], qa = qq[a];
+            for (int b = 0; b <= a; ++b) row[b] -= va * qq[b] + qa * vv[b];
+        }
+        for (int t = 0; t < len; ++t) H[(size_t)k * n + k + 1 + t] = v[t];
+        beta_out[k] = beta;
+    }
+    for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+    if (n >= 2) e[n - 2] = A[(size_t)(n - 1) * n + (n - 2)];
+    e[n - 1] = 0.0;
+}
+
+// sqrt(a^2 + b^2): the plain formula wherever the sum of squares neither
+// overflows nor underflows (within two units in the last place of the
+// library's hypot, several times faster), else the library's scaled hypot.
+inline double fast_hypot(double a, double b) {
+    const double s = a * a + b * b;
+    if (s > 1e-290 && s < 1e290) return sqrt(s);
+    return hypot(a, b);
+}
+
 // Implicit QL on the tridiagonal (d, e); ZT, when given, accumulates the
 // rotations, held transposed (row i of ZT is column i of the transform) so
 // that each rotation updates two contiguous rows.  Returns 0 on success, -1
@@ -123,14 +211,14 @@ int tridiag_ql(double* d, double* e, int n, double* ZT) {
             if (++iter > 100) return -1;
             // shift from the eigenvalue of the leading 2 x 2 block closer to d[l]
             double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double rr = hypot(g, 1.0);
+            double rr = fast_hypot(g, 1.0);
             g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? fabs(rr) : -fabs(rr)));
             double s = 1.0, c = 1.0, p = 0.0;
             bool early = false;
             for (int i = m - 1; i >= l; --i) {
                 const double f = s * e[i];
                 const double b = c * e[i];
-                rr = hypot(f, g);
+                rr = fast_hypot(f, g);
                 e[i + 1] = rr;
                 if (rr == 0.0) {
                     d[i + 1] -= p;
@@ -138,8 +226,9 @@ int tridiag_ql(double* d, double* e, int n, double* ZT) {
                     early = true;
                     break;
                 }
-                s = f / rr;
-                c = g / rr;
+                const double ir = 1.0 / rr;
+                s = f * ir;
+                c = g * ir;
                 g = d[i + 1] - p;
                 rr = (d[i] - g) * s + 2.0 * c * b;
                 p = s * rr;
@@ -229,7 +318,7 @@ int sym_eig_top(double* A, int n, int k, double* evals, double* vecs) {
         return 0;
     };
     std::vector<double> d(n), e(n), H((size_t)n * n, 0.0), beta(n, 0.0);
-    householder_tridiag(A, n, d.data(), e.data(), nullptr, H.data(), beta.data());
+    householder_tridiag_lower(A, n, d.data(), e.data(), H.data(), beta.data());
     std::vector<double> dt(d), et(e);  // T, kept for the inverse iteration
     if (tridiag_ql(d.data(), e.data(), n, nullptr) != 0) return -1;
     std::sort(d.begin(), d.end(), [](double a, double b) { return a > b; });
@@ -283,8 +372,16 @@ int sym_eig_top(double* A, int n, int k, double* evals, double* vecs) {
         for (int s = n - 3; s >= 0; --s) {
             if (beta[s] == 0.0) continue;
             const double* v = H.data() + (size_t)s * n;
-            double dot = 0.0;
-            for (int i = s + 1; i < n; ++i) dot += v[i] * y[i];
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;  // four partial sums
+            int i = s + 1;
+            for (; i + 4 <= n; i += 4) {
+                d0 += v[i] * y[i];
+                d1 += v[i + 1] * y[i + 1];
+                d2 += v[i + 2] * y[i + 2];
+                d3 += v[i + 3] * y[i + 3];
+            }
+            for (; i < n; ++i) d0 += v[i] * y[i];
+            double dot = (d0 + d1) + (d2 + d3);
             dot *= beta[s];
             for (int i = s + 1; i < n; ++i) y[i] -= dot * v[i];
         }
