@@ -73,20 +73,33 @@ __global__ __launch_bounds__(256) void k_cov_partial(const float* __restrict__ X
         for (int v = 0; v < 4; ++v) out[(ty * 4 + u) * CT + tx * 4 + v] = acc[u][v];
 }
 
-__global__ void k_cov_reduce(const double* __restrict__ part, int C, long N, int ntile, int npair,
-                             int nchunk, double* __restrict__ cov) {
+// One thread per entry of a tile pair (grid: pairs x entry blocks); the
+// chunk partials are added in chunk order, U loads in flight at a time.
+__global__ __launch_bounds__(256) void k_cov_reduce(const double* __restrict__ part, int C, long N, int ntile,
+                                                    int npair, int nchunk, double* __restrict__ cov) {
     const int pair0 = blockIdx.x;
     int pair = pair0, ta = 0;
     while (pair >= ntile - ta) { pair -= ntile - ta; ++ta; }
     const int tb = ta + pair;
-    for (int t = threadIdx.x; t < CT * CT; t += blockDim.x) {
-        double s = 0.0;
-        for (int k = 0; k < nchunk; ++k) s += part[((size_t)k * npair + pair0) * CT * CT + t];
-        const int a = ta * CT + t / CT, b = tb * CT + t % CT;
-        if (a < C && b < C) {
-            cov[(size_t)a * C + b] = s / (double)N;
-            cov[(size_t)b * C + a] = s / (double)N;
-        }
+    const int t = blockIdx.y * blockDim.x + threadIdx.x;
+    if (t >= CT * CT) return;
+    const double* p = part + (size_t)pair0 * CT * CT + t;
+    const size_t stride = (size_t)npair * CT * CT;
+    double s = 0.0;
+    constexpr int U = 8;
+    int k0 = 0;
+    for (; k0 + U <= nchunk; k0 += U) {
+        double x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = p[(size_t)(k0 + u) * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += x[u];
+    }
+    for (; k0 < nchunk; ++k0) s += p[(size_t)k0 * stride];
+    const int a = ta * CT + t / CT, b = tb * CT + t % CT;
+    if (a < C && b < C) {
+        cov[(size_t)a * C + b] = s / (double)N;
+        cov[(size_t)b * C + a] = s / (double)N;
     }
 }
 
@@ -121,10 +134,26 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ vals, 
         const uint32_t mask = pass == 0 ? 0u : (0xFFFFFFFFu << (32 - 8 * pass));
         for (int t = threadIdx.x; t < MAXR * 256; t += 256) (&hist[0][0])[t] = 0u;
         __syncthreads();
-        for (long i = threadIdx.x; i < N; i += 256) {
-            const uint32_t k = fkey(v[i]);
-            for (int q = 0; q < nr; ++q)
-                if ((k & mask) == prefix[q]) atomicAdd(&hist[q][(k >> shift) & 255u], 1u);
+        uint32_t pf[MAXR];
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q) pf[q] = q < nr ? prefix[q] : 0u;
+        // U loads per thread in flight before their histogram updates
+        constexpr int U = 16;
+        for (long i0 = threadIdx.x; i0 < N; i0 += 256 * U) {
+            float x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long i = i0 + (long)u * 256;
+                x[u] = v[i < N ? i : N - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i0 + (long)u * 256 >= N) break;
+                const uint32_t k = fkey(x[u]);
+#pragma unroll
+                for (int q = 0; q < MAXR; ++q)
+                    if (q < nr && (k & mask) == pf[q]) atomicAdd(&hist[q][(k >> shift) & 255u], 1u);
+            }
         }
         __syncthreads();
         if (threadIdx.x < nr) {
@@ -396,8 +425,8 @@ hipError_t launch_cov(const float* X, int C, long N, const double* mu, double* c
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cov_partial, dim3(npair, nchunk), dim3(256), 0, st, X, C, N, mu, ntile,
                        chunk, part);
-    hipLaunchKernelGGL(k_cov_reduce, dim3(npair), dim3(256), 0, st, part, C, N, ntile, npair,
-                       nchunk, cov);
+    hipLaunchKernelGGL(k_cov_reduce, dim3(npair, (CT * CT + 255) / 256), dim3(256), 0, st, part, C, N, ntile,
+                       npair, nchunk, cov);
     e = hipGetLastError();
     const hipError_t e2 = hipFreeAsync(part, st);
     return e != hipSuccess ? e : e2;
