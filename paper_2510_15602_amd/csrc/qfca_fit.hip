@@ -242,8 +242,43 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
     const int ys = max(y0, r), yend = min(ye, H - r);
     const int pxlo = max(x0, r), pxhi = min(xe, W - r);
     if (ys < yend && pxlo < pxhi) {
-        // image row yy into staging slot h (0 entering, 1 leaving); one
-        // coalesced pass for the S channels
+        // Image row yy into staging slot h (0 entering, 1 leaving), one pass
+        // for the S channels.  When a slot fits LR bytes per lane, each lane's
+        // source offsets are fixed for the tile (channel ss, column q of byte
+        // t = lane + 64 i: ss H W + x, offset 0 and bit i of lmark clear where
+        // the byte lies outside the image), and a row is loaded into
+        // registers (issue) a row before it is written to the slot (commit),
+        // so the loads overlap the previous row's counting.  Every load is
+        // issued from a valid address; markers and rows outside the image
+        // become 0x7F when committed.
+        constexpr int LR = 4;
+        const bool lfast = (S * WbP <= 64 * LR) && ((long long)S * H * W < 0x7FFFFFFFLL);
+        int loff[LR];
+        uint32_t lmark = 0;
+#pragma unroll
+        for (int i = 0; i < LR; ++i) {
+            const int t = lane + 64 * i;
+            const int ss = t / WbP, q = t - ss * WbP;
+            const int cc = cbase + ss, xl = xb0 + q;
+            const bool ok = lfast && t < S * WbP && q < Wb && cc < a.C && xl >= 0 && xl < W;
+            loff[i] = ok ? ss * H * W + xl : 0;
+            lmark |= ok ? (1u << i) : 0u;
+        }
+        const uint8_t* gbase = a.bins + (size_t)cbase * H * W;
+        auto issue = [&](uint32_t (&pre)[LR], int yy) {
+            const uint8_t* rowp = gbase + (size_t)(yy >= 0 && yy < H ? yy : 0) * W;
+#pragma unroll
+            for (int i = 0; i < LR; ++i) pre[i] = rowp[loff[i]];
+        };
+        auto commit = [&](const uint32_t (&pre)[LR], int h, int yy) {
+            const bool yok = yy >= 0 && yy < H;
+#pragma unroll
+            for (int i = 0; i < LR; ++i) {
+                const int t = lane + 64 * i;
+                if (t < S * WbP)
+                    rows[(size_t)h * S * WbP + t] = (yok && ((lmark >> i) & 1u)) ? (uint8_t)(pre[i] & 0x7Fu) : (uint8_t)0x7F;
+            }
+        };
         auto stage = [&](int h, int yy) {
             for (int t = lane; t < S * WbP; t += 64) {
                 const int ss = t / WbP, q = t - ss * WbP;
@@ -254,6 +289,7 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
                 rows[(size_t)(h * S + ss) * WbP + q] = v;
             }
         };
+        uint32_t pa[LR], pr[LR];  // the next row's entering and leaving bytes
         // the lane's counts += [entering bin <= j] (ADD), -= [leaving bin <= j]
         // (REM); the loads of a chunk are issued before its stores
         auto update = [&](bool add, bool rem) {
@@ -280,9 +316,15 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
                 }
             }
         };
+        if (lfast) issue(pa, ys - r);
         for (int yy = ys - r; yy < ys + r; ++yy) {
             __syncthreads();
-            stage(0, yy);
+            if (lfast) {
+                commit(pa, 0, yy);
+                issue(pa, yy + 1);  // the next warm-up row, or row ys + r
+            } else {
+                stage(0, yy);
+            }
             __syncthreads();
             update(true, false);
         }
@@ -290,8 +332,17 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
         for (int yc = ys; yc < yend; ++yc) {
             const bool rem = yc > ys;
             __syncthreads();
-            stage(0, yc + r);
-            if (rem) stage(1, yc - r - 1);
+            if (lfast) {
+                commit(pa, 0, yc + r);
+                if (rem) commit(pr, 1, yc - r - 1);
+                if (yc + 1 < yend) {
+                    issue(pa, yc + 1 + r);
+                    issue(pr, yc - r);
+                }
+            } else {
+                stage(0, yc + r);
+                if (rem) stage(1, yc - r - 1);
+            }
             __syncthreads();
             update(true, rem);
             __syncthreads();
