@@ -767,7 +767,7 @@ __device__ __forceinline__ int bin_fast(float rr, const float* __restrict__ e, f
 // staging area [CMAX][16] in LDS (the caller writes it out; bytes of invalid
 // values are never stored), or nullptr to store each bin directly.
 // bin = #{m : r >= e[m]}: t = (r - lo) / delta decides it on its own when t
-// lies farther than dl from every integer edge position 1 .. B-1 (dl bounds
+// lies at least dl from every integer edge position 1 .. B-1 (dl bounds
 // the stored edges' distance from the grid lo + m delta plus the FP32
 // rounding of t; a margin of one half or more disables this): floor(t) in
 // range, 0 below the grid, B-1 above it.  The test is made without branches
@@ -793,14 +793,12 @@ __device__ __forceinline__ void emit_values(const MArgs& a, int px, const int (&
             const int c = cs[e];
             const float lo = slo[c], idl = sid[c], dl = sfd[c];
             const float t = (rv[e] - lo) * idl;
-            const float fl = floorf(t);
-            const float f = t - fl;
-            const int b = (int)fl;
-            const bool neg = t < 0.f;
-            const bool hi = t >= top + dl;
-            const bool mid = (t >= 0.f) && (t < top) && (b == 0 || f >= dl) && (f <= 1.f - dl);
-            const bool dec = (dl < 0.5f) && (idl != 0.f) && (neg || hi || mid);
-            bq[e] = neg ? 0 : (hi ? B - 1 : b);
+            // the edge position nearest to t is rint(t) clamped to [1, B-1];
+            // t is decided when it lies at least dl from it, and its bin is
+            // then floor(t) clamped to [0, B-1] (NaN is never decided)
+            const float near = __builtin_amdgcn_fmed3f(rintf(t), 1.f, top);
+            const bool dec = (fabsf(t - near) >= dl) && (dl < 0.5f) && (idl != 0.f);
+            bq[e] = (int)__builtin_amdgcn_fmed3f(floorf(t), 0.f, top);
             need |= (!dec && valid[e]) ? (1u << e) : 0u;
         }
         if (__ballot(need != 0u)) {
