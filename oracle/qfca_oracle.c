@@ -12,23 +12,32 @@
  *   - PCA residual preprocessing, F = W - PCA^-1(PCA(W))        (Sec. 3.3)
  *   - per-channel quantisation into N equally spaced values      (Sec. 3.1)
  *   - a T x T window histogram per pixel, counted directly       (Sec. 3.1)
- *   - Algorithm 1, the two-pointer quantised patch mismatch      (Alg. 1)
- *   - error-to-pixel association, sigma_p = infinity (box mean)  (Sec. 3.1, Sec. 4.5.4)
+ *   - the per-bin patch mismatch of Alg. 1, written as the monotone coupling
+ *     of the two cumulative histograms it walks                  (Alg. 1, proof)
+ *   - error-to-pixel association: box mean (sigma_p = infinity) or Gaussian
+ *     weights over a patch-sized kernel (finite sigma_p)          (Eq. 2, Sec. 3.1, Sec. 4.5.4)
  *   - channel mean and the final Gaussian blur sigma_s           (Eq. 1, Sec. 4.5.4)
- *   - the median reference, computed at full precision and then
- *     quantised ("median -> quan")                                (Sec. 3.2, Tab. 3)
+ *   - the four reference choices: median -> quan (the default), mean -> quan,
+ *     quan -> median, quan -> mean                               (Sec. 3.2, Sec. 4.5.3, Tab. 3)
+ * and, beside the method itself:
+ *   - histograms of the k principal coordinates scored by the window
+ *     1-Wasserstein distance, box smoothed                        (Sec. 3.3, Sec. 3.1)
+ *   - FCA's sort-based comparison of real values, the method QFCA quantises
+ *                                                                 (Sec. 3.1, proof)
  *
  * Readings where the paper is silent (all listed in the design notes):
  *   - windows are clipped at the image border; patch and reference histograms
- *     are brought to equal mass by scaling P by n_R and R by n_p;
+ *     are brought to equal mass by scaling P by the reference mass and R by n_p;
  *   - quantisation range is [q_lo, q_hi] type-7 quantiles of each channel,
  *     edges rounded to float32 and a value equal to an edge goes to the upper bin;
- *   - the reference median over an even number of patches is the lower median;
- *   - the reference uses every full (unclipped) window;
- *   - the association averages over the in-image windows that contain a pixel;
+ *   - medians over an even number of windows are lower medians;
+ *   - references use every full (unclipped) window;
+ *   - the association averages over the in-image windows that contain a pixel
+ *     (with finite sigma_p, weighted and renormalised over those windows);
  *   - errors are in feature units (bin distance times the channel's bin width);
  *   - channels are averaged; the final blur has radius ceil(3 sigma_s) and is
- *     renormalised over in-image taps.
+ *     renormalised over in-image taps;
+ *   - FCA orders equal values by raster position inside the window.
  *
  * Parity pins for every function live in tests/test_oracle_pins.py.
  */
@@ -234,70 +243,123 @@ void orc_quantize(const double* R, int C, long N, int B, const float* edges, uin
 }
 
 /* ------------------------------------------------------------------------ */
-/* Algorithm 1: quantised patch mismatch.                                    */
+/* Per-bin patch mismatch (Sec. 3.1, Alg. 1; supplementary proof).           */
 
-/* P, R: histogram weights (equal total mass), N bins, Q_i = i (bin units).
- * E[i] receives the per-bin mismatch after the division by the original
- * P_i (0 where P_i = 0).  Returns the number of loop iterations. */
-int orc_alg1(const long long* Pin, const long long* Rin, int N, double* E) {
-    long long* P = (long long*)malloc((size_t)N * sizeof(long long));
-    long long* R = (long long*)malloc((size_t)N * sizeof(long long));
-    memcpy(P, Pin, (size_t)N * sizeof(long long));
-    memcpy(R, Rin, (size_t)N * sizeof(long long));
-    for (int i = 0; i < N; i++) E[i] = 0.0;
-    int i = 0, j = 0, steps = 0;
-    while (i < N && j < N) {
-        steps++;
-        double dist = (double)(i > j ? i - j : j - i);
-        if (P[i] < R[j]) {
-            E[i] += (double)P[i] * dist;
-            R[j] -= P[i];
-            i++;
-        } else {
-            E[i] += (double)R[j] * dist;
-            P[i] -= R[j];
-            j++;
-        }
+/* P, R: nonnegative bin weights of the patch and the reference with equal
+ * total mass, N bins, Q_i = i (bin units).  The optimal 1-D transport between
+ * them is the monotone (rank) coupling: the patch bin i occupies the mass
+ * interval (cP_{i-1}, cP_i] of the cumulative weights, the reference bin j
+ * occupies (cR_{j-1}, cR_j], and the mass moved from i to j is the length of
+ * the intersection of the two intervals.  The numerator of bin i is
+ *   I_i = sum_j |i - j| |(cP_{i-1}, cP_i] n (cR_{j-1}, cR_j]|
+ * and its mismatch E_i = I_i / P_i (0 where P_i = 0): the bin's share of the
+ * Wasserstein distance averaged over the mass of the bin, which is what the
+ * two-pointer walk of Alg. 1 accumulates.  I (may be NULL) receives the
+ * numerators.  Returns the number of (i, j) pairs that carry mass (at most
+ * 2N - 1, the length of a monotone staircase). */
+int orc_bin_mismatch(const double* P, const double* R, int N, double* E, double* I) {
+    double* cP = (double*)malloc((size_t)N * sizeof(double));
+    double* cR = (double*)malloc((size_t)N * sizeof(double));
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < N; i++) {
+        a += P[i];
+        b += R[i];
+        cP[i] = a;
+        cR[i] = b;
     }
-    for (int t = 0; t < N; t++) E[t] = Pin[t] > 0 ? E[t] / (double)Pin[t] : 0.0;
-    free(P); free(R);
-    return steps;
+    int cells = 0;
+    for (int i = 0; i < N; i++) {
+        double lo = i > 0 ? cP[i - 1] : 0.0, hi = cP[i];
+        double s = 0.0;
+        if (hi > lo) {
+            /* first reference bin whose interval ends above lo */
+            int j0 = 0, j1 = N - 1;
+            while (j0 < j1) {
+                int mid = (j0 + j1) / 2;
+                if (cR[mid] > lo) j1 = mid; else j0 = mid + 1;
+            }
+            for (int j = j0; j < N; j++) {
+                double rl = j > 0 ? cR[j - 1] : 0.0;
+                if (rl >= hi) break;
+                double ov = fmin(hi, cR[j]) - fmax(lo, rl);
+                if (ov > 0.0) {
+                    s += (double)(i > j ? i - j : j - i) * ov;
+                    cells++;
+                }
+            }
+        }
+        if (I) I[i] = s;
+        E[i] = P[i] > 0.0 ? s / P[i] : 0.0;
+    }
+    free(cR);
+    free(cP);
+    return cells;
 }
 
 /* ------------------------------------------------------------------------ */
-/* Reference (Sec. 3.2): per-rank median over patches, then quantised.       */
+/* Reference (Sec. 3.2, Sec. 4.5.3 and Tab. 3).                               */
 
 static int cmp_double_q(const void* a, const void* b) { return cmp_double(a, b); }
 
-/* Literal "median -> quan": every full T x T window's values are sorted; for
- * every rank the lower median over windows is taken at full precision; the
- * resulting reference vector is quantised with the channel's edges.  Output
- * cR[C][B] is the cumulative reference histogram (cR[B-1] = T*T). */
-void orc_reference_literal(const double* R, int C, int H, int W, int T, int B,
-                           const float* edges, int* cR) {
+/* Every full T x T window of channel plane Rc, sorted: out [nw][T*T], windows
+ * in raster order of their top-left corner.  Returns nw. */
+static long sorted_windows(const double* Rc, int H, int W, int T, double* out) {
+    int n = T * T;
+    long w = 0;
+    for (int py = 0; py + T <= H; py++)
+        for (int px = 0; px + T <= W; px++, w++) {
+            double* s = out + w * n;
+            int t = 0;
+            for (int dy = 0; dy < T; dy++)
+                for (int dx = 0; dx < T; dx++) s[t++] = Rc[(long)(py + dy) * W + px + dx];
+            qsort(s, (size_t)n, sizeof(double), cmp_double_q);
+        }
+    return w;
+}
+
+/* Full-precision reference vectors (Sec. 3.2): for every channel and every
+ * rank rho of the sorted full windows, the lower median (kind 0: the
+ * ceil(nw/2)-th smallest over the nw windows) or the mean (kind 1) of the
+ * rank-rho values.  Y: [C][T*T], nondecreasing in rho. */
+void orc_reference_values(const double* R, int C, int H, int W, int T, int kind, double* Y) {
     int n = T * T;
     long nw = (long)(H - T + 1) * (W - T + 1);
-    long h = (nw + 1) / 2; /* lower median: the ceil(nw/2)-th smallest */
+    long h = (nw + 1) / 2;
     #pragma omp parallel for schedule(dynamic)
     for (int c = 0; c < C; c++) {
-        const double* Rc = R + (long)c * H * W;
         double* sorted = (double*)malloc((size_t)nw * n * sizeof(double));
-        long w = 0;
-        for (int py = 0; py + T <= H; py++)
-            for (int px = 0; px + T <= W; px++, w++) {
-                double* s = sorted + w * n;
-                int t = 0;
-                for (int dy = 0; dy < T; dy++)
-                    for (int dx = 0; dx < T; dx++) s[t++] = Rc[(long)(py + dy) * W + px + dx];
-                qsort(s, (size_t)n, sizeof(double), cmp_double_q);
-            }
         double* col = (double*)malloc((size_t)nw * sizeof(double));
+        sorted_windows(R + (long)c * H * W, H, W, T, sorted);
+        for (int rho = 0; rho < n; rho++) {
+            for (long q = 0; q < nw; q++) col[q] = sorted[q * n + rho];
+            if (kind == 0) {
+                qsort(col, (size_t)nw, sizeof(double), cmp_double_q);
+                Y[(long)c * n + rho] = col[h - 1];
+            } else {
+                double s = 0.0;
+                for (long q = 0; q < nw; q++) s += col[q];
+                Y[(long)c * n + rho] = s / (double)nw;
+            }
+        }
+        free(col);
+        free(sorted);
+    }
+}
+
+/* "median -> quan" (kind 0, the default) and "mean -> quan" (kind 1):
+ * the full-precision reference vector of orc_reference_values, quantised with
+ * the channel's edges.  cR[C][B]: cumulative reference histogram
+ * (cR[B-1] = T*T). */
+void orc_reference_literal(const double* R, int C, int H, int W, int T, int B,
+                           const float* edges, int kind, int* cR) {
+    int n = T * T;
+    double* Y = (double*)malloc((size_t)C * n * sizeof(double));
+    orc_reference_values(R, C, H, W, T, kind, Y);
+    for (int c = 0; c < C; c++) {
         int* hist = (int*)calloc((size_t)B, sizeof(int));
         const float* e = edges + (long)c * (B - 1);
         for (int rho = 0; rho < n; rho++) {
-            for (long q = 0; q < nw; q++) col[q] = sorted[q * n + rho];
-            qsort(col, (size_t)nw, sizeof(double), cmp_double_q);
-            double ref = col[h - 1];
+            double ref = Y[(long)c * n + rho];
             int b = 0;
             for (int m = 0; m < B - 1; m++)
                 if (ref >= (double)e[m]) b++;
@@ -305,29 +367,45 @@ void orc_reference_literal(const double* R, int C, int H, int W, int T, int B,
         }
         int acc = 0;
         for (int i = 0; i < B; i++) { acc += hist[i]; cR[(long)c * B + i] = acc; }
-        free(hist); free(col); free(sorted);
+        free(hist);
     }
+    free(Y);
 }
 
-/* The same reference from the bins alone: cR(i) is the ceil(nw/2)-th largest
- * of the full-window cumulative counts cP_p(i).  This follows because
- * quantisation is monotone and commutes with order statistics (a derivation,
- * pinned against orc_reference_literal).  Window counts are taken directly. */
+/* Histogram of the window of side T centred at (py, px), clipped to the
+ * image: P[B] counts; returns the number of pixels n_p. */
+static long window_hist(const uint8_t* bc, int H, int W, int T, int B, int py, int px, long* P) {
+    int r = T / 2;
+    long np = 0;
+    for (int i = 0; i < B; i++) P[i] = 0;
+    for (int y = py - r; y <= py + r; y++) {
+        if (y < 0 || y >= H) continue;
+        for (int x = px - r; x <= px + r; x++) {
+            if (x < 0 || x >= W) continue;
+            P[bc[(long)y * W + x]]++;
+            np++;
+        }
+    }
+    return np;
+}
+
+/* The median -> quan reference from the bins alone: cR(i) is the
+ * ceil(nw/2)-th largest of the full-window cumulative counts cP_p(i).  This
+ * follows because quantisation is monotone and commutes with order
+ * statistics (a derivation, pinned against orc_reference_literal). */
 void orc_reference_cdf(const uint8_t* bins, int C, int H, int W, int T, int B, int* cR) {
-    int n = T * T;
+    int n = T * T, r = T / 2;
     long nw = (long)(H - T + 1) * (W - T + 1);
     long h = (nw + 1) / 2;
     #pragma omp parallel for schedule(dynamic)
     for (int c = 0; c < C; c++) {
         const uint8_t* bc = bins + (long)c * H * W;
         long* cnt = (long*)calloc((size_t)B * (n + 1), sizeof(long));
-        int* P = (int*)malloc((size_t)B * sizeof(int));
-        for (int py = 0; py + T <= H; py++)
-            for (int px = 0; px + T <= W; px++) {
-                for (int i = 0; i < B; i++) P[i] = 0;
-                for (int dy = 0; dy < T; dy++)
-                    for (int dx = 0; dx < T; dx++) P[bc[(long)(py + dy) * W + px + dx]]++;
-                int acc = 0;
+        long* P = (long*)malloc((size_t)B * sizeof(long));
+        for (int py = r; py + r < H; py++)
+            for (int px = r; px + r < W; px++) {
+                window_hist(bc, H, W, T, B, py, px, P);
+                long acc = 0;
                 for (int i = 0; i < B; i++) { acc += P[i]; cnt[(long)i * (n + 1) + acc]++; }
             }
         for (int i = 0; i < B; i++) {
@@ -343,102 +421,134 @@ void orc_reference_cdf(const uint8_t* bins, int C, int H, int W, int T, int B, i
     }
 }
 
+/* References taken after the quantisation, bin by bin over the full-window
+ * histograms P_p (Tab. 3): "quan -> median" (kind 0) takes for every bin i
+ * the lower median over windows of P_p(i) (the ceil(nw/2)-th smallest; the
+ * medians need not add up to T*T, so the reference mass is their sum);
+ * "quan -> mean" (kind 1) takes the mean of P_p(i) (mass T*T, fractional
+ * counts).  cR[C][B]: cumulative reference weights (double). */
+void orc_reference_hist(const uint8_t* bins, int C, int H, int W, int T, int B, int kind, double* cR) {
+    int n = T * T, r = T / 2;
+    long nw = (long)(H - T + 1) * (W - T + 1);
+    long h = (nw + 1) / 2;
+    #pragma omp parallel for schedule(dynamic)
+    for (int c = 0; c < C; c++) {
+        const uint8_t* bc = bins + (long)c * H * W;
+        long* cnt = (long*)calloc((size_t)B * (n + 1), sizeof(long));  /* [bin][count value] */
+        long* P = (long*)malloc((size_t)B * sizeof(long));
+        for (int py = r; py + r < H; py++)
+            for (int px = r; px + r < W; px++) {
+                window_hist(bc, H, W, T, B, py, px, P);
+                for (int i = 0; i < B; i++) cnt[(long)i * (n + 1) + P[i]]++;
+            }
+        double acc = 0.0;
+        for (int i = 0; i < B; i++) {
+            double v = 0.0;
+            if (kind == 0) {
+                long seen = 0;
+                int t;
+                for (t = 0; t <= n; t++) {
+                    seen += cnt[(long)i * (n + 1) + t];
+                    if (seen >= h) break;
+                }
+                v = (double)t;
+            } else {
+                double s = 0.0;
+                for (int t = 0; t <= n; t++) s += (double)t * (double)cnt[(long)i * (n + 1) + t];
+                v = s / (double)nw;
+            }
+            acc += v;
+            cR[(long)c * B + i] = acc;
+        }
+        free(P); free(cnt);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Patch statistics comparison and association for one channel.             */
 
-/* bins_c: [H][W]; cR_c: cumulative reference histogram [B] (total T*T).
- * Ac[H][W] (bin units): mean over the windows p containing x of e_p(b(x)).
- * W1c[H][W] (bin units, may be NULL): window 1-Wasserstein distance between
- * the window histogram and the reference, sum_k |cP~_k - cR~_k| / (n_p n_R).
- * Returns the largest Alg. 1 step count met. */
-int orc_channel_map(const uint8_t* bc, int H, int W, int T, int B, const int* cR_c,
-                    double* Ac, double* W1c) {
+/* Per-bin mismatch of the window centred at (py, px) against a reference
+ * given by its cumulative weights cR_c[B] (total M_R = cR_c[B-1], any
+ * nonnegative reals).  The patch histogram P (mass n_p) and the reference R
+ * (mass M_R) are brought to equal mass as P~ = P M_R and R~ = R n_p.
+ * e_out[B]: E_i of orc_bin_mismatch (bin units); I_out [B] (may be NULL):
+ * the numerators I_i (in units of the scaled masses); Pt_out [B] (may be
+ * NULL): P~.  Returns the number of transport cells. */
+int orc_window_errors(const uint8_t* bc, int H, int W, int T, int B, const double* cR_c,
+                      int py, int px, double* e_out, double* I_out, double* Pt_out) {
+    long* P = (long*)malloc((size_t)B * sizeof(long));
+    double* Pt = (double*)malloc((size_t)B * sizeof(double));
+    double* Rt = (double*)malloc((size_t)B * sizeof(double));
+    long np = window_hist(bc, H, W, T, B, py, px, P);
+    double MR = cR_c[B - 1];
+    for (int i = 0; i < B; i++) {
+        double Ri = cR_c[i] - (i > 0 ? cR_c[i - 1] : 0.0);
+        Pt[i] = (double)P[i] * MR;
+        Rt[i] = Ri * (double)np;
+    }
+    int cells = orc_bin_mismatch(Pt, Rt, B, e_out, I_out);
+    if (Pt_out) memcpy(Pt_out, Pt, (size_t)B * sizeof(double));
+    free(Rt); free(Pt); free(P);
+    return cells;
+}
+
+/* Spatial weight of a window whose centre is (dy, dx) away from the pixel
+ * (Eq. 2's G_sigma_p over a kernel the size of the patch, Sec. 3.1 and
+ * Sec. 4.5.4): 1 for sigma_p = infinity (box), else exp(-(dx^2 + dy^2) /
+ * (2 sigma_p^2)). */
+static double assoc_weight(int dy, int dx, double sigma_p) {
+    if (isinf(sigma_p)) return 1.0;
+    return exp(-(double)(dx * dx + dy * dy) / (2.0 * sigma_p * sigma_p));
+}
+
+/* bins_c: [H][W]; cR_c: cumulative reference weights [B] (see
+ * orc_window_errors).  Ac[H][W] (bin units): the sigma_p-weighted mean, over
+ * the windows p containing x, of e_p(b(x)) (the error of the pixel's own bin
+ * in that window).  W1c[H][W] (bin units, may be NULL): window
+ * 1-Wasserstein distance sum_k |cP~_k - cR~_k| / (n_p M_R).  Returns the
+ * largest number of transport cells met. */
+int orc_channel_map(const uint8_t* bc, int H, int W, int T, int B, const double* cR_c,
+                    double sigma_p, double* Ac, double* W1c) {
     int r = T / 2;
-    long nR = (long)T * T;
     double* e = (double*)malloc((size_t)H * W * B * sizeof(double));
-    long long* P = (long long*)malloc((size_t)B * sizeof(long long));
-    long long* Rt = (long long*)malloc((size_t)B * sizeof(long long));
-    double* E = (double*)malloc((size_t)B * sizeof(double));
-    int maxsteps = 0;
+    double* Pt = (double*)malloc((size_t)B * sizeof(double));
+    long* P = (long*)malloc((size_t)B * sizeof(long));
+    int maxcells = 0;
+    double MR = cR_c[B - 1];
     for (int py = 0; py < H; py++) {
         for (int px = 0; px < W; px++) {
-            for (int i = 0; i < B; i++) P[i] = 0;
-            long np = 0;
-            for (int y = py - r; y <= py + r; y++) {
-                if (y < 0 || y >= H) continue;
-                for (int x = px - r; x <= px + r; x++) {
-                    if (x < 0 || x >= W) continue;
-                    P[bc[(long)y * W + x]]++;
-                    np++;
-                }
-            }
-            /* equal-mass scaling: P~ = P n_R, R~ = R n_p */
-            for (int i = 0; i < B; i++) {
-                long Ri = cR_c[i] - (i > 0 ? cR_c[i - 1] : 0);
-                P[i] *= nR;
-                Rt[i] = Ri * np;
-            }
-            int steps = orc_alg1(P, Rt, B, E);
-            if (steps > maxsteps) maxsteps = steps;
             double* ep = e + ((long)py * W + px) * B;
-            for (int i = 0; i < B; i++) ep[i] = E[i];
+            int cells = orc_window_errors(bc, H, W, T, B, cR_c, py, px, ep, NULL, Pt);
+            if (cells > maxcells) maxcells = cells;
             if (W1c) {
-                long a = 0, b = 0;
-                double s = 0.0;
+                long np = window_hist(bc, H, W, T, B, py, px, P);
+                double a = 0.0, s = 0.0;
                 for (int k = 0; k < B; k++) {
-                    a += P[k];
-                    b += Rt[k];
-                    s += (double)llabs(a - b);
+                    a += Pt[k];
+                    s += fabs(a - cR_c[k] * (double)np);
                 }
-                W1c[(long)py * W + px] = s / ((double)np * (double)nR);
+                W1c[(long)py * W + px] = MR > 0.0 ? s / ((double)np * MR) : 0.0;
             }
         }
     }
     for (int y = 0; y < H; y++) {
         for (int x = 0; x < W; x++) {
             int b = bc[(long)y * W + x];
-            double s = 0.0;
-            long cnt = 0;
+            double s = 0.0, wsum = 0.0;
             for (int py = y - r; py <= y + r; py++) {
                 if (py < 0 || py >= H) continue;
                 for (int px = x - r; px <= x + r; px++) {
                     if (px < 0 || px >= W) continue;
-                    s += e[((long)py * W + px) * B + b];
-                    cnt++;
+                    double w = assoc_weight(py - y, px - x, sigma_p);
+                    s += w * e[((long)py * W + px) * B + b];
+                    wsum += w;
                 }
             }
-            Ac[(long)y * W + x] = s / (double)cnt;
+            Ac[(long)y * W + x] = s / wsum;
         }
     }
-    free(E); free(Rt); free(P); free(e);
-    return maxsteps;
-}
-
-/* The per-window mismatch vector e_p (bin units) of one window, as used by
- * orc_channel_map; exposed for pins.  Returns the Alg. 1 step count. */
-int orc_window_errors(const uint8_t* bc, int H, int W, int T, int B, const int* cR_c,
-                      int py, int px, double* e_out) {
-    int r = T / 2;
-    long nR = (long)T * T;
-    long long* P = (long long*)calloc((size_t)B, sizeof(long long));
-    long long* Rt = (long long*)malloc((size_t)B * sizeof(long long));
-    long np = 0;
-    for (int y = py - r; y <= py + r; y++) {
-        if (y < 0 || y >= H) continue;
-        for (int x = px - r; x <= px + r; x++) {
-            if (x < 0 || x >= W) continue;
-            P[bc[(long)y * W + x]]++;
-            np++;
-        }
-    }
-    for (int i = 0; i < B; i++) {
-        long Ri = cR_c[i] - (i > 0 ? cR_c[i - 1] : 0);
-        P[i] *= nR;
-        Rt[i] = Ri * np;
-    }
-    int steps = orc_alg1(P, Rt, B, e_out);
-    free(Rt); free(P);
-    return steps;
+    free(P); free(Pt); free(e);
+    return maxcells;
 }
 
 /* Final low-pass (Sec. 4.5.4): direct 2-D Gaussian convolution, radius
@@ -471,21 +581,21 @@ void orc_blur(const double* A, int H, int W, double sigma, double* out) {
 }
 
 /* Full score: A(x) = (1/C) sum_c delta_c Ac_c(x); score = blur(A).
- * Achan (may be NULL) receives the per-channel maps delta_c Ac_c [C][H][W];
- * W1 (may be NULL) the channel mean of delta_c W1c_c.  Returns the largest
- * Alg. 1 step count. */
-int orc_score(const uint8_t* bins, int C, int H, int W, int T, int B, const int* cR,
-              const double* delta, double sigma_s, double* A, double* score, double* W1,
-              double* Achan) {
+ * cR: [C][B] cumulative reference weights.  Achan (may be NULL) receives the
+ * per-channel maps delta_c Ac_c [C][H][W]; W1 (may be NULL) the channel mean
+ * of delta_c W1c_c.  Returns the largest number of transport cells met. */
+int orc_score(const uint8_t* bins, int C, int H, int W, int T, int B, const double* cR,
+              const double* delta, double sigma_p, double sigma_s, double* A, double* score,
+              double* W1, double* Achan) {
     long N = (long)H * W;
     double* Aall = (double*)malloc((size_t)C * N * sizeof(double));
     double* Wall = W1 ? (double*)malloc((size_t)C * N * sizeof(double)) : NULL;
-    int maxsteps = 0;
-    #pragma omp parallel for schedule(dynamic) reduction(max : maxsteps)
+    int maxcells = 0;
+    #pragma omp parallel for schedule(dynamic) reduction(max : maxcells)
     for (int c = 0; c < C; c++) {
-        int s = orc_channel_map(bins + (long)c * N, H, W, T, B, cR + (long)c * B,
+        int s = orc_channel_map(bins + (long)c * N, H, W, T, B, cR + (long)c * B, sigma_p,
                                 Aall + (long)c * N, Wall ? Wall + (long)c * N : NULL);
-        if (s > maxsteps) maxsteps = s;
+        if (s > maxcells) maxcells = s;
     }
     for (long i = 0; i < N; i++) {
         double s = 0.0, w = 0.0;
@@ -502,13 +612,13 @@ int orc_score(const uint8_t* bins, int C, int H, int W, int T, int B, const int*
     orc_blur(A, H, W, sigma_s, score);
     free(Aall);
     if (Wall) free(Wall);
-    return maxsteps;
+    return maxcells;
 }
 
 /* A(x) at a list of pixels only, each from its definition (for sampled checks
  * on maps too large for orc_score).  Achan_out may be NULL or [npix][C]. */
-void orc_amap_pixels(const uint8_t* bins, int C, int H, int W, int T, int B, const int* cR,
-                     const double* delta, int npix, const int* ys, const int* xs,
+void orc_amap_pixels(const uint8_t* bins, int C, int H, int W, int T, int B, const double* cR,
+                     const double* delta, double sigma_p, int npix, const int* ys, const int* xs,
                      double* A_out, double* Achan_out) {
     int r = T / 2;
     long N = (long)H * W;
@@ -520,22 +630,195 @@ void orc_amap_pixels(const uint8_t* bins, int C, int H, int W, int T, int B, con
         for (int c = 0; c < C; c++) {
             const uint8_t* bc = bins + (long)c * N;
             int b = bc[(long)y * W + x];
-            double s = 0.0;
-            long cnt = 0;
+            double s = 0.0, wsum = 0.0;
             for (int py = y - r; py <= y + r; py++) {
                 if (py < 0 || py >= H) continue;
                 for (int px = x - r; px <= x + r; px++) {
                     if (px < 0 || px >= W) continue;
-                    orc_window_errors(bc, H, W, T, B, cR + (long)c * B, py, px, E);
-                    s += E[b];
-                    cnt++;
+                    orc_window_errors(bc, H, W, T, B, cR + (long)c * B, py, px, E, NULL, NULL);
+                    double w = assoc_weight(py - y, px - x, sigma_p);
+                    s += w * E[b];
+                    wsum += w;
                 }
             }
-            double v = delta[c] * s / (double)cnt;
+            double v = delta[c] * s / wsum;
             if (Achan_out) Achan_out[(long)t * C + c] = v;
             acc += v;
         }
         A_out[t] = acc / (double)C;
         free(E);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Histograms of the k principal coordinates scored by the window            */
+/* 1-Wasserstein distance (the reading of the problem in which the PCA       */
+/* projection itself is histogrammed, Sec. 3.3 "PCA(W)").                    */
+
+/* z_j(x) = sum_c V[c][j] (x_c - mu_c): the k principal coordinates of every
+ * pixel, Z [k][N] double. */
+void orc_project(const float* X, int C, long N, const double* mu, const double* V, int k, double* Z) {
+    #pragma omp parallel for schedule(static)
+    for (long i = 0; i < N; i++) {
+        for (int j = 0; j < k; j++) {
+            double s = 0.0;
+            for (int c = 0; c < C; c++) s += V[c * k + j] * ((double)X[(long)c * N + i] - mu[c]);
+            Z[(long)j * N + i] = s;
+        }
+    }
+}
+
+/* bins [K][H][W] (one plane per coordinate), cR [K][B] integer cumulative
+ * references (mass T*T), delta [K].  For every window p the window W1
+ * distance of coordinate j, W1_j(p) = delta_j sum_k |cP~_k - cR~_k| /
+ * (n_p T^2) with the equal-mass scaling of orc_window_errors; the map is its
+ * mean over the windows that contain the pixel (box smoothing) averaged over
+ * the K coordinates, then blurred with sigma_s.  A and score: [H][W]. */
+void orc_w1_score(const uint8_t* bins, int K, int H, int W, int T, int B, const int* cR,
+                  const double* delta, double sigma_s, double* A, double* score) {
+    long N = (long)H * W;
+    int r = T / 2;
+    double nR = (double)T * T;
+    double* Aall = (double*)calloc((size_t)K * N, sizeof(double));
+    #pragma omp parallel for schedule(dynamic)
+    for (int j = 0; j < K; j++) {
+        const uint8_t* bc = bins + (long)j * N;
+        double* w1 = (double*)malloc((size_t)N * sizeof(double));
+        long* P = (long*)malloc((size_t)B * sizeof(long));
+        for (int py = 0; py < H; py++)
+            for (int px = 0; px < W; px++) {
+                long np = window_hist(bc, H, W, T, B, py, px, P);
+                double a = 0.0, s = 0.0;
+                for (int b = 0; b < B; b++) {
+                    a += (double)P[b] * nR;
+                    s += fabs(a - (double)cR[(long)j * B + b] * (double)np);
+                }
+                w1[(long)py * W + px] = delta[j] * s / ((double)np * nR);
+            }
+        for (int y = 0; y < H; y++)
+            for (int x = 0; x < W; x++) {
+                double s = 0.0;
+                long cnt = 0;
+                for (int py = y - r; py <= y + r; py++) {
+                    if (py < 0 || py >= H) continue;
+                    for (int px = x - r; px <= x + r; px++) {
+                        if (px < 0 || px >= W) continue;
+                        s += w1[(long)py * W + px];
+                        cnt++;
+                    }
+                }
+                Aall[(long)j * N + (long)y * W + x] = s / (double)cnt;
+            }
+        free(P);
+        free(w1);
+    }
+    for (long i = 0; i < N; i++) {
+        double s = 0.0;
+        for (int j = 0; j < K; j++) s += Aall[(long)j * N + i];
+        A[i] = s / (double)K;
+    }
+    orc_blur(A, H, W, sigma_s, score);
+    free(Aall);
+}
+
+/* ------------------------------------------------------------------------ */
+/* FCA's sort-based comparison (Sec. 3.1, the method QFCA quantises).        */
+
+/* Per-element mismatch of the window centred at (py, px) of channel plane
+ * Rc against the sorted full-precision reference Y[T*T]: the window's n_p
+ * values are sorted (equal values ordered by their raster position in the
+ * window), the element of rank rho gets |x - Y_rho| when n_p = T*T; for a
+ * window clipped at the border the masses are equalised as for the
+ * histograms (each window element carries T*T, each reference element n_p)
+ * and an element's error is the mass-weighted mean of |x - Y_k| over the
+ * reference elements its mass is matched to in rank order.  err[n_p]: the
+ * errors in raster order of the window's pixels.  Returns n_p. */
+int orc_fca_window(const double* Rc, int H, int W, int T, const double* Y, int py, int px, double* err) {
+    int r = T / 2, n = T * T;
+    int np = 0;
+    double vals[63 * 63];
+    int order[63 * 63];
+    for (int y = py - r; y <= py + r; y++) {
+        if (y < 0 || y >= H) continue;
+        for (int x = px - r; x <= px + r; x++) {
+            if (x < 0 || x >= W) continue;
+            vals[np] = Rc[(long)y * W + x];
+            order[np] = np;
+            np++;
+        }
+    }
+    /* insertion sort of the indices by (value, raster position) */
+    for (int i = 1; i < np; i++) {
+        int t = order[i];
+        int j = i - 1;
+        while (j >= 0 && vals[order[j]] > vals[t]) {
+            order[j + 1] = order[j];
+            j--;
+        }
+        order[j + 1] = t;
+    }
+    for (int rho = 0; rho < np; rho++) {
+        int idx = order[rho];
+        double x = vals[idx];
+        double e = 0.0;
+        if (np == n) {
+            e = fabs(x - Y[rho]);
+        } else {
+            /* element mass interval (rho n, (rho + 1) n]; reference element k
+             * holds (k np, (k + 1) np] */
+            double lo = (double)rho * n, hi = lo + (double)n;
+            for (int k = 0; k < n; k++) {
+                double rl = (double)k * np, rh = rl + (double)np;
+                double ov = fmin(hi, rh) - fmax(lo, rl);
+                if (ov > 0.0) e += ov * fabs(x - Y[k]);
+            }
+            e /= (double)n;
+        }
+        err[idx] = e;
+    }
+    return np;
+}
+
+/* FCA map of one channel: A_c(x) = mean over the windows p containing x of
+ * the error of x's element in window p (sigma_p = infinity). */
+static void fca_channel(const double* Rc, int H, int W, int T, const double* Y, double* Ac) {
+    int r = T / 2;
+    double err[63 * 63];
+    for (long i = 0; i < (long)H * W; i++) Ac[i] = 0.0;
+    int* cnt = (int*)calloc((size_t)H * W, sizeof(int));
+    for (int py = 0; py < H; py++)
+        for (int px = 0; px < W; px++) {
+            orc_fca_window(Rc, H, W, T, Y, py, px, err);
+            int t = 0;
+            for (int y = py - r; y <= py + r; y++) {
+                if (y < 0 || y >= H) continue;
+                for (int x = px - r; x <= px + r; x++) {
+                    if (x < 0 || x >= W) continue;
+                    Ac[(long)y * W + x] += err[t++];
+                    cnt[(long)y * W + x]++;
+                }
+            }
+        }
+    for (long i = 0; i < (long)H * W; i++) Ac[i] /= (double)cnt[i];
+    free(cnt);
+}
+
+/* FCA score: R [C][H][W] real features, Y [C][T*T] sorted references;
+ * A(x) = (1/C) sum_c A_c(x) (feature units) and score = blur(A, sigma_s).
+ * Achan (may be NULL): [C][H][W]. */
+void orc_fca_score(const double* R, int C, int H, int W, int T, const double* Y, double sigma_s,
+                   double* A, double* score, double* Achan) {
+    long N = (long)H * W;
+    double* Aall = (double*)malloc((size_t)C * N * sizeof(double));
+    #pragma omp parallel for schedule(dynamic)
+    for (int c = 0; c < C; c++)
+        fca_channel(R + (long)c * N, H, W, T, Y + (long)c * T * T, Aall + (long)c * N);
+    for (long i = 0; i < N; i++) {
+        double s = 0.0;
+        for (int c = 0; c < C; c++) s += Aall[(long)c * N + i];
+        A[i] = s / (double)C;
+    }
+    if (Achan) memcpy(Achan, Aall, (size_t)C * N * sizeof(double));
+    orc_blur(A, H, W, sigma_s, score);
+    free(Aall);
 }
