@@ -95,8 +95,9 @@ qfca_status qfca_ctx_destroy(qfca_ctx ctx);
  * qfca_ctx_profile_read synchronises on the recorded events and returns the
  * summed duration (ms) and the number of launches of one kernel since the
  * previous read, then resets that kernel's record.  Kernel ids:
- *   0 score (window histograms, Alg. 1, association), 1 projection +
- *   quantisation, 2 channel mean, 3 blur. */
+ *   0 score (zeroing of the channel sum, window histograms, Alg. 1,
+ *   association, channel sum), 1 projection + quantisation, 2 channel mean
+ *   and blur. */
 qfca_status qfca_ctx_profile(qfca_ctx ctx, int32_t enable);
 qfca_status qfca_ctx_profile_read(qfca_ctx ctx, int32_t kernel, double* total_ms,
                                   int64_t* launches);
@@ -105,9 +106,12 @@ qfca_status qfca_ctx_profile_read(qfca_ctx ctx, int32_t kernel, double* total_ms
  * this context: Ws output columns per strip, Hb output rows per band, S
  * channels per wavefront (S * lanes-per-channel <= 64, where lanes per
  * channel is the next power of two >= max(B, 8)) and the kernel variant
- * (0: column walk for any T; 1: block walk, T in 3..31).  Ws == 0 restores
- * the automatic choice.  A tile that does not fit in 64 KiB of LDS makes the
- * later score call fail with QFCA_E_UNSUPPORTED. */
+ * (0: column walk for any T; 1: block walk, T in 3..31).  The block walk
+ * rounds Ws down to a multiple of T (at least T), which places its blocks of
+ * T patch columns at the same image columns in every tiling: its maps are
+ * then bitwise the same for every (Ws, Hb, S).  Ws == 0 restores the
+ * automatic choice.  A tile that does not fit in LDS makes the later score
+ * call fail with QFCA_E_UNSUPPORTED. */
 qfca_status qfca_ctx_set_tile(qfca_ctx ctx, int32_t Ws, int32_t Hb, int32_t S, int32_t variant);
 
 /* Zero-shot fit on one image (Sec. 3.2, Sec. 3.3).  Synchronous.
@@ -162,10 +166,32 @@ qfca_status qfca_quantize(qfca_ctx ctx, qfca_model model, const float* X, int32_
  *   w1:    device [H][W] float32 out, channel mean of delta_c times the window
  *          1-Wasserstein distance sum_k |cP_k - cR_k| / (n_p n_R) (nullable)
  *   achan: device [C][H][W] float32 out, per-channel delta_c-weighted maps
- *          before the channel mean (nullable)
+ *          before the channel mean (nullable; an inspection output, the
+ *          channel mean does not read it)
+ * The channel mean is summed in 64-bit fixed point with integer atomics
+ * (each per-channel value rounded once, at 2^-62 of the largest possible
+ * sum), so it does not depend on the order of the channel groups; with the
+ * block walk (T in 3..31) every output is bitwise independent of the tile.
+ * Library scratch: 8 bytes per pixel (16 with w1).
  * Requires a model with a reference (QFCA_E_STATE otherwise). */
 qfca_status qfca_score_map(qfca_ctx ctx, qfca_model model, const uint8_t* bins, int32_t H,
                            int32_t W, float* score, float* amap, float* w1, float* achan);
+
+/* Inspection of the integer stages of qfca_score_map (Sec. 3.1, Alg. 1):
+ * runs the same score kernel code, built to also store, for every pixel p
+ * (window centre) and every bin j < B of every channel c,
+ *   cp: device [C][H][W][B] int32 out, cp[c][p][j] = #{q in N(p) : b_c(q) <= j},
+ *       the window's cumulative histogram (N(p) the T x T window clipped to
+ *       the image, n_p = |N(p)|);
+ *   I:  device [C][H][W][B] int32 out, the transport numerator of bin j:
+ *       sum_i |i - j| pi_ji over the monotone coupling of the patch masses
+ *       P_j T^2 and the reference masses R_i n_p (both of total T^2 n_p),
+ *       so that the bin's error is I / (P_j T^2) in bin units.
+ * Every value is an exact integer.  Needs the block walk (T in 3..31;
+ * QFCA_E_UNSUPPORTED otherwise) and a model with a reference.  Slow (a
+ * store per window and bin): for testing.  Stream-ordered. */
+qfca_status qfca_inspect_windows(qfca_ctx ctx, qfca_model model, const uint8_t* bins, int32_t H,
+                                 int32_t W, int32_t* cp, int32_t* I);
 
 /* One image of a batch. */
 typedef struct {
@@ -176,17 +202,19 @@ typedef struct {
     float* score;      /* device [H][W] float32 out */
     uint8_t* bins;     /* device [C][H][W] uint8 out, or NULL for library scratch */
     float* amap;       /* device [H][W] float32 out (map before the blur), or NULL */
+    float* achan;      /* device [C][H][W] float32 out, per-channel maps as in
+                          qfca_score_map (inspection output), or NULL */
 } qfca_job;
 
 /* Quantise and score n (1..256) images of different sizes: one persistent
  * kernel drains a device work queue holding the projection tiles of every
  * image followed by their score tiles (a score tile waits for its image's
- * projection tiles), then batched channel-mean and blur kernels run; the
+ * projection tiles), then a batched channel-mean and blur kernel runs; the
  * launch sequence is a HIP graph captured once per context and shape class
- * and replayed.  Stream-ordered like qfca_score_map; the per-channel
- * arithmetic is that of qfca_quantize + qfca_score_map, so results agree
- * with them to float rounding, and each image's result does not depend on
- * the other images of the batch.  Requires preproc = QFCA_PRE_RESIDUAL,
+ * and replayed.  Stream-ordered like qfca_score_map; the arithmetic is that
+ * of qfca_quantize + qfca_score_map with the block walk, so every output is
+ * bitwise the one those calls give for the same image, whatever the other
+ * images of the batch and the tile.  Requires preproc = QFCA_PRE_RESIDUAL,
  * T in {5, 7, 9, 11, 15, 31} and (C, k) within (64, 16), (256, 32) or
  * (512, 64) (FP32; BF16 needs C > 128); QFCA_E_UNSUPPORTED otherwise. */
 qfca_status qfca_score_batch(qfca_ctx ctx, const qfca_job* jobs, int32_t n);
@@ -196,7 +224,7 @@ qfca_status qfca_score_batch(qfca_ctx ctx, const qfca_job* jobs, int32_t n);
 qfca_status qfca_batch_error(qfca_ctx ctx, int32_t* failed);
 
 /* Tile autotuner: runs the batch `jobs` with candidate score tiles (strip
- * widths n T - (T - 1), band heights 64..256) timed with HIP events, keeps the
+ * widths n T, band heights 64..256) timed with HIP events, keeps the
  * fastest as this context's tile for later score calls (single image and
  * batch) with the same (T, B), and returns it.  Synchronous; overwrites the
  * jobs' outputs. */
@@ -210,6 +238,10 @@ qfca_status qfca_autotune(qfca_ctx ctx, const qfca_job* jobs, int32_t n, int32_t
  * bytes must equal the field size; QFCA_E_STATE if the field is not set. */
 qfca_status qfca_model_params(qfca_model model, qfca_params* out);
 qfca_status qfca_model_read(qfca_model model, int32_t field, void* host_dst, size_t bytes);
+/* Frees a model.  No work that uses it may still be queued on any stream.
+ * Releasing device memory waits until the device is idle, so this stalls
+ * every stream of the device (a live server's included) for as long as its
+ * queued work takes: destroy models outside latency-critical loops. */
 qfca_status qfca_model_destroy(qfca_model model);
 
 /* Model serialisation, for storing fitted models (for instance one per
@@ -239,7 +271,7 @@ qfca_status qfca_model_import(qfca_ctx ctx, const void* host_buf, size_t bytes, 
  * requests that can share a launch (same C, k, B, T, sigma_s, precision);
  * a request whose memory does not fit waits, and later requests of its kind
  * wait behind it.  Working memory per request is
- * 256-byte-aligned C*H*W (bins) + 4*C*H*W (channel maps) + 4*H*W bytes. */
+ * 256-byte-aligned C*H*W (bins) + 8*H*W (fixed-point channel sum) bytes. */
 typedef struct qfca_server_s* qfca_server;
 
 typedef struct {

@@ -33,9 +33,10 @@ EXPORTS = ("qfca_status_str", "qfca_last_error", "qfca_version", "qfca_ctx_creat
            "qfca_host_sym_eig", "qfca_host_sym_eig_top", "qfca_ctx_profile",
            "qfca_ctx_profile_read", "qfca_ctx_set_tile", "qfca_score_batch", "qfca_batch_error",
            "qfca_autotune", "qfca_clock", "qfca_server_create", "qfca_server_submit",
-           "qfca_server_poll", "qfca_server_drain", "qfca_server_stats", "qfca_server_destroy")
+           "qfca_server_poll", "qfca_server_drain", "qfca_server_stats", "qfca_server_destroy",
+           "qfca_inspect_windows")
 
-KERNELS = {"score": 0, "proj": 1, "chanmean": 2, "blur": 3}
+KERNELS = {"score": 0, "proj": 1, "finish": 2}
 
 
 class QfcaError(RuntimeError):
@@ -63,7 +64,7 @@ class Params(ctypes.Structure):
 class Job(ctypes.Structure):
     _fields_ = [("model", ctypes.c_void_p), ("X", ctypes.c_void_p), ("H", ctypes.c_int32),
                 ("W", ctypes.c_int32), ("score", ctypes.c_void_p), ("bins", ctypes.c_void_p),
-                ("amap", ctypes.c_void_p)]
+                ("amap", ctypes.c_void_p), ("achan", ctypes.c_void_p)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -111,6 +112,7 @@ def lib():
         L.qfca_fit_reference.argtypes = [P, P, P, i32, i32]
         L.qfca_quantize.argtypes = [P, P, P, i32, i32, P, P]
         L.qfca_score_map.argtypes = [P, P, P, i32, i32, P, P, P, P]
+        L.qfca_inspect_windows.argtypes = [P, P, P, i32, i32, P, P]
         L.qfca_model_params.argtypes = [P, ctypes.POINTER(Params)]
         L.qfca_model_read.argtypes = [P, i32, P, sz]
         L.qfca_model_destroy.argtypes = [P]
@@ -144,7 +146,7 @@ def lib():
                      "qfca_model_params", "qfca_model_read", "qfca_model_destroy", "qfca_model_export",
                      "qfca_model_import",
                      "qfca_ctx_profile", "qfca_ctx_profile_read", "qfca_ctx_set_tile",
-                     "qfca_score_batch", "qfca_batch_error", "qfca_autotune"):
+                     "qfca_score_batch", "qfca_batch_error", "qfca_autotune", "qfca_inspect_windows"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -362,12 +364,13 @@ def qfca_score_map(ctx: Context, model: Model, bins, amap=False, w1=False, achan
 
 
 def _jobs(items):
-    """items: sequence of (model, X, score[, bins[, amap]])."""
+    """items: sequence of (model, X, score[, bins[, amap[, achan]]])."""
     arr = (Job * len(items))()
     for i, it in enumerate(items):
         model, X, score = it[0], it[1], it[2]
         bins = it[3] if len(it) > 3 else None
         amap = it[4] if len(it) > 4 else None
+        achan = it[5] if len(it) > 5 else None
         import torch
         _dev_tensor(X, torch.float32, "X", 3)
         _dev_tensor(score, torch.float32, "score", 2)
@@ -378,15 +381,35 @@ def _jobs(items):
             _dev_tensor(bins, torch.uint8, "bins", 3)
         if amap is not None:
             _dev_tensor(amap, torch.float32, "amap", 2)
+        if achan is not None:
+            _dev_tensor(achan, torch.float32, "achan", 3)
+            if tuple(achan.shape) != (C, H, W):
+                raise ValueError("achan shape does not match")
         arr[i] = Job(model.handle.value if hasattr(model.handle, "value") else model.handle,
                      X.data_ptr(), H, W, score.data_ptr(), bins.data_ptr() if bins is not None else None,
-                     amap.data_ptr() if amap is not None else None)
+                     amap.data_ptr() if amap is not None else None,
+                     achan.data_ptr() if achan is not None else None)
     return arr
+
+
+def qfca_inspect_windows(ctx: Context, model: Model, bins):
+    """Integer stages of the score path for every window: (cp, I), each a
+    [C, H, W, B] int32 device tensor (see qfca.h)."""
+    import torch
+    _dev_tensor(bins, torch.uint8, "bins", 3)
+    C, H, W = bins.shape
+    if C != model.params.C:
+        raise ValueError("bins do not match the model's channel count")
+    B = model.params.B
+    cp = torch.empty((C, H, W, B), dtype=torch.int32, device=bins.device)
+    I = torch.empty((C, H, W, B), dtype=torch.int32, device=bins.device)
+    _check(lib().qfca_inspect_windows(ctx.handle, model.handle, _ptr(bins), H, W, _ptr(cp), _ptr(I)))
+    return cp, I
 
 
 def qfca_score_batch(ctx: Context, items):
     """Quantise and score a batch.  items: sequence of (model, X [C,H,W],
-    score [H,W] out[, bins [C,H,W] out[, amap [H,W] out]])."""
+    score [H,W] out[, bins [C,H,W] out[, amap [H,W] out[, achan [C,H,W] out]]])."""
     arr = _jobs(items)
     _check(lib().qfca_score_batch(ctx.handle, arr, len(items)))
 

@@ -21,8 +21,8 @@ void set_error(const std::string& msg) { g_err = msg; }
 using namespace qfca;
 
 enum Slot {
-    SL_ACHAN = 0, SL_W1CHAN, SL_AMAP, SL_W1TMP, SL_RESID, SL_BINS, SL_COUNTS, SL_SEL,
-    SL_COV, SL_MU, SL_RANKS, SL_CR, SL_BBINS, SL_BACHAN, SL_BAMAP, SL_COUNT
+    SL_ASUM = 0, SL_W1SUM, SL_SCORE, SL_RESID, SL_BINS, SL_COUNTS, SL_SEL,
+    SL_COV, SL_MU, SL_RANKS, SL_CR, SL_BBINS, SL_BASUM, SL_COUNT
 };
 
 struct GraphEntry {
@@ -30,7 +30,7 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
 };
 
-enum { K_SCORE = 0, K_PROJ, K_CHANMEAN, K_BLUR, K_COUNT };
+enum { K_SCORE = 0, K_PROJ, K_FINISH, K_COUNT };
 
 struct qfca_ctx_s {
     int device = 0;
@@ -253,6 +253,18 @@ qfca_status upload_quant(qfca_model m) {
     return QFCA_OK;
 }
 
+// Fixed-point scale of the channel sums (see KArgs): the largest power of two
+// s with s (B - 1) sum_c delta_c <= 2^62, so that the sum over channels of
+// per-channel values v_c <= (B - 1) delta_c, each rounded to llrint(v_c s),
+// stays below 2^63 with room for the float32 rounding of v_c.
+double fixed_point_scale(const std::vector<double>& delta, int B) {
+    double vmax = 0.0;
+    for (double d : delta) vmax += d;
+    vmax *= (double)std::max(B - 1, 0);
+    if (!(vmax > 0.0) || !std::isfinite(vmax)) return 1.0;
+    return ldexp(1.0, (int)floor(log2(ldexp(1.0, 62) / vmax)));
+}
+
 // Reference-dependent tables of the score kernel (see ScoreTables).
 qfca_status upload_tables(qfca_model m) {
     const int C = m->p.C, B = m->p.B, T = m->p.T;
@@ -288,6 +300,7 @@ qfca_status upload_tables(qfca_model m) {
     HIP_TRY(upload(m, &m->d_cR, m->cR.data(), m->cR.size()));
     m->tab.delta = m->d_delta;
     m->tab.Bp = Bp;
+    m->tab.fxs = fixed_point_scale(m->delta, B);
     m->has_ref = true;
     return QFCA_OK;
 }
@@ -346,18 +359,59 @@ ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
     t.S = 64 / Bp;
     t.variant = score_has_block_kernel(T) ? 1 : 0;
     if (t.variant) t.S = std::min(t.S, score_block_max_S(T));
-    // block walk: strips of n T - 2r columns fill whole blocks of T patch columns
-    t.Ws = t.variant ? std::max(8, 4 * T - (T - 1)) : 64;
+    // block walk: strips of 3 T columns (a multiple of T, so that blocks sit
+    // at the same image columns in every strip; 3T + 2r patch columns fill
+    // four blocks of T but one)
+    t.Ws = t.variant ? 3 * T : 64;
     t.Hb = 128;
     // prefer at most 64 KiB per wavefront (occupancy); very large windows may
     // use up to the 160 KiB of a compute unit
     while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.S > 1) t.S >>= 1;
-    while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.Ws > 8) t.Ws >>= 1;
+    while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.Ws > 8)
+        t.Ws = t.variant ? (t.Ws > T ? t.Ws - T : 8) : t.Ws >> 1;
     if (t.variant == 1 && t.Ws < T) t.variant = 0;  // the block walk needs strips of at least T columns
     (void)C;
     ctx->tiles[key] = t;
     return t;
 }
+
+// The score launch sequence of qfca_score_map on caller-given fixed-point
+// buffers asum [H][W] (and w1sum [H][W] when w1 is wanted): zero them, score
+// tiles, channel mean and blur.
+qfca_status score_map_into(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
+                           float* score, float* amap, float* w1, float* achan, long long* asum,
+                           long long* w1sum, int* dbg_cp = nullptr, int* dbg_I = nullptr) {
+    ScoreLaunch L;
+    L.dbg_cp = dbg_cp; L.dbg_I = dbg_I;
+    L.bins = bins; L.C = m->p.C; L.H = H; L.W = W; L.T = m->p.T; L.B = m->p.B;
+    L.tab = m->tab;
+    L.fxs = m->tab.fxs;
+    L.asum = asum; L.w1sum = w1 ? w1sum : nullptr; L.achan = achan;
+    if (ctx->tile_override.Ws > 0) {
+        L.tile = ctx->tile_override;
+        if (L.tile.S * m->Bp > 64) return fail(QFCA_E_UNSUPPORTED, "S * lanes per channel exceeds 64");
+        if (L.tile.variant == 1 && (!score_has_block_kernel(m->p.T) || L.tile.S > score_block_max_S(m->p.T) ||
+                                    L.tile.Ws < m->p.T))
+            L.tile.variant = 0;
+        if (score_lds_bytes(m->p.T, m->Bp, L.tile.S, L.tile.Ws, L.tile.variant) > 160 * 1024)
+            return fail(QFCA_E_UNSUPPORTED, "tile does not fit in LDS");
+    } else {
+        L.tile = choose_tile(ctx, m->p.C, H, W, m->p.T, m->p.B, m->Bp);
+    }
+    if (dbg_cp && L.tile.variant != 1)
+        return fail(QFCA_E_UNSUPPORTED, "window inspection needs the block walk (T in 3..31, S within its limit)");
+    {
+        KernelTimer kt(ctx, K_SCORE);
+        HIP_TRY(launch_score(L, ctx->stream));
+    }
+    {
+        KernelTimer kt(ctx, K_FINISH);
+        HIP_TRY(launch_finish(asum, L.w1sum, 1.0 / (m->tab.fxs * (double)m->p.C), H, W, m->p.sigma_s, amap, w1,
+                              score, ctx->stream));
+    }
+    return QFCA_OK;
+}
+
 
 }  // namespace
 
@@ -473,8 +527,7 @@ qfca_status qfca_ctx_destroy(qfca_ctx ctx) {
 qfca_status qfca_model_destroy(qfca_model m) {
     if (!m) return QFCA_OK;
     (void)hipSetDevice(m->device);
-    (void)hipDeviceSynchronize();
-    delete m;
+    delete m;  // hipFree of its arrays waits for the device (see qfca.h)
     return QFCA_OK;
 }
 
@@ -875,6 +928,23 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
     return QFCA_OK;
 }
 
+qfca_status qfca_inspect_windows(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
+                                 int32_t* cp, int32_t* I) {
+    if (!ctx || !m || !bins || !cp || !I) return fail(QFCA_E_ARG, "NULL argument");
+    qfca_status st = check_shape(H, W, m->p.C);
+    if (st != QFCA_OK) return st;
+    if (!m->has_ref) return fail(QFCA_E_STATE, "model has no reference");
+    if (m->device != ctx->device) return fail(QFCA_E_ARG, "model and context are on different devices");
+    if (!score_has_block_kernel(m->p.T)) return fail(QFCA_E_UNSUPPORTED, "window inspection needs T in 3..31");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const size_t N = (size_t)H * W;
+    long long* asum = nullptr;
+    float* score = nullptr;
+    HIP_TRY(scratch(ctx, SL_ASUM, N * 8, &asum));
+    HIP_TRY(scratch(ctx, SL_SCORE, N * 4, &score));
+    return score_map_into(ctx, m, bins, H, W, score, nullptr, nullptr, nullptr, asum, nullptr, cp, I);
+}
+
 qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
                            float* score, float* amap, float* w1, float* achan) {
     if (!ctx || !m || !bins || !score) return fail(QFCA_E_ARG, "NULL argument");
@@ -883,44 +953,12 @@ qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int3
     if (!m->has_ref) return fail(QFCA_E_STATE, "model has no reference");
     if (m->device != ctx->device) return fail(QFCA_E_ARG, "model and context are on different devices");
     HIP_TRY(hipSetDevice(ctx->device));
-    const int C = m->p.C;
     const size_t N = (size_t)H * W;
-    hipStream_t s = ctx->stream;
-    float* ach = achan;
-    if (!ach) HIP_TRY(scratch(ctx, SL_ACHAN, (size_t)C * N * 4, &ach));
-    float* w1ch = nullptr;
-    float* w1o = w1;
-    if (w1) HIP_TRY(scratch(ctx, SL_W1CHAN, (size_t)C * N * 4, &w1ch));
-    float* am = amap;
-    if (!am) HIP_TRY(scratch(ctx, SL_AMAP, N * 4, &am));
-    ScoreLaunch L;
-    L.bins = bins; L.C = C; L.H = H; L.W = W; L.T = m->p.T; L.B = m->p.B;
-    L.tab = m->tab;
-    L.achan = ach; L.w1chan = w1ch;
-    if (ctx->tile_override.Ws > 0) {
-        L.tile = ctx->tile_override;
-        if (L.tile.S * m->Bp > 64) return fail(QFCA_E_UNSUPPORTED, "S * lanes per channel exceeds 64");
-        if (L.tile.variant == 1 && (!score_has_block_kernel(m->p.T) || L.tile.S > score_block_max_S(m->p.T) ||
-                                    L.tile.Ws < m->p.T))
-            L.tile.variant = 0;
-        if (score_lds_bytes(m->p.T, m->Bp, L.tile.S, L.tile.Ws, L.tile.variant) > 160 * 1024)
-            return fail(QFCA_E_UNSUPPORTED, "tile does not fit in LDS");
-    } else {
-        L.tile = choose_tile(ctx, C, H, W, m->p.T, m->p.B, m->Bp);
-    }
-    {
-        KernelTimer kt(ctx, K_SCORE);
-        HIP_TRY(launch_score(L, s));
-    }
-    {
-        KernelTimer kt(ctx, K_CHANMEAN);
-        HIP_TRY(launch_chanmean(ach, w1ch, C, (int)N, am, w1o, s));
-    }
-    {
-        KernelTimer kt(ctx, K_BLUR);
-        HIP_TRY(launch_blur(am, H, W, m->p.sigma_s, score, s));
-    }
-    return QFCA_OK;
+    long long* asum = nullptr;
+    long long* w1sum = nullptr;
+    HIP_TRY(scratch(ctx, SL_ASUM, N * 8, &asum));
+    if (w1) HIP_TRY(scratch(ctx, SL_W1SUM, N * 8, &w1sum));
+    return score_map_into(ctx, m, bins, H, W, score, amap, w1, achan, asum, w1sum);
 }
 
 }  // extern "C"
@@ -934,6 +972,7 @@ ScoreTile batch_tile(qfca_ctx ctx, const qfca_params& p) {
     ScoreTile t = choose_tile(ctx, p.C, 256, 256, p.T, p.B, Bp);
     if (ctx->tile_override.Ws > 0) t = ctx->tile_override;
     t.variant = 1;
+    t.Ws = score_block_ws(p.T, t.Ws);
     t.S = std::min(std::min(t.S, 64 / Bp), score_block_max_S(p.T));
     if (t.S < 1) t.S = 1;
     // four wavefront regions and the shared reciprocal table must fit in LDS:
@@ -970,7 +1009,7 @@ qfca_status qfca::batch_job_check(qfca_ctx ctx, const qfca_job& J, const qfca_pa
     return QFCA_OK;
 }
 
-qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n, float* const* achan_ext,
+qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n, long long* const* asum_ext,
                                   int32_t* err_host) {
     if (!ctx || !jobs) return fail(QFCA_E_ARG, "NULL argument");
     if (n < 1 || n > BATCH_MAXJ) return fail(QFCA_E_ARG, "n must be in [1, 256]");
@@ -980,7 +1019,7 @@ qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n,
     for (int i = 0; i < n; ++i) {
         qfca_status st = batch_job_check(ctx, jobs[i], p);
         if (st != QFCA_OK) return st;
-        if (achan_ext && !achan_ext[i]) return fail(QFCA_E_ARG, "NULL channel-map buffer");
+        if (asum_ext && !asum_ext[i]) return fail(QFCA_E_ARG, "NULL channel-sum buffer");
     }
     const int CM = mfma_cmax(p.C, p.proj_prec), KT = mfma_kt(p.k, p.proj_prec);
     HIP_TRY(hipSetDevice(ctx->device));
@@ -1001,27 +1040,24 @@ qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n,
     } else {
         HIP_TRY(hipEventSynchronize(ctx->staged));  // previous upload has left the staging buffers
     }
-    // scratch for bins, per-channel maps and channel means
-    size_t nb = 0, na = 0, nm = 0;
+    // scratch for bins and the fixed-point channel sums
+    size_t nb = 0, na = 0;
     for (int i = 0; i < n; ++i) {
         const size_t N = (size_t)jobs[i].H * jobs[i].W;
         if (!jobs[i].bins) nb += (size_t)p.C * N;
-        if (!achan_ext) na += (size_t)p.C * N;
-        if (!jobs[i].amap) nm += N;
+        if (!asum_ext) na += N;
     }
     uint8_t* sb = nullptr;
-    float* sa = nullptr;
-    float* sm = nullptr;
+    long long* sa = nullptr;
     HIP_TRY(scratch(ctx, SL_BBINS, std::max<size_t>(nb, 1), &sb));
-    HIP_TRY(scratch(ctx, SL_BACHAN, std::max<size_t>(na, 1) * 4, &sa));
-    HIP_TRY(scratch(ctx, SL_BAMAP, std::max<size_t>(nm, 1) * 4, &sm));
+    HIP_TRY(scratch(ctx, SL_BASUM, std::max<size_t>(na, 1) * 8, &sa));
     BatchHeader& h = *ctx->h_hdr;
     memset(&h, 0, sizeof(h));
     h.n = n;
     const int S = tile.S;
     const int cgroups = (p.C + S - 1) / S;
     int np = 0, ns = 0;
-    size_t ob = 0, oa = 0, om = 0;
+    size_t ob = 0, oa = 0;
     for (int i = 0; i < n; ++i) {
         const qfca_job& J = jobs[i];
         const qfca_model m = J.model;
@@ -1030,10 +1066,8 @@ qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n,
         const int N = J.H * J.W;
         uint8_t* bins = J.bins ? J.bins : sb + ob;
         if (!J.bins) ob += (size_t)p.C * N;
-        float* achan = achan_ext ? achan_ext[i] : sa + oa;
-        if (!achan_ext) oa += (size_t)p.C * N;
-        float* amap = J.amap ? J.amap : sm + om;
-        if (!J.amap) om += N;
+        long long* asum = asum_ext ? asum_ext[i] : sa + oa;
+        if (!asum_ext) oa += (size_t)N;
         b.pa.X = J.X; b.pa.C = p.C; b.pa.N = N; b.pa.k = p.k; b.pa.B = p.B;
         b.pa.mu = m->d_mu; b.pa.V1 = m->d_V1; b.pa.V2 = m->d_V2; b.pa.edges = m->d_edges;
         b.pa.lo = m->d_lo; b.pa.inv_delta = m->d_invd; b.pa.fastd = m->d_fastd; b.pa.bins = bins;
@@ -1043,11 +1077,14 @@ qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n,
         b.sa.Bp = Bp; b.sa.S = S; b.sa.r = p.T / 2; b.sa.m = p.T * p.T; b.sa.Ws = tile.Ws;
         b.sa.Hb = tile.Hb; b.sa.WbA = tile.Ws + 4 * (p.T / 2);
         b.sa.psig = m->tab.psig; b.sa.cRm1 = m->tab.cRm1; b.sa.Dm1 = m->tab.Dm1; b.sa.cRl = m->tab.cRl;
-        b.sa.rcp = m->tab.rcp; b.sa.delta = m->d_delta; b.sa.achan = achan; b.sa.w1chan = nullptr;
+        b.sa.rcp = m->tab.rcp; b.sa.delta = m->d_delta;
+        b.sa.fxs = m->tab.fxs; b.sa.asum = asum; b.sa.w1sum = nullptr; b.sa.achan = J.achan;
         b.ntiles_proj = b.pa.ntiles;
         b.nstrips = (J.W + tile.Ws - 1) / tile.Ws;
         b.nbands = (J.H + tile.Hb - 1) / tile.Hb;
-        b.amap = amap;
+        b.asum = asum;
+        b.inv_scale = 1.0 / (m->tab.fxs * (double)p.C);
+        b.amap = J.amap;
         b.score = J.score;
         h.proj_prefix[i] = np;
         h.score_prefix[i] = ns;
@@ -1118,18 +1155,28 @@ qfca_status qfca_batch_error(qfca_ctx ctx, int32_t* failed) {
 
 qfca_status qfca_autotune(qfca_ctx ctx, const qfca_job* jobs, int32_t n, int32_t* best_Ws,
                           int32_t* best_Hb, double* best_ms) {
-    if (!ctx || !jobs || n < 1 || !best_Ws || !best_Hb) return fail(QFCA_E_ARG, "NULL argument");
+    if (!ctx || !jobs || n < 1 || !best_Ws || !best_Hb || !jobs[0].model) return fail(QFCA_E_ARG, "NULL argument");
     const qfca_params p = jobs[0].model->p;
     const int T = p.T, Bp = batch_lanes(p.B);
-    const ScoreTile saved = ctx->tile_override;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    // the tile override and the two events are restored and released on
+    // every exit, including the early returns of HIP_TRY
+    struct Guard {
+        qfca_ctx ctx;
+        ScoreTile saved;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Guard() {
+            ctx->tile_override = saved;
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } g{ctx, ctx->tile_override};
+    HIP_TRY(hipEventCreate(&g.e0));
+    HIP_TRY(hipEventCreate(&g.e1));
     double best = 1e30;
     ScoreTile bt;
     bool found = false;
     for (int kmul = 2; kmul <= 8; ++kmul) {
-        const int Ws = kmul * T - (T - 1);
+        const int Ws = kmul * T;  // a multiple of T (see score_block_ws)
         if (Ws < 8 || Ws > 256) continue;
         for (int Hb : {64, 128, 256}) {
             ScoreTile t;
@@ -1141,13 +1188,13 @@ qfca_status qfca_autotune(qfca_ctx ctx, const qfca_job* jobs, int32_t n, int32_t
             ctx->tile_override = t;
             qfca_status st = qfca_score_batch(ctx, jobs, n);  // warm-up (and graph capture)
             if (st != QFCA_OK) continue;
-            HIP_TRY(hipEventRecord(e0, ctx->stream));
+            HIP_TRY(hipEventRecord(g.e0, ctx->stream));
             for (int rep = 0; rep < 2; ++rep)
                 if ((st = qfca_score_batch(ctx, jobs, n)) != QFCA_OK) break;
-            HIP_TRY(hipEventRecord(e1, ctx->stream));
-            HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipEventRecord(g.e1, ctx->stream));
+            HIP_TRY(hipEventSynchronize(g.e1));
             float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            HIP_TRY(hipEventElapsedTime(&ms, g.e0, g.e1));
             if (st == QFCA_OK && ms / 2 < best) {
                 best = ms / 2;
                 bt = t;
@@ -1155,9 +1202,6 @@ qfca_status qfca_autotune(qfca_ctx ctx, const qfca_job* jobs, int32_t n, int32_t
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    ctx->tile_override = saved;
     if (!found) return fail(QFCA_E_UNSUPPORTED, "no candidate tile ran");
     ctx->tuned[(long long)T * 128 + p.B] = bt;
     ctx->tiles.clear();

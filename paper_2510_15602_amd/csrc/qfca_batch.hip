@@ -1,8 +1,8 @@
 // Batched QFCA for images of different sizes (gfx950): one persistent kernel
 // drains a device work queue of projection tiles (16 pixels of one image:
 // residual + bins) and score tiles (a strip x band of one image for 4 channel
-// groups: window histograms, Alg. 1, association), followed by batched
-// channel-mean and blur kernels.  The launch sequence is captured once in a
+// groups: window histograms, Alg. 1, association, fixed-point channel sum),
+// followed by a batched kernel for the channel mean and the blur.  The launch sequence is captured once in a
 // hipGraph whose kernels read every per-batch quantity from device-resident
 // descriptors, so one graph replays any batch within its capacity.
 //
@@ -110,6 +110,12 @@ __device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* job
                 proj_tile_f32<CMAX, KT>(J.pa, tile, w, lane, (const float*)J.pa.V1, (const float*)J.pa.V2,
                                         smu, slo, sid, sfd, zp, x, J.pa.edges, nullptr);
             }
+            // the tile's pixels start the image's fixed-point channel sum at 0
+            // (published with the bins by the release below)
+            if (threadIdx.x < 16) {
+                const int px = tile * 16 + threadIdx.x;
+                if (px < J.pa.N) J.asum[px] = 0;
+            }
             __syncthreads();
             if (threadIdx.x == 0) {
                 __threadfence();
@@ -167,18 +173,9 @@ const void* batch_kernel() {
     else return (const void*)k_batch1<T, CMAX, KT, BF>;
 }
 
-// A(x) = (1/C) sum_c achan[c][x] for every image (grid: pixel chunks of 128, images).
-__global__ __launch_bounds__(256) void k_batch_chanmean(const BatchHeader* hdr, const BatchJob* jobs) {
-    __shared__ double red[2][8][32][4];
-    const int jb = blockIdx.y;
-    if (jb >= hdr->n) return;
-    const BatchJob& J = jobs[jb];
-    const int N = J.sa.H * J.sa.W;
-    for (int q = blockIdx.x; q * 128 < N; q += gridDim.x)
-        chanmean_chunk(J.sa.achan, nullptr, J.sa.C, N, q, J.amap, nullptr, red);
-}
-
-// Separable Gaussian (radius R <= 16) for every image (grid: tiles, images).
+// Channel mean A = (float)(asum * inv_scale) of every image (written to its
+// amap when given) and its separable Gaussian blur, radius R <= 16 (grid:
+// tiles, images).
 __global__ __launch_bounds__(256) void k_batch_blur(const BatchHeader* hdr, const BatchJob* jobs) {
     constexpr int BT = 16, RM = 16;
     __shared__ double tile[BT + 2 * RM][BT + 2 * RM];
@@ -195,7 +192,8 @@ __global__ __launch_bounds__(256) void k_batch_blur(const BatchHeader* hdr, cons
         for (int t = threadIdx.x; t < TS * TS; t += 256) {
             const int ly = t / TS, lx = t - ly * TS;
             const int gy = by + ly - R, gx = bx + lx - R;
-            tile[ly][lx] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? (double)J.amap[(size_t)gy * W + gx] : 0.0;
+            tile[ly][lx] = (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                               ? (double)(float)((double)J.asum[(size_t)gy * W + gx] * J.inv_scale) : 0.0;
         }
         __syncthreads();
         for (int t = threadIdx.x; t < TS * BT; t += 256) {
@@ -214,6 +212,7 @@ __global__ __launch_bounds__(256) void k_batch_blur(const BatchHeader* hdr, cons
         __syncthreads();
         const int gy = by + ty, gx = bx + tx;
         if (gy < H && gx < W) {
+            if (J.amap) J.amap[(size_t)gy * W + gx] = (float)tile[ty + R][tx + R];
             double s = 0.0, ws = 0.0;
             for (int d = -R; d <= R; ++d) {
                 const int yy = gy + d;
@@ -235,7 +234,6 @@ hipError_t run_batch(BatchHeader* hdr, const BatchJob* jobs, int wave_lds, size_
         hipLaunchKernelGGL((k_batch2<T, CMAX, KT, BF>), dim3(grid), dim3(256), lds, st, hdr, jobs, wave_lds);
     else
         hipLaunchKernelGGL((k_batch1<T, CMAX, KT, BF>), dim3(grid), dim3(256), lds, st, hdr, jobs, wave_lds);
-    hipLaunchKernelGGL(k_batch_chanmean, dim3(512, maxn), dim3(256), 0, st, (const BatchHeader*)hdr, jobs);
     hipLaunchKernelGGL(k_batch_blur, dim3(256, 1, maxn), dim3(256), 0, st, (const BatchHeader*)hdr, jobs);
     return hipGetLastError();
 }

@@ -12,6 +12,12 @@
 namespace qfca {
 
 // Arguments of one score tile (see qfca_tiles.h).
+// The channel sum of the per-channel maps is accumulated in 64-bit fixed
+// point: every (channel, pixel) value v is rounded once to llrint(v * fxs)
+// and added with an integer atomic, so the sum does not depend on the order
+// in which tiles, channel groups or batch items finish.  fxs is a power of
+// two chosen per model so that the sum over all channels stays below 2^62
+// (every per-channel value is at most (B - 1) delta_c).
 struct KArgs {
     const uint8_t* bins;
     int C, H, W, T, B, Bp, S, r, m, Ws, Hb, WbA;
@@ -21,8 +27,12 @@ struct KArgs {
     const int32_t* cRl;
     const float* rcp;
     const double* delta;
-    float* achan;
-    float* w1chan;
+    double fxs;        // fixed-point scale of asum and w1sum
+    long long* asum;   // [H][W] sum over channels of A_c, fixed point (atomic adds)
+    long long* w1sum;  // [H][W] sum over channels of W1_c, fixed point, or nullptr
+    float* achan;      // [C][H][W] per-channel maps A_c (inspection output), or nullptr
+    int* dbg_cp;       // inspection kernel only: [C][H][W][B] window cumulative counts cP_j
+    int* dbg_I;        // inspection kernel only: [C][H][W][B] transport numerators I_j
 };
 
 // Arguments of the MFMA projection (see qfca_tiles.h).
@@ -49,7 +59,9 @@ struct BatchJob {
     KArgs sa;             // score tiles of this image
     int ntiles_proj;      // projection items of this image
     int nstrips, nbands;  // score item grid (x strips, y bands; z = channel groups / 4)
-    float* amap;          // [H][W] channel mean
+    long long* asum;      // [H][W] fixed-point channel sum (zeroed by the projection items)
+    double inv_scale;     // 1 / (fxs * C): asum to the channel mean
+    float* amap;          // [H][W] channel mean, or nullptr
     float* score;         // [H][W] blurred score
 };
 struct BatchHeader {
@@ -71,11 +83,11 @@ hipError_t prepare_batch(int T, int CMAX, int KT, int prec, size_t lds);
 hipError_t launch_batch(int T, int CMAX, int KT, int prec, BatchHeader* hdr, const BatchJob* jobs,
                         int wave_lds, size_t lds, int grid, int maxn, hipStream_t st);
 
-// Batched launch (the body of qfca_score_batch).  achan: per-job channel-map
-// buffers of C*H*W floats, or nullptr for context scratch.  err_host: pinned
-// host word that receives the batch's wait-failure flag (stream-ordered after
-// the batch), or nullptr.
-qfca_status score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n, float* const* achan,
+// Batched launch (the body of qfca_score_batch).  asum: per-job fixed-point
+// channel-sum buffers of H*W int64, or nullptr for context scratch.
+// err_host: pinned host word that receives the batch's wait-failure flag
+// (stream-ordered after the batch), or nullptr.
+qfca_status score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n, long long* const* asum,
                             int32_t* err_host);
 // Validation of one job against the parameters p of its batch.
 qfca_status batch_job_check(qfca_ctx ctx, const qfca_job& job, const qfca_params& p);
@@ -114,24 +126,36 @@ struct ScoreTables {
     float* rcp = nullptr;
     double* delta = nullptr;  // [C]
     int Bp = 0;               // lanes per channel (power of two, >= 8)
+    double fxs = 1.0;         // fixed-point scale of the channel sums (see KArgs)
 };
 
 struct ScoreLaunch {
     const uint8_t* bins;  // [C][H][W]
     int C, H, W, T, B;
     ScoreTables tab;
-    float* achan;   // [C][H][W] out
-    float* w1chan;  // [C][H][W] out or nullptr
+    double fxs;           // fixed-point scale (ScoreTables::fxs of the model)
+    long long* asum;      // [H][W] fixed-point channel sum (zeroed by the launcher)
+    long long* w1sum;     // [H][W] or nullptr
+    float* achan;         // [C][H][W] out or nullptr
+    int* dbg_cp = nullptr;  // inspection kernel: [C][H][W][B] out (with dbg_I), or nullptr
+    int* dbg_I = nullptr;
     ScoreTile tile;
 };
 
 size_t score_lds_bytes(int T, int Bp, int S, int Ws, int variant);
 bool score_has_block_kernel(int T);
 int score_block_max_S(int T);  // channels per wavefront the block walk supports
+// Strip width the block walk runs for a requested Ws: a multiple of T (at
+// least T), so that its blocks of T patch columns sit at the same image
+// columns whatever the tiling.
+int score_block_ws(int T, int Ws);
+// Zeroes asum (and w1sum when given), then launches the score tiles.
 hipError_t launch_score(const ScoreLaunch& L, hipStream_t st);
-hipError_t launch_chanmean(const float* achan, const float* w1chan, int C, int N, float* amap,
-                           float* w1, hipStream_t st);
-hipError_t launch_blur(const float* in, int H, int W, float sigma, float* out, hipStream_t st);
+// Channel mean A = asum * inv_scale (written to amap when given), its
+// sigma-blurred score, and the W1 channel mean w1 = w1sum * inv_scale when
+// both are given.
+hipError_t launch_finish(const long long* asum, const long long* w1sum, double inv_scale, int H, int W,
+                         float sigma, float* amap, float* w1, float* score, hipStream_t st);
 
 // Reference fit: count table [C][B][m+1] (uint32, zeroed by the launcher) of
 // full-window cumulative counts, then the selection of cR.

@@ -20,12 +20,16 @@
 //           = Phi(a_{j-1}) + Phi(a_j) - 2 Phi(s) + j (2 s - a_{j-1} - a_j),
 //     s = clamp(c_{j-1}, a_{j-1}, a_j).  This is exactly what the two-pointer
 //     loop of Alg. 1 accumulates; e_j = I_j / (P_j m) in bin units.
-//   * e is summed over the T patch columns around each output column in
-//     double precision (running sum), and the result for the pixel's own bin
-//     is gathered across lanes and added to the pixel's accumulator for each
-//     of the T patch rows that cover it.
-// All counts are exact integers; per-channel results are written to a
-// [C][H][W] buffer and reduced over channels in a fixed order.
+//   * e is summed over the T patch columns around each output column (a
+//     double-precision running sum in this generic kernel, whose bits
+//     therefore follow the strip's start; the block-walk kernel k_score_t
+//     sums in an order fixed by the image columns), and the result for the
+//     pixel's own bin is gathered across lanes and added to the pixel's
+//     accumulator for each of the T patch rows that cover it.
+// All counts are exact integers; each per-channel value is rounded once to
+// 64-bit fixed point and added to the channel sum with an integer atomic
+// (order-free); k_finish turns the sum into the channel mean and blurs it.
+#include <algorithm>
 #include <atomic>
 
 #include "qfca_internal.h"
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
     const int crl = a.cRl[ci * Bp + j];
     const bool binok = cval && (j < a.B);
     const bool w1ok = cval && (j < a.B - 1);
-    const bool want_w1 = a.w1chan != nullptr;
+    const bool want_w1 = a.w1sum != nullptr;
     const float inv_m = 1.0f / (float)m;
     __syncthreads();
 
@@ -192,9 +196,11 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
                 if (want_w1 && own_row && p >= x0 && p < xe) {
                     int d = w1ok ? abs(cP * m - crl * n) : 0;
                     for (int o = Bp >> 1; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
-                    if (cval && j == 0)
-                        a.w1chan[((size_t)c * H + y) * W + p] =
-                            (float)(a.delta[c] * (double)d / ((double)n * (double)m));
+                    if (cval && j == 0) {
+                        const double v = ((double)d * (a.delta[c] * a.fxs)) / ((double)n * (double)m);
+                        __hip_atomic_fetch_add(&a.w1sum[(size_t)y * W + p], __double2ll_rn(v), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
             }
             // Horizontal window sum of e over the T patch columns around
@@ -224,17 +230,21 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
         __syncthreads();
         for (int yo = yo_lo; yo <= yo_hi; ++yo) {
             const int nyo = min(H - 1, yo + r) - max(0, yo - r) + 1;
+            const double rny = 1.0 / (double)nyo;
             for (int t = lane; t < S * ws; t += 64) {
                 const int ss = t / ws, xo = t - ss * ws;
                 const int cc = cbase + ss;
                 float* ap = acc + ((yo % T) * S + ss) * a.Ws + xo;
+                const float av = *ap;
+                *ap = 0.f;
                 if (cc < a.C) {
                     const int xg = x0 + xo;
                     const int nxo = min(W - 1, xg + r) - max(0, xg - r) + 1;
-                    a.achan[((size_t)cc * H + yo) * W + xg] =
-                        (float)((double)(*ap) * a.delta[cc] / (double)(nyo * nxo));
+                    const double v = (((double)av * (a.delta[cc] * a.fxs)) * (1.0 / (double)nxo)) * rny;
+                    if (a.achan) a.achan[((size_t)cc * H + yo) * W + xg] = (float)(v * (1.0 / a.fxs));
+                    __hip_atomic_fetch_add(&a.asum[(size_t)yo * W + xg], __double2ll_rn(v), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
-                *ap = 0.f;
             }
         }
         __syncthreads();
@@ -252,15 +262,6 @@ __global__ __launch_bounds__(64) void k_score_t(KArgs a) {
                                rcp4);
 }
 
-// A(x) = (1/C) sum_c achan[c][x] in double precision, in a fixed order
-// (eight strided channel slices, then the slices).
-__global__ __launch_bounds__(256) void k_chanmean(const float* __restrict__ achan,
-                                                  const float* __restrict__ w1chan, int C, int N,
-                                                  float* __restrict__ amap, float* __restrict__ w1) {
-    __shared__ double red[2][8][32][4];
-    tiles::chanmean_chunk(achan, w1chan, C, N, blockIdx.x, amap, w1, red);
-}
-
 // Separable Gaussian, radius R, renormalised over in-image taps (the 2-D
 // renormalisation factorises because the in-image tap set is a rectangle).
 constexpr int BT = 16;
@@ -270,8 +271,31 @@ struct BlurW {
     double w[RMAX + 1];
 };
 
-__global__ __launch_bounds__(256) void k_blur(const float* __restrict__ in, int H, int W, int R,
-                                              BlurW wts, float* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_zero64(long long* __restrict__ a, long long* __restrict__ b, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        a[i] = 0;
+        if (b) b[i] = 0;
+    }
+}
+
+// Inspection build of k_score_t: the same tile code, also storing every
+// window's cumulative counts and transport numerators.
+template <int T>
+__global__ __launch_bounds__(64) void k_score_dbg(KArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* rcp4 = (float*)smem;
+    fill_rcp4<T>(rcp4, a.rcp, threadIdx.x, 64);
+    score_tile<T, false, true, true>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x,
+                                     smem + BLayout<T>::RCP_BYTES, rcp4);
+}
+
+// The channel mean A = (float)(asum * inv) of the fixed-point channel sum
+// (written to amap when given) and its separable Gaussian blur; with w1 and
+// w1sum given, also w1 = (float)(w1sum * inv).  R = 0 copies A.
+__global__ __launch_bounds__(256) void k_finish(const long long* __restrict__ asum,
+                                                const long long* __restrict__ w1sum, double inv, int H,
+                                                int W, int R, BlurW wts, float* __restrict__ amap,
+                                                float* __restrict__ w1, float* __restrict__ out) {
     __shared__ double tile[BT + 2 * RMAX][BT + 2 * RMAX];
     __shared__ double hpass[BT + 2 * RMAX][BT];
     __shared__ double w[RMAX + 1];
@@ -282,7 +306,8 @@ __global__ __launch_bounds__(256) void k_blur(const float* __restrict__ in, int 
     for (int t = threadIdx.x; t < TS * TS; t += 256) {
         const int ly = t / TS, lx = t - ly * TS;
         const int gy = by + ly - R, gx = bx + lx - R;
-        tile[ly][lx] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? (double)in[(size_t)gy * W + gx] : 0.0;
+        tile[ly][lx] = (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                           ? (double)(float)((double)asum[(size_t)gy * W + gx] * inv) : 0.0;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < TS * BT; t += 256) {
@@ -301,6 +326,9 @@ __global__ __launch_bounds__(256) void k_blur(const float* __restrict__ in, int 
     __syncthreads();
     const int gy = by + ty, gx = bx + tx;
     if (gy >= H || gx >= W) return;
+    const size_t g = (size_t)gy * W + gx;
+    if (amap) amap[g] = (float)tile[ty + R][tx + R];
+    if (w1 && w1sum) w1[g] = (float)((double)w1sum[g] * inv);
     double s = 0.0, ws = 0.0;
     for (int d = -R; d <= R; ++d) {
         const int yy = gy + d;
@@ -309,13 +337,14 @@ __global__ __launch_bounds__(256) void k_blur(const float* __restrict__ in, int 
         s += wd * hpass[ty + R + d][tx];
         ws += wd;
     }
-    out[(size_t)gy * W + gx] = (float)(s / ws);
+    out[g] = (float)(s / ws);
 }
 
 }  // namespace
 
 bool score_has_block_kernel(int T) { return T >= 3 && T <= 31 && (T & 1); }
 int score_block_max_S(int T) { return T <= 9 ? 4 : 2; }
+int score_block_ws(int T, int Ws) { return T < 1 ? Ws : std::max(T, Ws / T * T); }
 
 static int alloc_cols(int T, int Ws, int variant) {
     (void)variant;
@@ -329,6 +358,7 @@ size_t score_rcp_bytes(int T) { return align16((size_t)(T * T + 1) * 4); }
 
 size_t score_lds_bytes(int T, int Bp, int S, int Ws, int variant) {
     if (variant == 1 && score_has_block_kernel(T)) {
+        Ws = score_block_ws(T, Ws);
         switch (T) {
 #define QFCA_T_LDS(TT) case TT: return blayout_bytes<TT>(S, Ws);
             QFCA_T_LDS(3) QFCA_T_LDS(5) QFCA_T_LDS(7) QFCA_T_LDS(9) QFCA_T_LDS(11) QFCA_T_LDS(13)
@@ -358,6 +388,13 @@ static hipError_t no_static_lds(const void* k, int T) {
     return v == 1 ? hipSuccess : hipErrorInvalidDeviceFunction;
 }
 
+static hipError_t no_static_lds_uncached(const void* k) {
+    hipFuncAttributes fa;
+    const hipError_t e = hipFuncGetAttributes(&fa, k);
+    if (e != hipSuccess) return e;
+    return fa.sharedSizeBytes == 0 ? hipSuccess : hipErrorInvalidDeviceFunction;
+}
+
 hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     KArgs a;
     a.bins = L.bins;
@@ -366,19 +403,27 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     a.S = L.tile.S;
     a.r = L.T / 2;
     a.m = L.T * L.T;
-    a.Ws = L.tile.Ws;
     a.Hb = L.tile.Hb;
     const int variant =
         (L.tile.variant == 1 && score_has_block_kernel(L.T) && L.tile.S <= score_block_max_S(L.T) &&
          L.tile.Ws >= L.T) ? 1 : 0;
+    a.Ws = variant ? score_block_ws(L.T, L.tile.Ws) : L.tile.Ws;
     a.WbA = alloc_cols(L.T, a.Ws, variant);
     a.psig = L.tab.psig; a.cRm1 = L.tab.cRm1; a.Dm1 = L.tab.Dm1; a.cRl = L.tab.cRl;
     a.rcp = L.tab.rcp; a.delta = L.tab.delta;
-    a.achan = L.achan; a.w1chan = L.w1chan;
-    if (a.S < 1 || a.S * a.Bp > 64) return hipErrorInvalidValue;
+    a.fxs = L.fxs; a.asum = L.asum; a.w1sum = L.w1sum; a.achan = L.achan;
+    a.dbg_cp = L.dbg_cp; a.dbg_I = L.dbg_I;
+    const bool dbg = L.dbg_cp != nullptr;
+    if (dbg && (!L.dbg_I || variant != 1)) return hipErrorInvalidValue;
+    if (a.S < 1 || a.S * a.Bp > 64 || !a.asum) return hipErrorInvalidValue;
     const size_t lds = score_lds_bytes(a.T, a.Bp, a.S, a.Ws, variant);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     dim3 grid((L.W + a.Ws - 1) / a.Ws, (L.H + a.Hb - 1) / a.Hb, (L.C + a.S - 1) / a.S);
+    {
+        const size_t n = (size_t)L.H * L.W;
+        const int zb = (int)std::min<size_t>((n + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_zero64, dim3(zb), dim3(256), 0, st, a.asum, a.w1sum, n);
+    }
     // more than 64 KiB of dynamic LDS has to be allowed per kernel
     auto allow = [&](const void* k) -> hipError_t {
         return lds > 65536 ? hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
@@ -393,10 +438,14 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     switch (a.T) {
 #define QFCA_T_CASE(TT)                                                          \
         case TT: {                                                               \
-            hipError_t e = no_static_lds((const void*)k_score_t<TT>, TT);        \
-            if (e == hipSuccess) e = allow((const void*)k_score_t<TT>);          \
+            const void* kf = dbg ? (const void*)k_score_dbg<TT> : (const void*)k_score_t<TT>; \
+            hipError_t e = dbg ? no_static_lds_uncached(kf) : no_static_lds(kf, TT); \
+            if (e == hipSuccess) e = allow(kf);                                  \
             if (e != hipSuccess) return e;                                       \
-            hipLaunchKernelGGL(k_score_t<TT>, grid, dim3(64), lds, st, a);       \
+            if (dbg)                                                             \
+                hipLaunchKernelGGL(k_score_dbg<TT>, grid, dim3(64), lds, st, a); \
+            else                                                                 \
+                hipLaunchKernelGGL(k_score_t<TT>, grid, dim3(64), lds, st, a);   \
         } break;
         QFCA_T_CASE(3) QFCA_T_CASE(5) QFCA_T_CASE(7) QFCA_T_CASE(9) QFCA_T_CASE(11)
         QFCA_T_CASE(13) QFCA_T_CASE(15) QFCA_T_CASE(17) QFCA_T_CASE(19) QFCA_T_CASE(21)
@@ -407,22 +456,15 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_chanmean(const float* achan, const float* w1chan, int C, int N, float* amap,
-                           float* w1, hipStream_t st) {
-    hipLaunchKernelGGL(k_chanmean, dim3((N + 127) / 128), dim3(256), 0, st, achan, w1chan, C, N,
-                       amap, w1);
-    return hipGetLastError();
-}
-
-hipError_t launch_blur(const float* in, int H, int W, float sigma, float* out, hipStream_t st) {
-    if (!(sigma > 0.f)) return hipMemcpyAsync(out, in, (size_t)H * W * 4, hipMemcpyDeviceToDevice, st);
-    const int R = (int)ceil(3.0 * (double)sigma);
+hipError_t launch_finish(const long long* asum, const long long* w1sum, double inv_scale, int H, int W,
+                         float sigma, float* amap, float* w1, float* score, hipStream_t st) {
+    const int R = sigma > 0.f ? (int)ceil(3.0 * (double)sigma) : 0;
     if (R > RMAX) return hipErrorInvalidValue;
     BlurW wts;
     for (int d = 0; d <= RMAX; ++d)
-        wts.w[d] = d <= R ? exp(-(double)(d * d) / (2.0 * (double)sigma * (double)sigma)) : 0.0;
+        wts.w[d] = d <= R ? (R > 0 ? exp(-(double)(d * d) / (2.0 * (double)sigma * (double)sigma)) : 1.0) : 0.0;
     dim3 grid((W + BT - 1) / BT, (H + BT - 1) / BT);
-    hipLaunchKernelGGL(k_blur, grid, dim3(256), 0, st, in, H, W, R, wts, out);
+    hipLaunchKernelGGL(k_finish, grid, dim3(256), 0, st, asum, w1sum, inv_scale, H, W, R, wts, amap, w1, score);
     return hipGetLastError();
 }
 

@@ -111,25 +111,24 @@ void retire(qfca_server s, LaunchSlot& L, int32_t status) {
 qfca_status issue(qfca_server s, LaunchSlot& L, std::vector<Request>& reqs) {
     const size_t n = reqs.size();
     std::vector<qfca_job> jobs(n);
-    std::vector<float*> achan(n);
+    std::vector<long long*> asum(n);
     for (size_t i = 0; i < n; ++i) {
         const Request& r = reqs[i];
         const size_t N = (size_t)r.H * r.W;
         char* p = s->base + r.off;
         const size_t ob = serve::align_up((size_t)r.C * N);
-        const size_t oa = ob + serve::align_up((size_t)4 * r.C * N);
+        jobs[i] = qfca_job{};
         jobs[i].model = r.model;
         jobs[i].X = r.X;
         jobs[i].H = r.H;
         jobs[i].W = r.W;
         jobs[i].score = r.score;
         jobs[i].bins = (uint8_t*)p;
-        jobs[i].amap = (float*)(p + oa);
-        achan[i] = (float*)(p + ob);
+        asum[i] = (long long*)(p + ob);
     }
     if (hipEventRecord(L.ev0, L.stream) != hipSuccess) return QFCA_E_DEVICE;
     *L.h_err = 0;
-    qfca_status st = score_batch_ext(L.ctx, jobs.data(), (int32_t)n, achan.data(), L.h_err);
+    qfca_status st = score_batch_ext(L.ctx, jobs.data(), (int32_t)n, asum.data(), L.h_err);
     if (st != QFCA_OK) return st;
     if (hipEventRecord(L.ev1, L.stream) != hipSuccess) return QFCA_E_DEVICE;
     return QFCA_OK;

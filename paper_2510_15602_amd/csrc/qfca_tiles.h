@@ -148,7 +148,10 @@ __device__ __forceinline__ void fill_rcp4(float* rcp4, const float* rcp, int tid
 //   RCP0: the caller guarantees that rcp4 sits at LDS address 0 (a kernel
 //   with no static LDS whose dynamic LDS starts with it), so the byte offset
 //   4P of rcp4[P] is its address and costs no add.
-template <int T, bool FASTG, bool RCP0>
+//   DBG: inspection build of the same code that also stores, for every
+//   window of the tile's own outputs, the cumulative count cP_j and the
+//   transport numerator I_j of every bin (a.dbg_cp, a.dbg_I, [C][H][W][B]).
+template <int T, bool FASTG, bool RCP0, bool DBG = false>
 __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int bz, int lane,
                                            unsigned char* smem, const float* rcp4) {
     using BL = BLayout<T>;
@@ -219,7 +222,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     const int dm1_4 = 4 * dm1;
     const int negj = -j;
     const bool w1ok = cval && (j < a.B - 1);
-    const bool want_w1 = a.w1chan != nullptr;
+    const bool want_w1 = a.w1sum != nullptr;
     constexpr float inv_m = 1.0f / (float)m;
     wave_sync();
 
@@ -362,27 +365,23 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     const uint32_t gstep0 = (uint32_t)nlb << 16, gwrap0 = (uint32_t)(T1 * nlb) << 16;
     const uint32_t gstep1 = (uint32_t)(S * Ws) << 16, gwrap1 = (uint32_t)(T * S * Ws) << 16;
 
-    // Output slots of a row, t = lane + 64 i over the S x ws outputs, fixed for
-    // the tile: accumulator offset in a row (bit 31: the channel exists),
-    // offset from the group's first channel at the row in achan, and
-    // delta_c / n_x for the slot's column (a row adds 1 / n_y).
+    // Output columns of a row: column t = lane + 64 i of the strip (t < ws),
+    // with 1 / n_x of its global column; fixed for the tile.  An output of
+    // channel c at (yo, xg) is v = ((acc * delta_c fxs) * (1 / n_x)) * (1 / n_y),
+    // rounded once to an integer and added to the channel sum: the S channel
+    // values of a column are summed in the lane first (integer adds), so one
+    // atomic add per column carries the wavefront's channels.
     constexpr int OSL = 4;
-    const int nout = S * ws;
-    const bool ofast = (nout <= 64 * OSL) && ((long long)S * H * W < 0x7FFFFFFFLL);
-    uint32_t oacc[OSL];
-    int oglb[OSL];
-    double osc[OSL];
+    constexpr int OSM = (T <= 9) ? 4 : 2;  // channels per wavefront (score_block_max_S)
+    const bool ofast = (ws <= 64 * OSL) && (S <= OSM);
+    double orx[OSL];
 #pragma unroll
     for (int i = 0; i < OSL; ++i) {
-        const int t = lane + 64 * i;
-        const int ss = ofast ? t / ws : 0, xo = t - ss * ws;
-        const int cc = cbase + ss, xg = x0 + xo;
-        const bool ok = ofast && t < nout && cc < a.C;
+        const int xg = x0 + lane + 64 * i;
         const int nxo = min(W - 1, xg + r) - max(0, xg - r) + 1;
-        oacc[i] = (uint32_t)(ss * Ws + xo) | (ok ? 0x80000000u : 0u);
-        oglb[i] = ss * H * W + xg;
-        osc[i] = ok ? a.delta[cc] / (double)nxo : 0.0;
+        orx[i] = 1.0 / (double)max(nxo, 1);
     }
+    const double inv_fxs = 1.0 / a.fxs;
 
     for (int yy = lo_add; yy < hi_add; ++yy) {
         load_row(yy);
@@ -414,6 +413,19 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
         const int ny = min(H - 1, y + r) - max(0, y - r) + 1;
         const bool row_full = (ny == T);
         const bool own_row = (y >= y0) && (y < ye);
+        // inspection stores (DBG only): step i is patch column x0 - r + i;
+        // cpv carries 4 cP + bias and I4 = 4 I
+        // (full windows compute I with unscaled masses: the stored value is
+        // brought to the scaled masses P T^2, R n of the clipped windows)
+        auto dbg_store = [&](int i, int cpb_k, int I4, bool full_w) {
+            const int p = x0 - r + i;
+            if (own_row && cval && j < a.B && p >= x0 && p < xe) {
+                const size_t o = (((size_t)c * H + y) * W + p) * a.B + j;
+                a.dbg_cp[o] = (cpb_k - bias) >> 2;
+                a.dbg_I[o] = full_w ? (I4 >> 2) * m : (I4 >> 2);
+            }
+        };
+        (void)dbg_store;
         // Step i walks patch column p = x0 - r + i; its window covers bin
         // columns q in [i, i + 2r].  The count entering at step i is vc[i + 2r]
         // and the one leaving is vc[i - 1].
@@ -448,7 +460,10 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
         for (int blk = 0; blk < nblk; ++blk) {
             const int i0 = blk * T;
             const int p0 = x0 - r + i0;  // patch column of the block's first step
-            const bool full = row_full && (i0 + T <= np) && (p0 >= r) && (p0 + T - 1 <= W - 1 - r);
+            // (decided by the block's image columns only, so that a block of
+            // patch columns takes the same path in every tiling; steps past
+            // the strip's last patch column feed no output)
+            const bool full = row_full && (p0 >= r) && (p0 + T - 1 <= W - 1 - r);
             // 0. the gather's bin bytes and accumulators, read ahead: neither
             //    is written during the block (the ring rows are fixed within a
             //    row, and the accumulator columns of different blocks are
@@ -525,6 +540,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                     const int mn = (crmb <= cmv[k]) ? gu : ((crmb >= cpv[k]) ? gv[k] : gcb);
                     const int I4 = (gu + gv[k]) - (mn << 1);
                     ev[k] = (float)I4 * rc[k];
+                    if constexpr (DBG) dbg_store(i0 + k, cpv[k], I4, true);
                 }
             } else {
                 // Windows clipped at the image border (or rows with fewer than
@@ -583,6 +599,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                             const int phis = (cm <= au) ? phiu : ((cm >= av) ? phia : __mul24(n, dm1_4));
                             const int I4 = (phia - phis) + (phiu - phis) + __mul24(4 * j, 2 * sc - au - av);
                             ev[k] = pval ? (float)I4 * grc[kk] * inv_m : 0.f;
+                            if constexpr (DBG) dbg_store(i, cpv[k], I4, false);
                         }
                     }
                 }
@@ -596,9 +613,11 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                         const int n = ny * nx;
                         int d = w1ok ? abs((cpv[k] - bias) * m - crl4 * n) : 0;
                         for (int o = Bp >> 1; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
-                        if (cval && j == 0)
-                            a.w1chan[((size_t)c * H + y) * W + p] =
-                                (float)(a.delta[c] * (double)d / (4.0 * (double)n * (double)m));
+                        if (cval && j == 0) {
+                            const double v = ((double)d * (a.delta[c] * a.fxs * 0.25)) / ((double)n * (double)m);
+                            __hip_atomic_fetch_add(&a.w1sum[(size_t)y * W + p], __double2ll_rn(v), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        }
                     }
                 }
             }
@@ -693,19 +712,37 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
         yo_hi = min(yo_hi, ye - 1);
         for (int yo = yo_lo; yo <= yo_hi; ++yo) {
             const int nyo = min(H - 1, yo + r) - max(0, yo - r) + 1;
+            const double rny = 1.0 / (double)nyo;
+            float* ar = acc + (yo % T) * S * Ws;
             if (ofast) {
-                float* ar = acc + (yo % T) * S * Ws;
-                float* gr = a.achan + ((size_t)cbase * H + yo) * W;
-                const double rny = 1.0 / (double)nyo;
-                float ov[OSL];
+                // every read of the row before the stores that clear it
+                float ov[OSL][OSM];
 #pragma unroll
                 for (int i = 0; i < OSL; ++i)
-                    ov[i] = (lane + 64 * i < nout) ? ar[oacc[i] & 0x7FFFFFFFu] : 0.f;
+#pragma unroll
+                    for (int ss = 0; ss < OSM; ++ss)
+                        ov[i][ss] = (lane + 64 * i < ws && ss < S) ? ar[ss * Ws + lane + 64 * i] : 0.f;
+#pragma unroll
+                for (int i = 0; i < OSL; ++i)
+#pragma unroll
+                    for (int ss = 0; ss < OSM; ++ss)
+                        if (lane + 64 * i < ws && ss < S) ar[ss * Ws + lane + 64 * i] = 0.f;
 #pragma unroll
                 for (int i = 0; i < OSL; ++i) {
-                    if (lane + 64 * i < nout) {
-                        if (oacc[i] >> 31) gr[oglb[i]] = (float)((double)ov[i] * osc[i] * rny);
-                        ar[oacc[i] & 0x7FFFFFFFu] = 0.f;
+                    if (lane + 64 * i < ws) {
+                        const int xg = x0 + lane + 64 * i;
+                        long long qs = 0;
+#pragma unroll
+                        for (int ss = 0; ss < OSM; ++ss) {
+                            const int cc = cbase + ss;
+                            if (ss < S && cc < a.C) {
+                                const double v = (((double)ov[i][ss] * (a.delta[cc] * a.fxs)) * orx[i]) * rny;
+                                qs += __double2ll_rn(v);
+                                if (a.achan) a.achan[((size_t)cc * H + yo) * W + xg] = (float)(v * inv_fxs);
+                            }
+                        }
+                        __hip_atomic_fetch_add(&a.asum[(size_t)yo * W + xg], qs, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
                 continue;
@@ -713,14 +750,17 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
             for (int t = lane; t < S * ws; t += 64) {
                 const int ss = t / ws, xo = t - ss * ws;
                 const int cc = cbase + ss;
-                float* ap = acc + ((yo % T) * S + ss) * Ws + xo;
+                float* ap = ar + ss * Ws + xo;
+                const float av = *ap;
+                *ap = 0.f;
                 if (cc < a.C) {
                     const int xg = x0 + xo;
                     const int nxo = min(W - 1, xg + r) - max(0, xg - r) + 1;
-                    a.achan[((size_t)cc * H + yo) * W + xg] =
-                        (float)((double)(*ap) * a.delta[cc] / (double)(nyo * nxo));
+                    const double v = (((double)av * (a.delta[cc] * a.fxs)) * (1.0 / (double)nxo)) * rny;
+                    if (a.achan) a.achan[((size_t)cc * H + yo) * W + xg] = (float)(v * inv_fxs);
+                    __hip_atomic_fetch_add(&a.asum[(size_t)yo * W + xg], __double2ll_rn(v), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
-                *ap = 0.f;
             }
         }
         wave_sync();
@@ -1037,67 +1077,6 @@ __device__ __forceinline__ void proj_tile_bf16(const MArgs& a, int tile, int w, 
     emit_values<NSW * 8>(a, px, cs, rv, valid, slo, sid, sfd, edges, stg);
 }
 
-// Channel mean A(x) = (1/C) sum_c achan[c][x] (and the same for the W1
-// maps when w1chan is given) over the pixel chunk [128 q, 128 q + 128) of a
-// map of N pixels, by a block of 256 threads: thread (g, u) loads pixels
-// 4u .. 4u+3 of the chunk (one 16-byte load when N is a multiple of 4 and
-// the maps are 16-byte aligned) for
-// channels g, g + 8, g + 16, ... and sums them in FP64; the eight slices are
-// then added in the order g = 0 .. 7 through `red`, so the result does not
-// depend on scheduling.
-__device__ __forceinline__ void chanmean_chunk(const float* __restrict__ achan, const float* __restrict__ w1chan,
-                                               int C, int N, int q, float* __restrict__ amap,
-                                               float* __restrict__ w1, double (*red)[8][32][4]) {
-    const int tid = threadIdx.x;
-    const int u = tid & 31, g = tid >> 5;
-    const int i0 = q * 128 + 4 * u;
-    double s[4] = {0.0, 0.0, 0.0, 0.0}, t[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i0 < N) {
-        const bool vec = ((N & 3) == 0) && (((uintptr_t)achan & 15) == 0) && (((uintptr_t)w1chan & 15) == 0);
-        if (vec) {
-#pragma unroll 4
-            for (int c = g; c < C; c += 8) {
-                const float4 v = *(const float4*)(achan + (size_t)c * N + i0);
-                s[0] += (double)v.x; s[1] += (double)v.y; s[2] += (double)v.z; s[3] += (double)v.w;
-                if (w1chan) {
-                    const float4 w = *(const float4*)(w1chan + (size_t)c * N + i0);
-                    t[0] += (double)w.x; t[1] += (double)w.y; t[2] += (double)w.z; t[3] += (double)w.w;
-                }
-            }
-        } else {
-            for (int c = g; c < C; c += 8) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (i0 + e < N) {
-                        s[e] += (double)achan[(size_t)c * N + i0 + e];
-                        if (w1chan) t[e] += (double)w1chan[(size_t)c * N + i0 + e];
-                    }
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        red[0][g][u][e] = s[e];
-        red[1][g][u][e] = t[e];
-    }
-    __syncthreads();
-    if (tid < 128) {
-        const int uu = tid >> 2, e = tid & 3;
-        const int i = q * 128 + tid;
-        double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int gg = 0; gg < 8; ++gg) {
-            a += red[0][gg][uu][e];
-            b += red[1][gg][uu][e];
-        }
-        if (i < N) {
-            amap[i] = (float)(a / (double)C);
-            if (w1chan) w1[i] = (float)(b / (double)C);
-        }
-    }
-    __syncthreads();
-}
 
 }  // namespace tiles
 }  // namespace qfca

@@ -69,11 +69,11 @@ private:
 };
 
 // Device working memory of one request of H*W pixels and C channels: bins
-// (C bytes per pixel), per-channel association maps (4C bytes per pixel) and
-// the channel mean (4 bytes per pixel), each 256-byte aligned.
+// (C bytes per pixel) and the fixed-point channel sum (8 bytes per pixel),
+// each 256-byte aligned.
 inline size_t request_bytes(int C, int H, int W) {
     const size_t N = (size_t)H * W;
-    return align_up((size_t)C * N) + align_up((size_t)4 * C * N) + align_up(4 * N);
+    return align_up((size_t)C * N) + align_up(8 * N);
 }
 
 // Moves requests from the front of `pending` into `out` (one batch):

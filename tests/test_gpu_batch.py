@@ -64,8 +64,9 @@ def test_batch_equals_single_image_path(ctx, cfg):
         o1 = q.qfca_score_map(ctx, m, b1, amap=True)
         torch.cuda.synchronize()
         assert torch.equal(bins, b1), "batch bins differ from qfca_quantize"
-        close(amap.cpu().numpy(), o1.amap.cpu().numpy())
-        close(score.cpu().numpy(), o1.score.cpu().numpy())
+        # same block-walk arithmetic and an order-free channel sum: bitwise
+        assert torch.equal(amap, o1.amap), "batch channel mean differs from qfca_score_map"
+        assert torch.equal(score, o1.score), "batch score differs from qfca_score_map"
 
 
 def test_batch_alone_equals_in_mix(ctx):
@@ -115,12 +116,34 @@ def test_batch_against_oracle(ctx):
 def test_autotune_picks_a_valid_tile(ctx):
     C, k, B, T, prec, shapes = CONFIGS[0]
     jobs = make_jobs(ctx, shapes[:3], C, k, B, T, prec, 900)
-    ws, hb, ms = q.qfca_autotune(ctx, jobs)
-    say(f"[autotune] Ws={ws} Hb={hb} {ms:.3f} ms")
-    assert (ws + T - 1) % T == 0 and hb in (64, 128, 256) and ms > 0
     q.qfca_score_batch(ctx, jobs)
     torch.cuda.synchronize()
-    for (m, X, score, bins, amap) in jobs:
+    before = [j[2].clone() for j in jobs]
+    ws, hb, ms = q.qfca_autotune(ctx, jobs)
+    say(f"[autotune] Ws={ws} Hb={hb} {ms:.3f} ms")
+    assert ws % T == 0 and hb in (64, 128, 256) and ms > 0
+    q.qfca_score_batch(ctx, jobs)
+    torch.cuda.synchronize()
+    for i, (m, X, score, bins, amap) in enumerate(jobs):
         o1 = q.qfca_score_map(ctx, m, bins, amap=True)
         torch.cuda.synchronize()
-        close(score.cpu().numpy(), o1.score.cpu().numpy())
+        # the tuned tile changes no bit, in the batch or the single-image path
+        assert torch.equal(score, o1.score) and torch.equal(score, before[i])
+
+
+@pytest.mark.parametrize("cfg", CONFIGS[:2], ids=lambda c: f"C{c[0]}_k{c[1]}_B{c[2]}_T{c[3]}_p{c[4]}")
+def test_batch_channel_maps_against_oracle(ctx, cfg):
+    """Per-channel maps of every image of a batch, every pixel and channel,
+    against the oracle on the batch's own bins and the model."""
+    C, k, B, T, prec, shapes = cfg
+    say(f"[batch channel maps] C={C} k={k} B={B} T={T} prec={prec} shapes={shapes}")
+    jobs = make_jobs(ctx, shapes, C, k, B, T, prec, 950)
+    items = [j + (torch.empty((C,) + tuple(j[2].shape), device="cuda"),) for j in jobs]
+    q.qfca_score_batch(ctx, items)
+    torch.cuda.synchronize()
+    assert q.qfca_batch_error(ctx) == 0
+    for (m, X, score, bins, amap, achan) in items:
+        ref = oracle.score(bins.cpu().numpy(), T, B, m.read("cR"), m.read("delta"), 1.0, want_chan=True)
+        close(achan.cpu().numpy(), ref.Achan)
+        close(amap.cpu().numpy(), ref.A)
+        close(score.cpu().numpy(), ref.score)

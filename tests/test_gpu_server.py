@@ -10,6 +10,7 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+import oracle  # noqa: E402
 import paper_2510_15602_amd as q  # noqa: E402
 import qfca_synth  # noqa: E402
 
@@ -90,6 +91,17 @@ def test_server_results_equal_alone(ctx, models):
         assert torch.equal(s, ref[i]), f"request {i} differs from its result alone"
     assert st["completed"] == st["submitted"] == 24 and st["failed"] == 0
     srv.close()
+    # served maps against the FP64 oracle on the request's bins (those of
+    # qfca_quantize with the class model, which the batch reproduces bit for bit)
+    for i in range(0, 24, 5):
+        cls, X, s = reqs[i]
+        m = models[cls]
+        bins, _ = q.qfca_quantize(ctx, m, X)
+        torch.cuda.synchronize()
+        ref_o = oracle.score(bins.cpu().numpy(), T, B, m.read("cR"), m.read("delta"), 1.0)
+        g = s.cpu().numpy().astype(np.float64)
+        tol = 1e-5 * np.abs(ref_o.score) + 1e-7 * np.abs(ref_o.score).max()
+        assert (np.abs(g - ref_o.score) <= tol).all(), f"request {i}: served score against the oracle"
 
 
 def test_server_memory_budget_defers_and_completes(ctx, models):
@@ -138,7 +150,7 @@ def test_server_rejects_bad_requests(ctx, models):
     X = torch.zeros((C, 128, 128), device="cuda")
     s = torch.empty((128, 128), device="cuda")
     with pytest.raises(q.QfcaError) as e:
-        srv.submit(models[0], X, s)  # 128x128 needs ~21 MB
+        srv.submit(models[0], X, s)  # 128x128 needs ~4.3 MB
     assert e.value.status == 3
     with pytest.raises(ValueError):
         srv.submit(models[0], X, torch.empty((64, 64), device="cuda"))
@@ -152,4 +164,4 @@ def q_bytes(H, W):
     def a(x):
         return (x + 255) // 256 * 256
     N = H * W
-    return a(C * N) + a(4 * C * N) + a(4 * N)
+    return a(C * N) + a(8 * N)

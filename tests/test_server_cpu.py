@@ -42,9 +42,10 @@ def test_request_bytes(driver):
     out = run(driver, ["bytes 256 512 512", "bytes 3 5 7", "bytes 1 1 1"])
     def a(x):
         return (x + 255) // 256 * 256
-    assert int(out[0]) == a(256 * 512 * 512) + a(4 * 256 * 512 * 512) + a(4 * 512 * 512)
-    assert int(out[1]) == a(105) + a(420) + a(140)
-    assert int(out[2]) == 3 * 256
+    # bins (C bytes per pixel) and the fixed-point channel sum (8 bytes per pixel)
+    assert int(out[0]) == a(256 * 512 * 512) + a(8 * 512 * 512)
+    assert int(out[1]) == a(105) + a(8 * 35)
+    assert int(out[2]) == 2 * 256
 
 
 def test_fifo_and_batch_cap(driver):
