@@ -177,6 +177,19 @@ qfca_status qfca_quantize(qfca_ctx ctx, qfca_model model, const float* X, int32_
 qfca_status qfca_score_map(qfca_ctx ctx, qfca_model model, const uint8_t* bins, int32_t H,
                            int32_t W, float* score, float* amap, float* w1, float* achan);
 
+/* qfca_score_map for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): same arguments, outputs and arithmetic (bit for bit), but the
+ * library's scratch is a fixed device array of 64 MiB that the library
+ * holds on every GPU it runs on until the process ends, so the call makes
+ * no device allocation.  Limit: H * W <= 4194304 pixels (2048 x 2048);
+ * larger maps give QFCA_E_UNSUPPORTED.  The scratch is cleared by the call
+ * itself.  Every call on one GPU uses that GPU's single array: calls that
+ * overlap on one GPU (on different streams, or from different contexts or
+ * threads) race and give wrong maps; order them on one stream. */
+qfca_status qfca_score_map_noalloc(qfca_ctx ctx, qfca_model model, const uint8_t* bins, int32_t H,
+                                   int32_t W, float* score, float* amap, float* w1, float* achan);
+
 /* Inspection of the integer stages of qfca_score_map (Sec. 3.1, Alg. 1):
  * runs the same score kernel code, built to also store, for every pixel p
  * (window centre) and every bin j < B of every channel c,

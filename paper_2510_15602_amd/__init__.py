@@ -34,7 +34,7 @@ EXPORTS = ("qfca_status_str", "qfca_last_error", "qfca_version", "qfca_ctx_creat
            "qfca_ctx_profile_read", "qfca_ctx_set_tile", "qfca_score_batch", "qfca_batch_error",
            "qfca_autotune", "qfca_clock", "qfca_server_create", "qfca_server_submit",
            "qfca_server_poll", "qfca_server_drain", "qfca_server_stats", "qfca_server_destroy",
-           "qfca_inspect_windows")
+           "qfca_inspect_windows", "qfca_score_map_noalloc")
 
 KERNELS = {"score": 0, "proj": 1, "finish": 2}
 
@@ -113,6 +113,7 @@ def lib():
         L.qfca_quantize.argtypes = [P, P, P, i32, i32, P, P]
         L.qfca_score_map.argtypes = [P, P, P, i32, i32, P, P, P, P]
         L.qfca_inspect_windows.argtypes = [P, P, P, i32, i32, P, P]
+        L.qfca_score_map_noalloc.argtypes = [P, P, P, i32, i32, P, P, P, P]
         L.qfca_model_params.argtypes = [P, ctypes.POINTER(Params)]
         L.qfca_model_read.argtypes = [P, i32, P, sz]
         L.qfca_model_destroy.argtypes = [P]
@@ -146,7 +147,8 @@ def lib():
                      "qfca_model_params", "qfca_model_read", "qfca_model_destroy", "qfca_model_export",
                      "qfca_model_import",
                      "qfca_ctx_profile", "qfca_ctx_profile_read", "qfca_ctx_set_tile",
-                     "qfca_score_batch", "qfca_batch_error", "qfca_autotune", "qfca_inspect_windows"):
+                     "qfca_score_batch", "qfca_batch_error", "qfca_autotune", "qfca_inspect_windows",
+                     "qfca_score_map_noalloc"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -390,6 +392,24 @@ def _jobs(items):
                      amap.data_ptr() if amap is not None else None,
                      achan.data_ptr() if achan is not None else None)
     return arr
+
+
+def qfca_score_map_noalloc(ctx: Context, model: Model, bins, out: ScoreMaps):
+    """qfca_score_map without device allocation: out (a ScoreMaps whose
+    score and any of amap, w1, achan are preallocated device tensors)
+    receives the maps."""
+    import torch
+    bins = _dev_tensor(bins, torch.uint8, "bins", 3)
+    C, H, W = bins.shape
+    if C != model.params.C:
+        raise ValueError("bins.shape[0] != model C")
+    _dev_tensor(out.score, torch.float32, "score", 2)
+    for name, nd in (("amap", 2), ("w1", 2), ("achan", 3)):
+        if getattr(out, name) is not None:
+            _dev_tensor(getattr(out, name), torch.float32, name, nd)
+    _check(lib().qfca_score_map_noalloc(ctx.handle, model.handle, _ptr(bins), H, W, _ptr(out.score),
+                                        _ptr(out.amap), _ptr(out.w1), _ptr(out.achan)))
+    return out
 
 
 def qfca_inspect_windows(ctx: Context, model: Model, bins):

@@ -375,12 +375,14 @@ ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
     return t;
 }
 
+}  // namespace
+
 // The score launch sequence of qfca_score_map on caller-given fixed-point
 // buffers asum [H][W] (and w1sum [H][W] when w1 is wanted): zero them, score
-// tiles, channel mean and blur.
-qfca_status score_map_into(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
-                           float* score, float* amap, float* w1, float* achan, long long* asum,
-                           long long* w1sum, int* dbg_cp = nullptr, int* dbg_I = nullptr) {
+// tiles, channel mean and blur.  Arguments checked by score_map_check.
+qfca_status qfca::score_map_into(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
+                                 float* score, float* amap, float* w1, float* achan, long long* asum,
+                                 long long* w1sum, int* dbg_cp, int* dbg_I) {
     ScoreLaunch L;
     L.dbg_cp = dbg_cp; L.dbg_I = dbg_I;
     L.bins = bins; L.C = m->p.C; L.H = H; L.W = W; L.T = m->p.T; L.B = m->p.B;
@@ -411,6 +413,23 @@ qfca_status score_map_into(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int3
     }
     return QFCA_OK;
 }
+
+qfca_status qfca::score_map_check(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
+                                  const float* score) {
+    if (!ctx || !m || !bins || !score) return fail(QFCA_E_ARG, "NULL argument");
+    qfca_status st = check_shape(H, W, m->p.C);
+    if (st != QFCA_OK) return st;
+    if (!m->has_ref) return fail(QFCA_E_STATE, "model has no reference");
+    if (m->device != ctx->device) return fail(QFCA_E_ARG, "model and context are on different devices");
+    HIP_TRY(hipSetDevice(ctx->device));
+    return QFCA_OK;
+}
+
+int qfca::ctx_device(qfca_ctx ctx) { return ctx->device; }
+
+qfca_status qfca::status_fail(qfca_status s, const std::string& msg) { return fail(s, msg); }
+
+namespace {
 
 
 }  // namespace
@@ -448,6 +467,12 @@ qfca_status qfca_ctx_create(int32_t device, void* hip_stream, qfca_ctx* out) {
     if (!c) return fail(QFCA_E_NOMEM, "context allocation failed");
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    // the device address of this device's allocation-free scratch (once per device)
+    const hipError_t e = noalloc_init(device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipGetSymbolAddress (scratch)");
+    }
     *out = c;
     return QFCA_OK;
 }
@@ -947,12 +972,8 @@ qfca_status qfca_inspect_windows(qfca_ctx ctx, qfca_model m, const uint8_t* bins
 
 qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
                            float* score, float* amap, float* w1, float* achan) {
-    if (!ctx || !m || !bins || !score) return fail(QFCA_E_ARG, "NULL argument");
-    qfca_status st = check_shape(H, W, m->p.C);
+    qfca_status st = score_map_check(ctx, m, bins, H, W, score);
     if (st != QFCA_OK) return st;
-    if (!m->has_ref) return fail(QFCA_E_STATE, "model has no reference");
-    if (m->device != ctx->device) return fail(QFCA_E_ARG, "model and context are on different devices");
-    HIP_TRY(hipSetDevice(ctx->device));
     const size_t N = (size_t)H * W;
     long long* asum = nullptr;
     long long* w1sum = nullptr;

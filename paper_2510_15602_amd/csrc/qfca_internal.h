@@ -89,6 +89,19 @@ hipError_t launch_batch(int T, int CMAX, int KT, int prec, BatchHeader* hdr, con
 // (stream-ordered after the batch), or nullptr.
 qfca_status score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n, long long* const* asum,
                             int32_t* err_host);
+// qfca_score_map's checks (and hipSetDevice), and its launch sequence on
+// caller-given fixed-point buffers (dbg_cp, dbg_I: inspection outputs).
+qfca_status score_map_check(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
+                            const float* score);
+qfca_status score_map_into(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
+                           float* score, float* amap, float* w1, float* achan, long long* asum,
+                           long long* w1sum, int* dbg_cp = nullptr, int* dbg_I = nullptr);
+int ctx_device(qfca_ctx ctx);
+qfca_status status_fail(qfca_status s, const std::string& msg);  // sets the message, returns s
+// Allocation-free entry point: resolves the device address of the static
+// scratch array on `device` (current), once per device.
+hipError_t noalloc_init(int device);
+
 // Validation of one job against the parameters p of its batch.
 qfca_status batch_job_check(qfca_ctx ctx, const qfca_job& job, const qfca_params& p);
 
