@@ -228,8 +228,10 @@ typedef struct {
  * of qfca_quantize + qfca_score_map with the block walk, so every output is
  * bitwise the one those calls give for the same image, whatever the other
  * images of the batch and the tile.  Requires preproc = QFCA_PRE_RESIDUAL,
- * T in {5, 7, 9, 11, 15, 31} and (C, k) within (64, 16), (256, 32) or
- * (512, 64) (FP32; BF16 needs C > 128); QFCA_E_UNSUPPORTED otherwise. */
+ * T odd in 3..31, C <= 512 and k in 1..64 (the kernel is instantiated for
+ * channel/component paddings (64, 16), (256, 32), (512, 64) in FP32 and
+ * (256, 32), (512, 64) in BF16; a model keeps operand tables padded to the
+ * smallest one that holds it); QFCA_E_UNSUPPORTED otherwise. */
 qfca_status qfca_score_batch(qfca_ctx ctx, const qfca_job* jobs, int32_t n);
 
 /* Synchronises the context's stream and reports whether a batch on it gave

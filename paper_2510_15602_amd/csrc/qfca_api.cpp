@@ -68,6 +68,8 @@ struct qfca_model_s {
     float* d_V = nullptr;
     void* d_V1 = nullptr;  // MFMA operand tables of the projection (nullptr: VALU path)
     void* d_V2 = nullptr;
+    void* d_V1b = nullptr;  // the same padded for the batch kernel (batch_combo), or nullptr
+    void* d_V2b = nullptr;
     uint16_t* d_Vbf = nullptr;
     float* d_edges = nullptr;
     float* d_lo = nullptr;
@@ -190,26 +192,47 @@ qfca_status upload_projection(qfca_model m) {
     HIP_TRY(upload(m, &m->d_V, Vf.data(), Vf.size()));
     HIP_TRY(upload(m, &m->d_Vbf, Vb.data(), Vb.size()));
     m->d_V1 = m->d_V2 = nullptr;
+    m->d_V1b = m->d_V2b = nullptr;
     if (pre && k > 0 && mfma_cmax(C, m->p.proj_prec) && mfma_kt(k, m->p.proj_prec)) {
         std::vector<float> Vk((size_t)C * k);
         for (size_t i = 0; i < Vk.size(); ++i) Vk[i] = (float)m->V[i];
-        if (m->p.proj_prec == QFCA_PREC_BF16) {
-            std::vector<uint16_t> Vkb(Vk.size()), T1, T2;
-            for (size_t i = 0; i < Vk.size(); ++i) Vkb[i] = f32_to_bf16(Vk[i]);
-            mfma_tables_bf16(Vkb.data(), C, k, T1, T2);
-            uint16_t *p1 = nullptr, *p2 = nullptr;
-            HIP_TRY(upload(m, &p1, T1.data(), T1.size()));
-            HIP_TRY(upload(m, &p2, T2.data(), T2.size()));
-            m->d_V1 = p1;
-            m->d_V2 = p2;
-        } else {
-            std::vector<float> T1, T2;
-            mfma_tables_f32(Vk.data(), C, k, T1, T2);
-            float *p1 = nullptr, *p2 = nullptr;
-            HIP_TRY(upload(m, &p1, T1.data(), T1.size()));
-            HIP_TRY(upload(m, &p2, T2.data(), T2.size()));
-            m->d_V1 = p1;
-            m->d_V2 = p2;
+        std::vector<uint16_t> Vkb(Vk.size());
+        for (size_t i = 0; i < Vk.size(); ++i) Vkb[i] = f32_to_bf16(Vk[i]);
+        const bool bf = m->p.proj_prec == QFCA_PREC_BF16;
+        // tables padded to (CM, KT): uploads them, returns the two device pointers
+        auto tables = [&](int CM, int KT, void** d1, void** d2) -> qfca_status {
+            if (bf) {
+                std::vector<uint16_t> T1, T2;
+                mfma_tables_bf16_at(Vkb.data(), C, k, CM, KT, T1, T2);
+                uint16_t *p1 = nullptr, *p2 = nullptr;
+                HIP_TRY(upload(m, &p1, T1.data(), T1.size()));
+                HIP_TRY(upload(m, &p2, T2.data(), T2.size()));
+                *d1 = p1;
+                *d2 = p2;
+            } else {
+                std::vector<float> T1, T2;
+                mfma_tables_f32_at(Vk.data(), C, k, CM, KT, T1, T2);
+                float *p1 = nullptr, *p2 = nullptr;
+                HIP_TRY(upload(m, &p1, T1.data(), T1.size()));
+                HIP_TRY(upload(m, &p2, T2.data(), T2.size()));
+                *d1 = p1;
+                *d2 = p2;
+            }
+            return QFCA_OK;
+        };
+        const int CM = mfma_cmax(C, m->p.proj_prec), KT = mfma_kt(k, m->p.proj_prec);
+        qfca_status st = tables(CM, KT, &m->d_V1, &m->d_V2);
+        if (st != QFCA_OK) return st;
+        // the persistent batch kernel is instantiated for fewer paddings: its
+        // own copy of the tables when its padding differs
+        int CMb = 0, KTb = 0;
+        if (batch_combo(C, k, m->p.proj_prec, &CMb, &KTb)) {
+            if (CMb == CM && KTb == KT) {
+                m->d_V1b = m->d_V1;
+                m->d_V2b = m->d_V2;
+            } else if ((st = tables(CMb, KTb, &m->d_V1b, &m->d_V2b)) != QFCA_OK) {
+                return st;
+            }
         }
     } else if (pre && k > 0 && m->p.proj_prec == QFCA_PREC_BF16) {
         return fail(QFCA_E_UNSUPPORTED, "the BF16 projection needs C <= 512");
@@ -1023,10 +1046,11 @@ qfca_status qfca::batch_job_check(qfca_ctx ctx, const qfca_job& J, const qfca_pa
     if (J.model->device != ctx->device) return fail(QFCA_E_ARG, "model on another device");
     qfca_status st = check_shape(J.H, J.W, p.C);
     if (st != QFCA_OK) return st;
-    const int CM = mfma_cmax(p.C, p.proj_prec), KT = mfma_kt(p.k, p.proj_prec);
-    if (p.preproc != QFCA_PRE_RESIDUAL || !CM || !KT || !batch_supported(p.T, CM, KT, p.proj_prec) ||
-        !J.model->d_V1)
-        return fail(QFCA_E_UNSUPPORTED, "batched path: unsupported (T, C, k, precision) combination");
+    int CM = 0, KT = 0;
+    if (p.preproc != QFCA_PRE_RESIDUAL || !batch_combo(p.C, p.k, p.proj_prec, &CM, &KT) ||
+        !batch_supported(p.T, CM, KT, p.proj_prec) || !J.model->d_V1b)
+        return fail(QFCA_E_UNSUPPORTED, "batched path: needs the PCA residual, T odd in 3..31, C <= 512 and "
+                                        "k in 1..64");
     return QFCA_OK;
 }
 
@@ -1042,7 +1066,8 @@ qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n,
         if (st != QFCA_OK) return st;
         if (asum_ext && !asum_ext[i]) return fail(QFCA_E_ARG, "NULL channel-sum buffer");
     }
-    const int CM = mfma_cmax(p.C, p.proj_prec), KT = mfma_kt(p.k, p.proj_prec);
+    int CM = 0, KT = 0;
+    batch_combo(p.C, p.k, p.proj_prec, &CM, &KT);
     HIP_TRY(hipSetDevice(ctx->device));
     const ScoreTile tile = batch_tile(ctx, p);
     const int Bp = batch_lanes(p.B);
@@ -1090,7 +1115,7 @@ qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n,
         long long* asum = asum_ext ? asum_ext[i] : sa + oa;
         if (!asum_ext) oa += (size_t)N;
         b.pa.X = J.X; b.pa.C = p.C; b.pa.N = N; b.pa.k = p.k; b.pa.B = p.B;
-        b.pa.mu = m->d_mu; b.pa.V1 = m->d_V1; b.pa.V2 = m->d_V2; b.pa.edges = m->d_edges;
+        b.pa.mu = m->d_mu; b.pa.V1 = m->d_V1b; b.pa.V2 = m->d_V2b; b.pa.edges = m->d_edges;
         b.pa.lo = m->d_lo; b.pa.inv_delta = m->d_invd; b.pa.fastd = m->d_fastd; b.pa.bins = bins;
         b.pa.resid = nullptr;
         b.pa.ntiles = (N + 15) / 16;

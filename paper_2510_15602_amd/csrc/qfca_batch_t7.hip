@@ -1,0 +1,5 @@
+// Instantiations of the persistent batch kernel for T = 31 (one
+// translation unit per group of window sides, so they compile in parallel).
+#include "qfca_batch_impl.h"
+
+QFCA_BATCH_INSTANTIATE(31)

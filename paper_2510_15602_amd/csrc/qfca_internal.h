@@ -208,6 +208,17 @@ int mfma_kt(int k, int prec);
 void mfma_tables_f32(const float* V, int C, int k, std::vector<float>& V1, std::vector<float>& V2);
 void mfma_tables_bf16(const uint16_t* Vb, int C, int k, std::vector<uint16_t>& V1,
                       std::vector<uint16_t>& V2);
+// The same tables padded to CM channels and KT 16-wide component tiles
+// (CM >= C, 16 KT >= k; KT even in BF16).
+void mfma_tables_f32_at(const float* V, int C, int k, int CM, int KT, std::vector<float>& V1,
+                        std::vector<float>& V2);
+void mfma_tables_bf16_at(const uint16_t* Vb, int C, int k, int CM, int KT, std::vector<uint16_t>& V1,
+                         std::vector<uint16_t>& V2);
+// Channel and component padding of the persistent batch kernel for (C, k):
+// the smallest of its instantiated shapes (64, 1), (256, 2), (512, 4) (FP32)
+// or (256, 2), (512, 4) (BF16) that holds C channels and k components;
+// false if none does (C > 512 or k outside 1..64).
+bool batch_combo(int C, int k, int prec, int* CM, int* KT);
 hipError_t launch_proj_mfma(const ProjLaunch& L, const void* V1, const void* V2, hipStream_t st);
 
 // Fit statistics.

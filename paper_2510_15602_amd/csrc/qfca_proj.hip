@@ -309,9 +309,19 @@ int mfma_kt(int k, int prec) {
     return kt == 3 ? 4 : kt;
 }
 
-// Operand tables: see the file comment.  V: host [C][k] (float).
+// Operand tables: see the file comment.  V: host [C][k] (float), padded to
+// CM channels and KT component tiles (zero rows and columns).
 void mfma_tables_f32(const float* V, int C, int k, std::vector<float>& V1, std::vector<float>& V2) {
-    const int CM = mfma_cmax(C, QFCA_PREC_FP32), KT = mfma_kt(k, QFCA_PREC_FP32), NU = 4 * KT;
+    mfma_tables_f32_at(V, C, k, mfma_cmax(C, QFCA_PREC_FP32), mfma_kt(k, QFCA_PREC_FP32), V1, V2);
+}
+
+void mfma_tables_bf16(const uint16_t* Vb, int C, int k, std::vector<uint16_t>& V1, std::vector<uint16_t>& V2) {
+    mfma_tables_bf16_at(Vb, C, k, mfma_cmax(C, QFCA_PREC_BF16), mfma_kt(k, QFCA_PREC_BF16), V1, V2);
+}
+
+void mfma_tables_f32_at(const float* V, int C, int k, int CM, int KT, std::vector<float>& V1,
+                        std::vector<float>& V2) {
+    const int NU = 4 * KT;
     V1.assign((size_t)CM * KT * 16, 0.f);
     V2.assign((size_t)CM * KT * 16, 0.f);
     auto at = [&](int c, int j) { return (c < C && j < k) ? V[(size_t)c * k + j] : 0.f; };
@@ -327,8 +337,9 @@ void mfma_tables_f32(const float* V, int C, int k, std::vector<float>& V1, std::
                         at(16 * t + 4 * (n % 4) + n / 4, 16 * (u / 4) + 4 * g + (u % 4));
 }
 
-void mfma_tables_bf16(const uint16_t* Vb, int C, int k, std::vector<uint16_t>& V1, std::vector<uint16_t>& V2) {
-    const int CM = mfma_cmax(C, QFCA_PREC_BF16), KT = mfma_kt(k, QFCA_PREC_BF16), NU = KT / 2;
+void mfma_tables_bf16_at(const uint16_t* Vb, int C, int k, int CM, int KT, std::vector<uint16_t>& V1,
+                         std::vector<uint16_t>& V2) {
+    const int NU = KT / 2;
     V1.assign((size_t)CM * KT * 16, 0);
     V2.assign((size_t)CM * KT * 16, 0);
     auto at = [&](int c, int j) -> uint16_t { return (c < C && j < k) ? Vb[(size_t)c * k + j] : (uint16_t)0; };
