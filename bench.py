@@ -1,15 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the QFCA score path on one MI355X.
 
-Workload: one 256 x 256 feature map with C = 256 float32 channels (seeded
-Gaussian random-field texture with three anomalies), PCA residual with k = 32
-components, B = 32 bins, T = 15 windows, sigma_s = 1.
+Headline workload: one 256 x 256 feature map with C = 256 float32 channels
+(seeded Gaussian random-field texture with three anomalies), PCA residual
+with k = 32 components, B = 32 bins, T = 15 windows, sigma_s = 1.
 
 One step = one image through quantisation (PCA residual projection + bins)
-and the score map (window histograms, Algorithm 1, association, channel mean,
+and the score map (window histograms, Algorithm 1, association, channel sum,
 blur), with the image's model fitted beforehand on the same image (the
 zero-shot fit latency is reported separately as fit_ms).  Inputs are resident
-in device memory when the timed region starts.
+in device memory when the timed region starts.  `value` is the timed K steps'
+throughput; latency_ms gives p50/p99 of separately synchronised steps.
+
+Beside it: the 64-image uneven BF16 batch (batched_bf16), the 8 x 1024^2 +
+32 x 256^2, C = 512, B = 64, T = 31 BF16 batch (large_bf16), the Poisson
+serving run (serving_bf16), each BF16 leg with its bin flip rate and score
+error against the FP64 oracle, and the FP64 oracle itself on the host
+(cpu_baseline).  --sweep times the score kernel against T and B instead.
 
 Prints one JSON line.  --gpus above 1 is refused: this benchmark measures one
 GPU.
@@ -30,11 +37,12 @@ HBM_PEAK_GBS = 8000.0
 # 32-bit vector ALU lane-operations per second: 256 CUs x 64 lanes x 2.4 GHz
 # (packed FP32 is not used).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic vector operations per (pixel, channel, bin) of the score kernel:
-# window cumulative count by separable running sums (4), the closed-form
-# transport numerator from two neighbouring counts and the reference tables
-# (10), the per-bin error I / P (4) and the separable box association (4).
-SCORE_OPS_PER_PCB = 22
+# Algorithmic vector operations per (pixel, channel, bin) of the score kernel,
+# the per-(pixel, channel, bin) count of the method's own work: window
+# cumulative count by separable running sums (3), the closed-form transport
+# numerator from two neighbouring counts and the reference table (10), the
+# per-bin error I / P (3) and the separable box association (4).
+SCORE_OPS_PER_PCB = 20
 METRIC = "score Mpixel/s at 256\u00b2\u00d7256ch (FP32 vs BF16-batched); p50/p99 latency"
 
 
@@ -72,28 +80,67 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prec", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--seed", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--latency-steps", type=int, default=50)
+    ap.add_argument("--latency-steps", type=int, default=100)
     ap.add_argument("--batch-images", type=int, default=64,
                     help="images in the uneven BF16 batch measured beside the single-image path (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the open-loop Poisson serving run (0: skip)")
-    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-warmup", type=float, default=3.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--large", type=int, default=1,
+                    help="measure the 8 x 1024^2 + 32 x 256^2, C=512, k=64 BF16, B=64, T=31 batch (0: skip)")
+    ap.add_argument("--large-steps", type=int, default=3)
+    ap.add_argument("--no-flips", action="store_true",
+                    help="skip the BF16 flip rates and score errors against the FP64 oracle")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark, time the score kernel on the 256x256 x 256 image for "
+                         "T in 3..31 and B in 4..64 and print one JSON line")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="after the run, run an elementwise kernel twice over a MIB-sized float32 buffer so "
                          "that hardware byte counters of the run can be scaled by a copy of known size")
     return ap.parse_args()
+
+
+def bf16_vs_fp64(q, torch, np, model, X, bins, score=None, pixels=None):
+    """Bins of the BF16 projection against the FP64 oracle's (the residual
+    (I - V V^T)(x - mu) in float64 with the model's own mu and V, quantised with
+    the model's float32 edges), and, given the GPU score of those bins, the
+    score error against the oracle's score of its own bins with the same
+    model: (flips, values compared, max |score - oracle| / max |oracle|).
+    pixels: optional flat pixel indices to compare bins on (a sample)."""
+    import oracle
+    prm = model.params
+    Xh = X.detach().cpu().numpy()
+    C, H, W = Xh.shape
+    mu, V = model.read("mu").astype(np.float64), model.read("V").astype(np.float64)
+    edges = model.read("edges")
+    gb = bins.detach().cpu().numpy().reshape(C, -1)
+    if pixels is not None:
+        Xs = np.ascontiguousarray(Xh.reshape(C, -1)[:, pixels])
+        R = oracle.residual(Xs, mu, V)
+        ob = oracle.quantize(R, prm.B, edges)
+        return int((ob != gb[:, pixels]).sum()), int(ob.size), None
+    R = oracle.residual(Xh, mu, V)
+    ob = oracle.quantize(R, prm.B, edges)
+    flips = int((ob.reshape(C, -1) != gb).sum())
+    err = None
+    if score is not None:
+        ref = oracle.score(ob, prm.T, prm.B, model.read("cR"), model.read("delta"), prm.sigma_s)
+        g = score.detach().cpu().numpy().astype(np.float64)
+        err = float(np.abs(g - ref.score).max() / max(np.abs(ref.score).max(), 1e-30))
+    return flips, int(ob.size), err
+
 
 
 def batched_leg(args, q, torch, np, dev):
@@ -151,6 +198,19 @@ def batched_leg(args, q, torch, np, dev):
         err = max(err, float(((score - s32).abs().max() / s32.abs().max().clamp_min(1e-30)).item()))
         m32.close()
     sides = sorted({int(j[1].shape[1]) for j in jobs})
+    vs64 = None
+    if not args.no_flips:
+        # one image of each side against the FP64 oracle (bins), the smallest
+        # one's score against the oracle's score of the oracle's bins
+        fl, tot, err = 0, 0, None
+        for sd in sides:
+            i = next(ii for ii, j in enumerate(jobs) if int(j[1].shape[1]) == sd)
+            m, X, score, bins = jobs[i]
+            f, t, e = bf16_vs_fp64(q, torch, np, m, X, bins, score if sd == sides[0] else None)
+            fl, tot = fl + f, tot + t
+            err = e if e is not None else err
+        vs64 = {"flip_rate": fl / tot, "bins_compared": tot, "max_score_rel_err": err,
+                "images": f"one image of each side {sides}; score error on the {sides[0]}x{sides[0]} one"}
     return {
         "value": round(px / (ms * 1e-3) / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(ms, 3),
         "graph_ms": round(ev_ms / max(ev_n, 1), 3), "images": len(jobs), "pixels": px,
@@ -161,7 +221,75 @@ def batched_leg(args, q, torch, np, dev):
         "tile": tile, "fit_ms_median": round(float(np.median(fit_ms)), 3),
         "bf16_flip_rate_vs_fp32": flips / (px * p["C"]),
         "bf16_max_score_rel_err_vs_fp32": err,
+        "bf16_vs_fp64_oracle": vs64,
     }
+
+
+def large_leg(args, q, torch, np, dev):
+    """8 maps of 1024x1024 and 32 of 256x256, C=512 float32, PCA residual k=64
+    on BF16 MFMA (FP32 accumulation), B=64, T=31: one graph replay of the
+    persistent kernel per step, autotuned tile, every model fitted on its
+    image beforehand (untimed)."""
+    import qfca_synth
+    C, k, B, T = 512, 64, 64, 31
+    ctx = q.Context(0)
+    prm = q.Params.make(C=C, k=k, B=B, T=T, proj_prec=q.QFCA_PREC_BF16)
+    jobs, px = [], 0
+    big = [("shift", 16, 96), ("scale", 16, 96), ("permute", 16, 96), ("shift", 16, 96), ("scale", 16, 96)]
+    for i in range(8 + 32):
+        side = 1024 if i < 8 else 256
+        X, _, _ = qfca_synth.make_texture_torch(C, side, side, (500 + i) if i < 8 else (510 + i - 8), dev,
+                                                anomalies=big if i < 8 else [("shift", 8, 32)])
+        m = q.qfca_fit_pca(ctx, prm, X)
+        jobs.append((m, X, torch.empty((side, side), device=dev),
+                     torch.empty((C, side, side), dtype=torch.uint8, device=dev)))
+        px += side * side
+    torch.cuda.synchronize()
+    tile = None
+    if not args.no_autotune:
+        ws, hb, tms = q.qfca_autotune(ctx, jobs)
+        tile = {"Ws": ws, "Hb": hb, "ms": round(tms, 3)}
+    q.qfca_score_batch(ctx, jobs)
+    torch.cuda.synchronize()
+    ctx.profile_read("score")
+    ctx.profile(True, kernels=["score"])
+    t0 = time.perf_counter()
+    for _ in range(args.large_steps):
+        q.qfca_score_batch(ctx, jobs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile(False)
+    ev_ms, ev_n = ctx.profile_read("score")
+    if q.qfca_batch_error(ctx) != 0:
+        raise RuntimeError("batched kernel reported a failed dependency wait")
+    ms = (t1 - t0) * 1e3 / args.large_steps
+    ops = float(px) * C * B * SCORE_OPS_PER_PCB
+    vs64 = None
+    if not args.no_flips:
+        # bins of one 1024^2 map on a sample of 65536 pixels and of one 256^2
+        # map in full, and the score of that 256^2 map
+        rng = np.random.Generator(np.random.PCG64(5))
+        f1, t1_, _ = bf16_vs_fp64(q, torch, np, jobs[0][0], jobs[0][1], jobs[0][3],
+                                  pixels=np.sort(rng.choice(1024 * 1024, 65536, replace=False)))
+        f2, t2_, err = bf16_vs_fp64(q, torch, np, jobs[8][0], jobs[8][1], jobs[8][3], jobs[8][2])
+        vs64 = {"flip_rate": (f1 + f2) / (t1_ + t2_), "bins_compared": t1_ + t2_, "max_score_rel_err": err,
+                "images": "65536 sampled pixels of one 1024x1024 map and one whole 256x256 map (bins); "
+                          "the 256x256 map's score"}
+    for j in jobs:
+        j[0].close()
+    return {
+        "value": round(px / (ms * 1e-3) / 1e6, 3), "unit": "Mpixel/s", "ms_per_step": round(ms, 2),
+        "graph_ms": round(ev_ms / max(ev_n, 1), 2), "images": len(jobs), "pixels": px,
+        "steps": args.large_steps, "dtype": "bf16-proj/f32",
+        "workload": f"8 maps of 1024x1024 and 32 of 256x256, C={C} float32, PCA residual k={k} (BF16 MFMA, "
+                    f"FP32 accumulation), B={B}, T={T}, one persistent kernel per step under a HIP graph",
+        "tile": tile,
+        "valu": {"ops_per_step": ops, "kappa": SCORE_OPS_PER_PCB,
+                 "achieved_tops": round(ops / (ms * 1e-3) / 1e12, 3),
+                 "frac": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)},
+        "bf16_vs_fp64_oracle": vs64,
+    }
+
 
 
 def serving_leg(args, q, torch, np, dev, tile=None):
@@ -221,6 +349,18 @@ def serving_leg(args, q, torch, np, dev, tile=None):
     sched, lat, bs, pxs, wall, status = run(args.serve_seconds, seed=4)
     st = srv.stats()
     srv.close()
+    vs64 = None
+    if not args.no_flips:
+        # one 256x256 request image of class 0: its served map is the one
+        # qfca_score_batch gives it alone, its bins those of qfca_quantize
+        X = pool[(0, 256, 0)]
+        s1 = torch.empty((256, 256), device=dev)
+        q.qfca_score_batch(ctx, [(models[0], X, s1)])
+        b1, _ = q.qfca_quantize(ctx, models[0], X)
+        torch.cuda.synchronize()
+        f, t, err = bf16_vs_fp64(q, torch, np, models[0], X, b1, s1)
+        vs64 = {"flip_rate": f / t, "bins_compared": t, "max_score_rel_err": err,
+                "images": "one 256x256 request image against its class model"}
     for m in models:
         m.close()
     if any(s != 0 for s in status):
@@ -241,7 +381,50 @@ def serving_leg(args, q, torch, np, dev, tile=None):
         "max_inflight_seen": st["max_inflight_seen"], "deferred_memory": st["deferred_memory"] - st0["deferred_memory"],
         "hbm_budget_gib": args.serve_budget_gib, "arena_peak_gib": round(st["arena_peak"] / 2 ** 30, 3),
         "slots": args.serve_slots, "max_batch": args.serve_max_batch,
+        "warmup_s": args.serve_warmup, "bf16_vs_fp64_oracle": vs64,
     }
+
+
+def sweep(args, q, torch, np, dev):
+    """Score-kernel time on the 256x256 x 256 image against the window side T
+    (B = 32) and the bin count B (T = 15), FP32 projection, model fitted on
+    the image: the T-independence of the association and the linear cost in
+    B (one JSON line)."""
+    import qfca_synth
+    ts, p = qfca_synth.workload_256(args.seed)
+    X = torch.from_numpy(ts[0].X).to(dev)
+    C, H, W = ts[0].X.shape
+    ctx = q.Context(0)
+    out = {"workload": f"{H}x{W} feature map, C={C} float32, PCA residual k={p['k']}, score kernel only",
+           "kappa": SCORE_OPS_PER_PCB, "T_sweep": [], "B_sweep": []}
+
+    def one(T, B):
+        prm = q.Params.make(C=C, k=p["k"], B=B, T=T, sigma_s=p["sigma_s"])
+        m = q.qfca_fit_pca(ctx, prm, X)
+        bins, _ = q.qfca_quantize(ctx, m, X)
+        o = q.qfca_score_map(ctx, m, bins)
+        for _ in range(3):
+            q.qfca_score_map(ctx, m, bins, out=o)
+        torch.cuda.synchronize()
+        ctx.profile_read("score")
+        ctx.profile(True, kernels=["score"])
+        for _ in range(20):
+            q.qfca_score_map(ctx, m, bins, out=o)
+        torch.cuda.synchronize()
+        ctx.profile(False)
+        ms, n = ctx.profile_read("score")
+        m.close()
+        ms /= max(n, 1)
+        ops = float(H) * W * C * B * SCORE_OPS_PER_PCB
+        return {"T": T, "B": B, "score_ms": round(ms, 4), "mpx_s": round(H * W / (ms * 1e-3) / 1e6, 2),
+                "valu_frac": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)}
+
+    for T in range(3, 32, 2):
+        out["T_sweep"].append(one(T, 32))
+    for B in (4, 8, 12, 16, 24, 32, 48, 64):
+        out["B_sweep"].append(one(15, B))
+    print(json.dumps(out), flush=True)
+
 
 
 def main():
@@ -256,10 +439,13 @@ def main():
     import paper_2510_15602_amd as q
     import qfca_synth
 
+    dev = torch.device("cuda:0")
+    if args.sweep:
+        sweep(args, q, torch, np, dev)
+        return
     ts, p = qfca_synth.workload_256(args.seed)
     tex = ts[0]
     C, H, W = tex.X.shape
-    dev = torch.device("cuda:0")
     X = torch.from_numpy(tex.X).to(dev)
     ctx = q.Context(0)
     prec = q.QFCA_PREC_BF16 if args.prec == "bf16" else q.QFCA_PREC_FP32
@@ -333,8 +519,10 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": measured_traffic() if default_workload else None, "traffic_unit": "bytes/launch",
-                "kernel": "k_score", "avg_ms": round(score_ms, 4),
-                "ops_per_launch": score_ops}
+                "kernel": "k_score_t<15>", "avg_ms": round(score_ms, 4),
+                "ops_per_launch": score_ops, "kappa": SCORE_OPS_PER_PCB,
+                "ops_model": "kappa vector ops per (pixel, channel, bin): window count 3, Alg. 1 numerator 10, "
+                             "e = I/P 3, box association 4"}
     kernels = {
         k: {"avg_ms": round(v[0] / max(v[1], 1), 4), "launches": v[1]} for k, v in kt.items()}
     kernels["proj"]["hbm_gbs"] = round(proj_bytes / (proj_ms * 1e-3) / 1e9, 1)
@@ -357,6 +545,10 @@ def main():
     batched = None
     if args.batch_images > 0:
         batched = batched_leg(args, q, torch, np, dev)
+        torch.cuda.empty_cache()
+    large = None
+    if args.large:
+        large = large_leg(args, q, torch, np, dev)
         torch.cuda.empty_cache()
     serving = None
     if args.serve_seconds > 0:
@@ -389,6 +581,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "batched_bf16": batched,
+        "large_bf16": large,
         "serving_bf16": serving,
     }
     print(json.dumps(res), flush=True)
