@@ -54,9 +54,18 @@ enum { QFCA_PRE_NONE = 0,       /* plain QFCA: histogram the features as given *
 enum { QFCA_PREC_FP32 = 0,      /* projection in FP32 */
        QFCA_PREC_BF16 = 1 };    /* projection on BF16 MFMA, FP32 accumulate */
 
+/* How the reference histogram is taken from the full T x T windows of the fit
+ * image (Sec. 3.2; the choices of Sec. 4.5.3, Tab. 3). */
+enum { QFCA_REF_MEDIAN_QUAN = 0,  /* rank-wise lower median of the sorted windows, then
+                                     quantised (the paper's choice; default) */
+       QFCA_REF_MEAN_QUAN = 1,    /* rank-wise mean of the sorted windows, then quantised */
+       QFCA_REF_QUAN_MEDIAN = 2,  /* bin-wise lower median of the window histograms (mass:
+                                     the sum of the medians) */
+       QFCA_REF_QUAN_MEAN = 3 };  /* bin-wise mean of the window histograms (fractional) */
+
 /* Method parameters.  Paper defaults: B = 16 bins (Sec. 4.5.1), k = 10
- * principal components (Sec. 4.5.2), sigma_p = infinity (box association,
- * the only one implemented), sigma_s = 1 (Sec. 4.5.4).
+ * principal components (Sec. 4.5.2), sigma_p = infinity (box association),
+ * sigma_s = 1 (Sec. 4.5.4), median -> quan reference (Sec. 4.5.3).
  *   C        channels, 1..2048
  *   k        principal components removed, 0..C-1 (ignored for PRE_NONE)
  *   B        bins N of Sec. 3.1, 1..64
@@ -64,11 +73,19 @@ enum { QFCA_PREC_FP32 = 0,      /* projection in FP32 */
  *   q_lo/hi  quantisation range as per-channel quantiles, 0 <= q_lo < q_hi <= 1
  *   sigma_s  final Gaussian blur, 0 (none) .. 5 px
  *   preproc  QFCA_PRE_*
- *   proj_prec QFCA_PREC_* */
+ *   proj_prec QFCA_PREC_*
+ *   sigma_p  association weights (Eq. 2, Sec. 4.5.4): the error of a pixel's
+ *            bin in the window centred at p is weighted by
+ *            exp(-|p - x|^2 / (2 sigma_p^2)) over the T x T windows holding
+ *            the pixel (renormalised over those inside the image); INFINITY
+ *            (the default) is the plain mean.  > 0.
+ *   reference QFCA_REF_* (used by the fit) */
 typedef struct {
     int32_t C, k, B, T;
     float q_lo, q_hi, sigma_s;
     int32_t preproc, proj_prec;
+    float sigma_p;
+    int32_t reference;
 } qfca_params;
 
 typedef struct qfca_ctx_s* qfca_ctx;
@@ -140,10 +157,21 @@ qfca_status qfca_model_create(qfca_ctx ctx, const qfca_params* params, const flo
                               const float* V, const float* edges, const double* delta,
                               const int32_t* cR, qfca_model* out);
 
-/* (Re)compute the model's median reference from device bins [C][H][W]
- * (H, W >= T), exactly in integers (Sec. 3.2).  Synchronous. */
+/* (Re)compute the model's reference from device bins [C][H][W] (H, W >= T)
+ * by params->reference: median -> quan exactly in integers (Sec. 3.2),
+ * quan -> median and quan -> mean from the count table of the windows' bin
+ * counts (Tab. 3).  mean -> quan needs the real values and is computed by
+ * qfca_fit_pca only (QFCA_E_UNSUPPORTED here).  Synchronous. */
 qfca_status qfca_fit_reference(qfca_ctx ctx, qfca_model model, const uint8_t* bins,
                                int32_t H, int32_t W);
+
+/* Set a general reference: cRw host [C][B] cumulative weights, nonnegative,
+ * nondecreasing per channel, finite (any total mass M_R > 0 or 0; Alg. 1
+ * accepts arbitrary weights, Sec. 3.1: each window is compared after scaling
+ * both histograms to equal mass).  Integer weights of mass T*T take the
+ * integer path of a qfca_model_create reference; any other reference is
+ * scored by the column-walk kernel in double precision.  Synchronous. */
+qfca_status qfca_model_set_reference(qfca_ctx ctx, qfca_model model, const double* cRw);
 
 /* Quantisation (Sec. 3.1, Sec. 3.3).  X: device [C][H][W] float32.
  * bins: device [C][H][W] uint8 out, bins = #{m : r >= edge_m} with r the
@@ -248,8 +276,10 @@ qfca_status qfca_autotune(qfca_ctx ctx, const qfca_job* jobs, int32_t n, int32_t
 
 /* Model queries.  qfca_model_read copies one field to host memory:
  *   field 0 mu [C] float32, 1 V [C][k] float32, 2 edges [C][B-1] float32,
- *   3 delta [C] float64, 4 cR [C][B] int32, 5 eigenvalues [C] float64
- *   (descending; fit only), 6 lo [C] float64, 7 hi [C] float64.
+ *   3 delta [C] float64, 4 cR [C][B] int32 (integer references of mass T*T
+ *   only), 5 eigenvalues [C] float64 (descending; fit only), 6 lo [C]
+ *   float64, 7 hi [C] float64, 8 reference weights [C][B] float64 (any
+ *   reference).
  * bytes must equal the field size; QFCA_E_STATE if the field is not set. */
 qfca_status qfca_model_params(qfca_model model, qfca_params* out);
 qfca_status qfca_model_read(qfca_model model, int32_t field, void* host_dst, size_t bytes);

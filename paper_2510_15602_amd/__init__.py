@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libqfca.so")
 
 QFCA_PRE_NONE, QFCA_PRE_RESIDUAL = 0, 1
 QFCA_PREC_FP32, QFCA_PREC_BF16 = 0, 1
+QFCA_REF_MEDIAN_QUAN, QFCA_REF_MEAN_QUAN, QFCA_REF_QUAN_MEDIAN, QFCA_REF_QUAN_MEAN = 0, 1, 2, 3
 
 STATUS = {0: "QFCA_OK", 1: "QFCA_E_ARG", 2: "QFCA_E_SHAPE", 3: "QFCA_E_NOMEM", 4: "QFCA_E_DEVICE",
           5: "QFCA_E_STATE", 6: "QFCA_E_NONFINITE", 7: "QFCA_E_UNSUPPORTED"}
@@ -34,7 +35,7 @@ EXPORTS = ("qfca_status_str", "qfca_last_error", "qfca_version", "qfca_ctx_creat
            "qfca_ctx_profile_read", "qfca_ctx_set_tile", "qfca_score_batch", "qfca_batch_error",
            "qfca_autotune", "qfca_clock", "qfca_server_create", "qfca_server_submit",
            "qfca_server_poll", "qfca_server_drain", "qfca_server_stats", "qfca_server_destroy",
-           "qfca_inspect_windows", "qfca_score_map_noalloc")
+           "qfca_inspect_windows", "qfca_score_map_noalloc", "qfca_model_set_reference")
 
 KERNELS = {"score": 0, "proj": 1, "finish": 2}
 
@@ -49,13 +50,14 @@ class Params(ctypes.Structure):
     _fields_ = [("C", ctypes.c_int32), ("k", ctypes.c_int32), ("B", ctypes.c_int32),
                 ("T", ctypes.c_int32), ("q_lo", ctypes.c_float), ("q_hi", ctypes.c_float),
                 ("sigma_s", ctypes.c_float), ("preproc", ctypes.c_int32),
-                ("proj_prec", ctypes.c_int32)]
+                ("proj_prec", ctypes.c_int32), ("sigma_p", ctypes.c_float), ("reference", ctypes.c_int32)]
 
     @classmethod
     def make(cls, C, k=10, B=16, T=9, q_lo=0.01, q_hi=0.99, sigma_s=1.0,
-             preproc=QFCA_PRE_RESIDUAL, proj_prec=QFCA_PREC_FP32):
+             preproc=QFCA_PRE_RESIDUAL, proj_prec=QFCA_PREC_FP32, sigma_p=float("inf"),
+             reference=QFCA_REF_MEDIAN_QUAN):
         return cls(int(C), int(k), int(B), int(T), float(q_lo), float(q_hi), float(sigma_s),
-                   int(preproc), int(proj_prec))
+                   int(preproc), int(proj_prec), float(sigma_p), int(reference))
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -114,6 +116,7 @@ def lib():
         L.qfca_score_map.argtypes = [P, P, P, i32, i32, P, P, P, P]
         L.qfca_inspect_windows.argtypes = [P, P, P, i32, i32, P, P]
         L.qfca_score_map_noalloc.argtypes = [P, P, P, i32, i32, P, P, P, P]
+        L.qfca_model_set_reference.argtypes = [P, P, P]
         L.qfca_model_params.argtypes = [P, ctypes.POINTER(Params)]
         L.qfca_model_read.argtypes = [P, i32, P, sz]
         L.qfca_model_destroy.argtypes = [P]
@@ -148,7 +151,7 @@ def lib():
                      "qfca_model_import",
                      "qfca_ctx_profile", "qfca_ctx_profile_read", "qfca_ctx_set_tile",
                      "qfca_score_batch", "qfca_batch_error", "qfca_autotune", "qfca_inspect_windows",
-                     "qfca_score_map_noalloc"):
+                     "qfca_score_map_noalloc", "qfca_model_set_reference"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -223,7 +226,7 @@ class Context:
 
 FIELDS = {"mu": (0, np.float32), "V": (1, np.float32), "edges": (2, np.float32),
           "delta": (3, np.float64), "cR": (4, np.int32), "evals": (5, np.float64),
-          "lo": (6, np.float64), "hi": (7, np.float64)}
+          "lo": (6, np.float64), "hi": (7, np.float64), "cRw": (8, np.float64)}
 
 
 class Model:
@@ -237,7 +240,7 @@ class Model:
         fid, dt = FIELDS[field]
         p = self.params
         shape = {"mu": (p.C,), "V": (p.C, p.k), "edges": (p.C, max(p.B - 1, 0)), "delta": (p.C,),
-                 "cR": (p.C, p.B), "evals": (p.C,), "lo": (p.C,), "hi": (p.C,)}[field]
+                 "cR": (p.C, p.B), "evals": (p.C,), "lo": (p.C,), "hi": (p.C,), "cRw": (p.C, p.B)}[field]
         out = np.zeros(shape, dt)
         _check(lib().qfca_model_read(self.handle, fid, out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
         return out
@@ -256,6 +259,14 @@ class Model:
 
 # ---------------------------------------------------------------------------
 # Entry points (same names as the C ABI)
+
+def qfca_model_set_reference(ctx: Context, model: Model, cRw):
+    """General reference: cumulative weights [C, B] (host, float64)."""
+    w = np.ascontiguousarray(cRw, dtype=np.float64)
+    if w.shape != (model.params.C, model.params.B):
+        raise ValueError("cRw must be [C, B]")
+    _check(lib().qfca_model_set_reference(ctx.handle, model.handle, w.ctypes.data_as(ctypes.c_void_p)))
+
 
 def qfca_fit_pca(ctx: Context, params: Params, X) -> Model:
     import torch

@@ -22,7 +22,7 @@ using namespace qfca;
 
 enum Slot {
     SL_ASUM = 0, SL_W1SUM, SL_SCORE, SL_RESID, SL_BINS, SL_COUNTS, SL_SEL,
-    SL_COV, SL_MU, SL_RANKS, SL_CR, SL_BBINS, SL_BASUM, SL_COUNT
+    SL_COV, SL_MU, SL_RANKS, SL_CR, SL_CRW, SL_RMPART, SL_BBINS, SL_BASUM, SL_COUNT
 };
 
 struct GraphEntry {
@@ -62,8 +62,10 @@ struct qfca_model_s {
     int m = 1;   // T*T
     std::vector<double> mu, V, evals, lo, hi, delta;
     std::vector<float> edges;
-    std::vector<int32_t> cR;
+    std::vector<int32_t> cR;   // integer reference of mass T*T (the fast path)
+    std::vector<double> cRw;   // the reference as cumulative weights (any reference)
     bool has_ref = false, has_evals = false, has_lohi = false;
+    bool ref_general = false;  // the reference is not integer of mass T*T
     float* d_mu = nullptr;
     float* d_V = nullptr;
     void* d_V1 = nullptr;  // MFMA operand tables of the projection (nullptr: VALU path)
@@ -116,6 +118,9 @@ qfca_status check_params(const qfca_params* p) {
     if (!(p->q_lo >= 0.f && p->q_lo < p->q_hi && p->q_hi <= 1.f))
         return fail(QFCA_E_ARG, "need 0 <= q_lo < q_hi <= 1");
     if (!(p->sigma_s >= 0.f && p->sigma_s <= 5.f)) return fail(QFCA_E_ARG, "sigma_s must be in [0, 5]");
+    if (!(p->sigma_p > 0.f)) return fail(QFCA_E_ARG, "sigma_p must be > 0 (INFINITY: plain mean)");
+    if (p->reference < QFCA_REF_MEDIAN_QUAN || p->reference > QFCA_REF_QUAN_MEAN)
+        return fail(QFCA_E_ARG, "unknown reference");
     return QFCA_OK;
 }
 
@@ -324,7 +329,52 @@ qfca_status upload_tables(qfca_model m) {
     m->tab.delta = m->d_delta;
     m->tab.Bp = Bp;
     m->tab.fxs = fixed_point_scale(m->delta, B);
+    m->tab.cRw = nullptr;
+    m->cRw.assign(m->cR.begin(), m->cR.end());
+    m->ref_general = false;
     m->has_ref = true;
+    return QFCA_OK;
+}
+
+// Sets the reference from cumulative weights (validated by the caller):
+// integer weights of mass T*T go to the integer tables, any other reference
+// to the column-walk kernel's double weights.
+qfca_status set_reference_weights(qfca_model m, const double* cRw) {
+    const int C = m->p.C, B = m->p.B, mm = m->p.T * m->p.T;
+    bool integral = true;
+    for (size_t i = 0; i < (size_t)C * B && integral; ++i)
+        integral = cRw[i] == floor(cRw[i]) && cRw[i] <= (double)mm;
+    for (int c = 0; c < C && integral; ++c) integral = cRw[(size_t)c * B + B - 1] == (double)mm;
+    if (integral) {
+        m->cR.assign((size_t)C * B, 0);
+        for (size_t i = 0; i < m->cR.size(); ++i) m->cR[i] = (int32_t)cRw[i];
+        return upload_tables(m);
+    }
+    // the scaled masses P M_R and R n_p must stay exact in double
+    for (int c = 0; c < C; ++c)
+        if (cRw[(size_t)c * B + B - 1] * (double)mm > 1e15)
+            return fail(QFCA_E_UNSUPPORTED, "reference mass too large");
+    m->cRw.assign(cRw, cRw + (size_t)C * B);
+    m->cR.clear();
+    HIP_TRY(upload(m, &m->tab.cRw, m->cRw.data(), m->cRw.size()));
+    m->tab.delta = m->d_delta;
+    m->tab.Bp = m->Bp;
+    m->tab.fxs = fixed_point_scale(m->delta, B);
+    m->ref_general = true;
+    m->has_ref = true;
+    return QFCA_OK;
+}
+
+// Association weights w(d) = exp(-d^2 / (2 sigma_p^2)), d = -r .. r, of a
+// finite sigma_p (float32, one table per model).
+qfca_status upload_assoc_weights(qfca_model m) {
+    m->tab.wgt = nullptr;
+    if (std::isinf(m->p.sigma_p)) return QFCA_OK;
+    const int T = m->p.T, r = T / 2;
+    const double sp = (double)m->p.sigma_p;
+    std::vector<float> w(T);
+    for (int i = 0; i < T; ++i) w[i] = (float)exp(-(double)((i - r) * (i - r)) / (2.0 * sp * sp));
+    HIP_TRY(upload(m, &m->tab.wgt, w.data(), w.size()));
     return QFCA_OK;
 }
 
@@ -604,7 +654,8 @@ qfca_status qfca_model_read(qfca_model m, int32_t field, void* dst, size_t bytes
             src = tmp.data(); need = tmp.size() * 4; break;
         case 2: src = m->edges.data(); need = (size_t)C * (B - 1) * 4; break;
         case 3: src = m->delta.data(); need = (size_t)C * 8; break;
-        case 4: ok = m->has_ref; src = m->cR.data(); need = (size_t)C * B * 4; break;
+        case 4: ok = m->has_ref && !m->ref_general; src = m->cR.data(); need = (size_t)C * B * 4; break;
+        case 8: ok = m->has_ref; src = m->cRw.data(); need = (size_t)C * B * 8; break;
         case 5: ok = m->has_evals; src = m->evals.data(); need = (size_t)C * 8; break;
         case 6: ok = m->has_lohi; src = m->lo.data(); need = (size_t)C * 8; break;
         case 7: ok = m->has_lohi; src = m->hi.data(); need = (size_t)C * 8; break;
@@ -668,6 +719,7 @@ qfca_status build_model(qfca_ctx ctx, const qfca_params* p, const double* mu, co
                       : ((B > 1 && m->delta[c] > 0.0) ? (double)m->edges[(size_t)c * (B - 1)] - m->delta[c] : 0.0);
     if ((st = upload_projection(m.get())) != QFCA_OK) return st;
     if ((st = upload_quant(m.get())) != QFCA_OK) return st;
+    if ((st = upload_assoc_weights(m.get())) != QFCA_OK) return st;
     if (cR) {
         m->cR.assign(cR, cR + (size_t)C * B);
         if ((st = upload_tables(m.get())) != QFCA_OK) return st;
@@ -676,21 +728,26 @@ qfca_status build_model(qfca_ctx ctx, const qfca_params* p, const double* mu, co
     return QFCA_OK;
 }
 
-// Serialised model: an 8-byte magic, u32 version, u32 flags (bit 0 reference,
-// bit 1 eigenvalues, bit 2 lo/hi), the parameters (C k B T as int32, q_lo q_hi
-// sigma_s as float32, preproc proj_prec as int32), then mu [C] f64, V [C][k]
-// f64 (residual models only), edges [C][B-1] f32, delta [C] f64, and, by
-// flag, cR [C][B] i32, eigenvalues [C] f64, lo [C] f64 and hi [C] f64.  Host
-// byte order.
+// Serialised model: an 8-byte magic, u32 version, u32 flags (bit 0 integer
+// reference, bit 1 eigenvalues, bit 2 lo/hi, bit 3 general reference), the
+// parameters (C k B T as int32, q_lo q_hi sigma_s as float32, preproc
+// proj_prec as int32, then in version 2 sigma_p as float32 and reference as
+// int32), then mu [C] f64, V [C][k] f64 (residual models only), edges
+// [C][B-1] f32, delta [C] f64, and, by flag, cR [C][B] i32, eigenvalues [C]
+// f64, lo [C] f64, hi [C] f64 and the general reference weights [C][B] f64.
+// Host byte order.  Version 1 (no sigma_p, reference) is read with
+// sigma_p = INFINITY and the median -> quan reference.
 constexpr char kModelMagic[8] = {'Q', 'F', 'C', 'A', 'M', 'D', 'L', '\0'};
-constexpr uint32_t kModelVersion = 1;
-constexpr size_t kModelHeader = 8 + 4 + 4 + 40;
+constexpr uint32_t kModelVersion = 2;
+constexpr size_t kParamBytes[3] = {0, 40, 44};
+
+size_t model_header(uint32_t version) { return 8 + 4 + 4 + kParamBytes[version]; }
 
 struct ModelBlob {
-    size_t mu, V, edges, delta, cR, evals, lohi, total;
+    size_t mu, V, edges, delta, cR, evals, lohi, cRw, total;
 };
 
-ModelBlob blob_sizes(const qfca_params& p, uint32_t flags) {
+ModelBlob blob_sizes(const qfca_params& p, uint32_t flags, uint32_t version) {
     ModelBlob z;
     const size_t C = (size_t)p.C;
     z.mu = C * 8;
@@ -700,7 +757,8 @@ ModelBlob blob_sizes(const qfca_params& p, uint32_t flags) {
     z.cR = (flags & 1u) ? C * (size_t)p.B * 4 : 0;
     z.evals = (flags & 2u) ? C * 8 : 0;
     z.lohi = (flags & 4u) ? C * 16 : 0;
-    z.total = kModelHeader + z.mu + z.V + z.edges + z.delta + z.cR + z.evals + z.lohi;
+    z.cRw = (flags & 8u) ? C * (size_t)p.B * 8 : 0;
+    z.total = model_header(version) + z.mu + z.V + z.edges + z.delta + z.cR + z.evals + z.lohi + z.cRw;
     return z;
 }
 
@@ -711,10 +769,11 @@ void put_params(unsigned char* d, const qfca_params& p) {
     memcpy(d, iv, 16);
     memcpy(d + 16, fv, 12);
     memcpy(d + 28, jv, 8);
-    memset(d + 36, 0, 4);
+    memcpy(d + 36, &p.sigma_p, 4);
+    memcpy(d + 40, &p.reference, 4);
 }
 
-qfca_params get_params(const unsigned char* d) {
+qfca_params get_params(const unsigned char* d, uint32_t version) {
     int32_t iv[4];
     float fv[3];
     int32_t jv[2];
@@ -725,6 +784,12 @@ qfca_params get_params(const unsigned char* d) {
     p.C = iv[0]; p.k = iv[1]; p.B = iv[2]; p.T = iv[3];
     p.q_lo = fv[0]; p.q_hi = fv[1]; p.sigma_s = fv[2];
     p.preproc = jv[0]; p.proj_prec = jv[1];
+    p.sigma_p = INFINITY;
+    p.reference = QFCA_REF_MEDIAN_QUAN;
+    if (version >= 2) {
+        memcpy(&p.sigma_p, d + 36, 4);
+        memcpy(&p.reference, d + 40, 4);
+    }
     return p;
 }
 
@@ -745,8 +810,9 @@ qfca_status qfca_model_create(qfca_ctx ctx, const qfca_params* p, const float* m
 
 qfca_status qfca_model_export(qfca_model m, void* host_buf, size_t* inout_bytes) {
     if (!m || !inout_bytes) return fail(QFCA_E_ARG, "NULL argument");
-    const uint32_t flags = (m->has_ref ? 1u : 0u) | (m->has_evals ? 2u : 0u) | (m->has_lohi ? 4u : 0u);
-    const ModelBlob z = blob_sizes(m->p, flags);
+    const uint32_t flags = ((m->has_ref && !m->ref_general) ? 1u : 0u) | (m->has_evals ? 2u : 0u) |
+                           (m->has_lohi ? 4u : 0u) | ((m->has_ref && m->ref_general) ? 8u : 0u);
+    const ModelBlob z = blob_sizes(m->p, flags, kModelVersion);
     if (!host_buf) {
         *inout_bytes = z.total;
         return QFCA_OK;
@@ -760,7 +826,7 @@ qfca_status qfca_model_export(qfca_model m, void* host_buf, size_t* inout_bytes)
     memcpy(d + 8, &kModelVersion, 4);
     memcpy(d + 12, &flags, 4);
     put_params(d + 16, m->p);
-    size_t o = kModelHeader;
+    size_t o = model_header(kModelVersion);
     auto put = [&](const void* src, size_t n) {
         if (n) memcpy(d + o, src, n);
         o += n;
@@ -777,6 +843,7 @@ qfca_status qfca_model_export(qfca_model m, void* host_buf, size_t* inout_bytes)
         put(m->lo.data(), z.lohi / 2);
         put(m->hi.data(), z.lohi / 2);
     }
+    put(m->cRw.data(), z.cRw);
     *inout_bytes = z.total;
     return QFCA_OK;
 }
@@ -785,18 +852,20 @@ qfca_status qfca_model_import(qfca_ctx ctx, const void* host_buf, size_t bytes, 
     if (!ctx || !host_buf || !out) return fail(QFCA_E_ARG, "NULL argument");
     *out = nullptr;
     const unsigned char* d = (const unsigned char*)host_buf;
-    if (bytes < kModelHeader || memcmp(d, kModelMagic, 8) != 0) return fail(QFCA_E_ARG, "not a serialised model");
+    if (bytes < model_header(1) || memcmp(d, kModelMagic, 8) != 0) return fail(QFCA_E_ARG, "not a serialised model");
     uint32_t version = 0, flags = 0;
     memcpy(&version, d + 8, 4);
     memcpy(&flags, d + 12, 4);
-    if (version != kModelVersion) return fail(QFCA_E_UNSUPPORTED, "unknown model format version");
-    if (flags & ~7u) return fail(QFCA_E_ARG, "unknown model flags");
-    const qfca_params p = get_params(d + 16);
+    if (version < 1 || version > kModelVersion) return fail(QFCA_E_UNSUPPORTED, "unknown model format version");
+    if (bytes < model_header(version)) return fail(QFCA_E_ARG, "not a serialised model");
+    if (flags & ~15u) return fail(QFCA_E_ARG, "unknown model flags");
+    if ((flags & 1u) && (flags & 8u)) return fail(QFCA_E_ARG, "two references in one model");
+    const qfca_params p = get_params(d + 16, version);
     qfca_status st = check_params(&p);
     if (st != QFCA_OK) return st;
-    const ModelBlob z = blob_sizes(p, flags);
+    const ModelBlob z = blob_sizes(p, flags, version);
     if (bytes != z.total) return fail(QFCA_E_ARG, "byte count does not match the serialised model");
-    size_t o = kModelHeader;
+    size_t o = model_header(version);
     auto take = [&](size_t n) {
         const unsigned char* q = d + o;
         o += n;
@@ -816,6 +885,8 @@ qfca_status qfca_model_import(qfca_ctx ctx, const void* host_buf, size_t bytes, 
         memcpy(lo.data(), take(z.lohi / 2), z.lohi / 2);
         memcpy(hi.data(), take(z.lohi / 2), z.lohi / 2);
     }
+    std::vector<double> cRw(z.cRw / 8);
+    if (z.cRw) memcpy(cRw.data(), take(z.cRw), z.cRw);
     qfca_model m = nullptr;
     st = build_model(ctx, &p, mu.data(), z.V ? V.data() : nullptr, z.edges ? edges.data() : nullptr, delta.data(),
                      z.cR ? cR.data() : nullptr, z.lohi ? lo.data() : nullptr, &m);
@@ -827,6 +898,17 @@ qfca_status qfca_model_import(qfca_ctx ctx, const void* host_buf, size_t bytes, 
     if (z.lohi) {
         m->hi = hi;
         m->has_lohi = true;
+    }
+    if (z.cRw) {
+        for (size_t i = 0; i < cRw.size(); ++i)
+            if (!std::isfinite(cRw[i]) || cRw[i] < 0.0 || (i % p.B && cRw[i] < cRw[i - 1])) {
+                delete m;
+                return fail(QFCA_E_ARG, "malformed reference weights");
+            }
+        if ((st = set_reference_weights(m, cRw.data())) != QFCA_OK) {
+            delete m;
+            return st;
+        }
     }
     *out = m;
     return QFCA_OK;
@@ -856,18 +938,46 @@ qfca_status qfca_fit_reference(qfca_ctx ctx, qfca_model m, const uint8_t* bins, 
     if (st != QFCA_OK) return st;
     const int C = m->p.C, B = m->p.B, T = m->p.T, mm = T * T;
     if (H < T || W < T) return fail(QFCA_E_SHAPE, "the reference needs H, W >= T");
+    if (m->p.reference == QFCA_REF_MEAN_QUAN)
+        return fail(QFCA_E_UNSUPPORTED, "the mean -> quan reference needs the features: use qfca_fit_pca");
     HIP_TRY(hipSetDevice(ctx->device));
     uint32_t* counts = nullptr;
-    int32_t* dcR = nullptr;
     HIP_TRY(scratch(ctx, SL_COUNTS, (size_t)C * B * (mm + 1) * 4, &counts));
+    const long long P = (long long)(H - T + 1) * (W - T + 1);
+    if (m->p.reference == QFCA_REF_QUAN_MEDIAN || m->p.reference == QFCA_REF_QUAN_MEAN) {
+        // bin-wise statistics of the full windows' bin counts (Tab. 3)
+        double* dw = nullptr;
+        HIP_TRY(scratch(ctx, SL_CRW, (size_t)C * B * 8, &dw));
+        HIP_TRY(launch_refcount(bins, C, H, W, T, B, counts, ctx->stream, 1));
+        HIP_TRY(launch_refstat(counts, C, B, mm, P, m->p.reference == QFCA_REF_QUAN_MEDIAN ? 0 : 1, dw,
+                               ctx->stream));
+        std::vector<double> w((size_t)C * B);
+        HIP_TRY(hipMemcpyAsync(w.data(), dw, w.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return set_reference_weights(m, w.data());
+    }
+    int32_t* dcR = nullptr;
     HIP_TRY(scratch(ctx, SL_CR, (size_t)C * B * 4, &dcR));
     HIP_TRY(launch_refcount(bins, C, H, W, T, B, counts, ctx->stream));
-    const long long P = (long long)(H - T + 1) * (W - T + 1);
     HIP_TRY(launch_refselect(counts, C, B, mm, (P + 1) / 2, dcR, ctx->stream));
     m->cR.assign((size_t)C * B, 0);
     HIP_TRY(hipMemcpyAsync(m->cR.data(), dcR, (size_t)C * B * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return upload_tables(m);
+}
+
+qfca_status qfca_model_set_reference(qfca_ctx ctx, qfca_model m, const double* cRw) {
+    if (!ctx || !m || !cRw) return fail(QFCA_E_ARG, "NULL argument");
+    if (m->device != ctx->device) return fail(QFCA_E_ARG, "model and context are on different devices");
+    const int C = m->p.C, B = m->p.B;
+    for (int c = 0; c < C; ++c)
+        for (int i = 0; i < B; ++i) {
+            const double v = cRw[(size_t)c * B + i];
+            if (!std::isfinite(v) || v < 0.0 || (i > 0 && v < cRw[(size_t)c * B + i - 1]))
+                return fail(QFCA_E_ARG, "reference weights must be finite, >= 0 and nondecreasing");
+        }
+    HIP_TRY(hipSetDevice(ctx->device));
+    return set_reference_weights(m, cRw);
 }
 
 qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int32_t H, int32_t W,
@@ -967,11 +1077,27 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
     m->has_lohi = true;
     if ((st = upload_quant(m.get())) != QFCA_OK) return st;
 
-    // 4. bins with the final edges, then the median reference
+    if ((st = upload_assoc_weights(m.get())) != QFCA_OK) return st;
+
+    // 4. bins with the final edges, then the reference
     uint8_t* bins = nullptr;
     HIP_TRY(scratch(ctx, SL_BINS, (size_t)C * N, &bins));
     if ((st = qfca_quantize(ctx, m.get(), X, H, W, bins, nullptr)) != QFCA_OK) return st;
-    if ((st = qfca_fit_reference(ctx, m.get(), bins, H, W)) != QFCA_OK) return st;
+    if (p->reference == QFCA_REF_MEAN_QUAN) {
+        // rank-wise mean of the sorted full windows of the residual, quantised
+        int nparts = 0, NP = 0;
+        double* part = nullptr;
+        int32_t* dcR = nullptr;
+        HIP_TRY(scratch(ctx, SL_RMPART, refmean_part_bytes(C, p->T, &nparts, &NP), &part));
+        HIP_TRY(scratch(ctx, SL_CR, (size_t)C * B * 4, &dcR));
+        HIP_TRY(launch_refmean(resid, C, H, W, p->T, m->d_edges, B, part, dcR, s));
+        m->cR.assign((size_t)C * B, 0);
+        HIP_TRY(hipMemcpyAsync(m->cR.data(), dcR, (size_t)C * B * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if ((st = upload_tables(m.get())) != QFCA_OK) return st;
+    } else if ((st = qfca_fit_reference(ctx, m.get(), bins, H, W)) != QFCA_OK) {
+        return st;
+    }
     *out = m.release();
     return QFCA_OK;
 }
@@ -983,7 +1109,9 @@ qfca_status qfca_inspect_windows(qfca_ctx ctx, qfca_model m, const uint8_t* bins
     if (st != QFCA_OK) return st;
     if (!m->has_ref) return fail(QFCA_E_STATE, "model has no reference");
     if (m->device != ctx->device) return fail(QFCA_E_ARG, "model and context are on different devices");
-    if (!score_has_block_kernel(m->p.T)) return fail(QFCA_E_UNSUPPORTED, "window inspection needs T in 3..31");
+    if (!score_has_block_kernel(m->p.T) || m->ref_general || !std::isinf(m->p.sigma_p))
+        return fail(QFCA_E_UNSUPPORTED, "window inspection needs T in 3..31, sigma_p = INFINITY and an integer "
+                                        "reference of mass T*T");
     HIP_TRY(hipSetDevice(ctx->device));
     const size_t N = (size_t)H * W;
     long long* asum = nullptr;
@@ -1040,9 +1168,11 @@ qfca_status qfca::batch_job_check(qfca_ctx ctx, const qfca_job& J, const qfca_pa
     if (!J.model || !J.X || !J.score) return fail(QFCA_E_ARG, "job with a NULL model, X or score");
     const qfca_params& q = J.model->p;
     if (q.C != p.C || q.k != p.k || q.B != p.B || q.T != p.T || q.preproc != p.preproc ||
-        q.proj_prec != p.proj_prec || q.sigma_s != p.sigma_s)
+        q.proj_prec != p.proj_prec || q.sigma_s != p.sigma_s || !(q.sigma_p == p.sigma_p))
         return fail(QFCA_E_ARG, "all jobs of a batch must share C, k, B, T, sigma_s, preproc, proj_prec");
     if (!J.model->has_ref) return fail(QFCA_E_STATE, "model without reference");
+    if (J.model->ref_general || !std::isinf(q.sigma_p))
+        return fail(QFCA_E_UNSUPPORTED, "batched path: needs sigma_p = INFINITY and an integer reference of mass T*T");
     if (J.model->device != ctx->device) return fail(QFCA_E_ARG, "model on another device");
     qfca_status st = check_shape(J.H, J.W, p.C);
     if (st != QFCA_OK) return st;

@@ -6,9 +6,11 @@
 #include <algorithm>
 
 #include "qfca_internal.h"
+#include "qfca_tiles.h"
 
 namespace qfca {
 namespace {
+using tiles::lane_prev;
 
 // ------------------------------------------------------------------------
 // Mean: one block per channel, FP64 tree reduction in a fixed order.
@@ -189,6 +191,7 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ vals, 
 struct RArgs {
     const uint8_t* bins;
     int C, H, W, T, B, Bp, S, r, m, Ws, Hb, nsplit;
+    int perbin;  // 1: count the windows' bin counts P(j) instead of their cumulative counts cP(j)
     uint32_t* counts;
 };
 
@@ -364,8 +367,14 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
                     const int q = q0 + i;
                     cP += vn[i] - vo[i];
                     const int px = xb0 + q - r;
+                    // the bin's own count: its cumulative count minus the
+                    // previous bin's (the neighbouring lane of the channel)
+                    // (the exchange runs in every lane, outside any branch:
+                    // a lane with execution off would give 0 to its neighbour)
+                    const int pv = lane_prev(cP);
+                    const int cu = a.perbin ? cP - (j == 0 ? 0 : pv) : cP;
                     if (counting && q < Wb && q >= T - 1 && px >= pxlo && px < pxhi)
-                        atomicAdd(mycnt + (cP >> 1), 1u << ((cP & 1) << 4));
+                        atomicAdd(mycnt + (cu >> 1), 1u << ((cu & 1) << 4));
                 }
             }
         }
@@ -382,6 +391,130 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
             if (v & 0xFFFFu) atomicAdd(dst, v & 0xFFFFu);
             if ((v >> 16) && 2 * w + 1 <= m) atomicAdd(dst + 1, v >> 16);
         }
+    }
+}
+
+// References taken bin by bin over the full-window histograms (Sec. 4.5.3,
+// Tab. 3), from the count table of the windows' bin counts: for every
+// channel (one thread each) and bin i, the lower median over windows of
+// P(i) (kind 0: the h-th smallest, h = ceil(P_w / 2)) or its mean (kind 1),
+// accumulated into cumulative weights cRw [C][B] (double).
+__global__ void k_refstat(const uint32_t* __restrict__ counts, int C, int B, int m, long long nw, int kind,
+                          double* __restrict__ cRw) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const long long h = (nw + 1) / 2;
+    double acc = 0.0;
+    for (int i = 0; i < B; ++i) {
+        const uint32_t* cnt = counts + ((size_t)c * B + i) * (m + 1);
+        double v = 0.0;
+        if (kind == 0) {
+            long long seen = 0;
+            int t = 0;
+            for (t = 0; t < m; ++t) {
+                seen += cnt[t];
+                if (seen >= h) break;
+            }
+            v = (double)t;
+        } else {
+            double sum = 0.0;  // integer-valued, exact below 2^53
+            for (int t = 1; t <= m; ++t) sum += (double)t * (double)cnt[t];
+            v = sum / (double)nw;
+        }
+        acc += v;
+        cRw[(size_t)c * B + i] = acc;
+    }
+}
+
+// Rank-wise mean of the sorted full windows (Sec. 3.2 "mean -> quan"):
+// for channel c (blockIdx.y) and a slice of the window-centre rows
+// (blockIdx.x), every wavefront sorts its windows' T*T values in its LDS
+// region (bitonic, padded to NP = 2^k >= T*T with +inf) and adds the value of
+// rank rho to its running double sum (lane l holds ranks l, l + 64, ...).
+// The sums go to part[(c * gridDim.x + blockIdx.x) * 4 + wave][rho], reduced
+// afterwards in a fixed order.
+template <int NP>
+__global__ __launch_bounds__(256) void k_refmean(const float* __restrict__ R, int C, int H, int W, int T,
+                                                 double* __restrict__ part) {
+    extern __shared__ __align__(16) unsigned char smem_rm[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float* v = (float*)smem_rm + (size_t)wv * NP;
+    const int c = blockIdx.y, r = T / 2, n = T * T;
+    const int ny = H - T + 1, nx = W - T + 1;
+    const int rows_per = (ny + gridDim.x - 1) / gridDim.x;
+    const int py0 = r + blockIdx.x * rows_per, py1 = min(r + ny, py0 + rows_per);
+    constexpr int PER = NP / 64;
+    double sum[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) sum[i] = 0.0;
+    const float* Rc = R + (size_t)c * H * W;
+    // windows of the slice, one per wavefront in turn
+    const int nwin = (py1 > py0) ? (py1 - py0) * nx : 0;
+    for (int wi = wv; wi < nwin; wi += 4) {
+        const int py = py0 + wi / nx, px = r + wi % nx;
+        for (int t = lane; t < NP; t += 64) {
+            float x = INFINITY;
+            if (t < n) {
+                const int dy = t / T, dx = t - dy * T;
+                x = Rc[(size_t)(py - r + dy) * W + (px - r + dx)];
+            }
+            v[t] = x;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int k = 2; k <= NP; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int pi = lane; pi < NP / 2; pi += 64) {
+                    const int i = ((pi & ~(jj - 1)) << 1) | (pi & (jj - 1));
+                    const int q = i | jj;
+                    const float a = v[i], b = v[q];
+                    const bool up = (i & k) == 0;
+                    const bool sw = up ? (a > b) : (a < b);
+                    v[i] = sw ? b : a;
+                    v[q] = sw ? a : b;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int rho = lane + 64 * i;
+            if (rho < n) sum[i] += (double)v[rho];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    double* dst = part + (((size_t)c * gridDim.x + blockIdx.x) * 4 + wv) * NP;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) dst[lane + 64 * i] = sum[i];
+}
+
+// Y[c][rho] = (sum over the slices and wavefronts, in order) / P_w, then the
+// reference histogram of Y quantised with the float32 edges (a value equal
+// to an edge goes to the upper bin), cumulated: cR [C][B] (one thread per
+// channel).
+__global__ void k_refmean_finish(const double* __restrict__ part, int C, int nparts, int NP, int n, double nw,
+                                 const float* __restrict__ edges, int B, int32_t* __restrict__ cR) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    int hist[64];
+    for (int i = 0; i < 64; ++i) hist[i] = 0;
+    for (int rho = 0; rho < n; ++rho) {
+        double s = 0.0;
+        for (int pw = 0; pw < nparts * 4; ++pw) s += part[((size_t)c * nparts * 4 + pw) * NP + rho];
+        const double y = s / nw;
+        int b = 0;
+        for (int e = 0; e < B - 1; ++e) b += (y >= (double)edges[(size_t)c * (B - 1) + e]) ? 1 : 0;
+        hist[b] += 1;
+    }
+    int acc = 0;
+    for (int i = 0; i < B; ++i) {
+        acc += hist[i];
+        cR[(size_t)c * B + i] = acc;
     }
 }
 
@@ -491,9 +624,10 @@ hipError_t launch_select(const float* vals, int C, long N, const long long* rank
 }
 
 hipError_t launch_refcount(const uint8_t* bins, int C, int H, int W, int T, int B,
-                           uint32_t* counts, hipStream_t st) {
+                           uint32_t* counts, hipStream_t st, int perbin) {
     RArgs a;
     a.bins = bins; a.C = C; a.H = H; a.W = W; a.T = T; a.B = B;
+    a.perbin = perbin;
     int Bp = 8;
     while (Bp < B) Bp <<= 1;
     a.Bp = Bp;
@@ -513,6 +647,50 @@ hipError_t launch_refcount(const uint8_t* bins, int C, int H, int W, int T, int 
     a.S = S; a.nsplit = nsplit;
     dim3 grid((W + a.Ws - 1) / a.Ws, (H + a.Hb - 1) / a.Hb, ((C + S - 1) / S) * nsplit);
     hipLaunchKernelGGL(k_refcount, grid, dim3(64), lds(S, nsplit), st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_refstat(const uint32_t* counts, int C, int B, int m, long long nw, int kind, double* cRw,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_refstat, dim3((C + 63) / 64), dim3(64), 0, st, counts, C, B, m, nw, kind, cRw);
+    return hipGetLastError();
+}
+
+size_t refmean_part_bytes(int C, int T, int* nparts, int* NP) {
+    int np2 = 64;
+    while (np2 < T * T) np2 <<= 1;
+    *NP = np2;
+    *nparts = 32;
+    return (size_t)C * 32 * 4 * np2 * sizeof(double);
+}
+
+hipError_t launch_refmean(const float* R, int C, int H, int W, int T, const float* edges, int B, double* part,
+                          int32_t* cR, hipStream_t st) {
+    int nparts = 0, NP = 0;
+    (void)refmean_part_bytes(C, T, &nparts, &NP);
+    const size_t lds = (size_t)4 * NP * sizeof(float);
+    dim3 grid(nparts, C);
+    auto go = [&](const void* k, auto launch) -> hipError_t {
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        launch();
+        return hipGetLastError();
+    };
+    hipError_t e = hipErrorInvalidValue;
+    switch (NP) {
+#define QFCA_RM(NPV) \
+        case NPV: e = go((const void*)k_refmean<NPV>, [&] { \
+            hipLaunchKernelGGL(k_refmean<NPV>, grid, dim3(256), lds, st, R, C, H, W, T, part); }); break;
+        QFCA_RM(64) QFCA_RM(128) QFCA_RM(256) QFCA_RM(512) QFCA_RM(1024) QFCA_RM(2048) QFCA_RM(4096)
+#undef QFCA_RM
+        default: break;
+    }
+    if (e != hipSuccess) return e;
+    const double nw = (double)(H - T + 1) * (double)(W - T + 1);
+    hipLaunchKernelGGL(k_refmean_finish, dim3((C + 63) / 64), dim3(64), 0, st, (const double*)part, C, nparts,
+                       NP, T * T, nw, edges, B, cR);
     return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@ struct KArgs {
     long long* asum;   // [H][W] sum over channels of A_c, fixed point (atomic adds)
     long long* w1sum;  // [H][W] sum over channels of W1_c, fixed point, or nullptr
     float* achan;      // [C][H][W] per-channel maps A_c (inspection output), or nullptr
+    const double* cRw; // generic kernel: [C][B] cumulative weights of a general reference, or nullptr
+    const float* wgt;  // generic kernel: [T] association weights for a finite sigma_p, or nullptr
     int* dbg_cp;       // inspection kernel only: [C][H][W][B] window cumulative counts cP_j
     int* dbg_I;        // inspection kernel only: [C][H][W][B] transport numerators I_j
 };
@@ -140,6 +142,8 @@ struct ScoreTables {
     double* delta = nullptr;  // [C]
     int Bp = 0;               // lanes per channel (power of two, >= 8)
     double fxs = 1.0;         // fixed-point scale of the channel sums (see KArgs)
+    double* cRw = nullptr;    // [C][B] general reference weights (column-walk kernel), or nullptr
+    float* wgt = nullptr;     // [T] association weights of a finite sigma_p (column-walk kernel), or nullptr
 };
 
 struct ScoreLaunch {
@@ -172,8 +176,20 @@ hipError_t launch_finish(const long long* asum, const long long* w1sum, double i
 
 // Reference fit: count table [C][B][m+1] (uint32, zeroed by the launcher) of
 // full-window cumulative counts, then the selection of cR.
+// perbin = 1 counts the windows' bin counts P(i) instead (for the
+// references taken after the quantisation).
 hipError_t launch_refcount(const uint8_t* bins, int C, int H, int W, int T, int B,
-                           uint32_t* counts, hipStream_t st);
+                           uint32_t* counts, hipStream_t st, int perbin = 0);
+// From the perbin count table: cumulative reference weights cRw [C][B] of the
+// bin-wise lower median (kind 0) or mean (kind 1) over the nw full windows.
+hipError_t launch_refstat(const uint32_t* counts, int C, int B, int m, long long nw, int kind, double* cRw,
+                          hipStream_t st);
+// Rank-wise mean of the sorted full windows of the residual R [C][H][W],
+// quantised with edges [C][B-1]: cumulative reference cR [C][B] (mass T*T).
+// part: device scratch of refmean_part_bytes(C, T, ...) bytes.
+size_t refmean_part_bytes(int C, int T, int* nparts, int* NP);
+hipError_t launch_refmean(const float* R, int C, int H, int W, int T, const float* edges, int B, double* part,
+                          int32_t* cR, hipStream_t st);
 hipError_t launch_refselect(const uint32_t* counts, int C, int B, int m, long long h,
                             int32_t* cR, hipStream_t st);
 

@@ -40,7 +40,7 @@ namespace {
 using namespace tiles;
 
 struct Lds {
-    size_t vc, ring, acc, psig, rcp, ering, total;
+    size_t vc, ring, acc, psig, rcp, ering, crw, wgt, total;
 };
 
 // WbA: allocated bin columns per row (>= Ws + 4r; the block-walk kernel
@@ -57,6 +57,8 @@ __host__ __device__ inline Lds lds_layout(int T, int Bp, int S, int Ws, int WbA)
     L.psig = off;  off += align16((size_t)S * (m + 1) * 8);
     L.rcp = off;   off += align16((size_t)(m + 1) * 4);
     L.ering = off; off += align16((size_t)T * 64 * 4);
+    L.crw = off;   off += align16((size_t)S * 64 * 8);  // general reference weights (B <= 64)
+    L.wgt = off;   off += align16((size_t)T * 4);       // association weights (finite sigma_p)
     L.total = off;
     return L;
 }
@@ -88,19 +90,30 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
     int2* psig = (int2*)(smem + L.psig);
     float* rcp = (float*)(smem + L.rcp);
     float* ering = (float*)(smem + L.ering);
+    double* crw = (double*)(smem + L.crw);  // [S][B] cumulative reference weights (general reference)
+    float* wgt = (float*)(smem + L.wgt);    // [T] association weights w(d), d = -r .. r
+    const bool gen = a.cRw != nullptr, gauss = a.wgt != nullptr;
+    const int B = a.B;
+    for (int t = lane; t < S * B; t += 64) {
+        const int ss = t / B, cc = cbase + ss;
+        crw[t] = (gen && cc < a.C) ? a.cRw[(size_t)cc * B + (t - ss * B)] : 0.0;
+    }
+    for (int t = lane; t < T; t += 64) wgt[t] = gauss ? a.wgt[t] : 1.f;
 
+    // the integer tables exist only for an integer reference of mass T*T (a
+    // general reference has none: nothing is read from them then)
     for (int t = lane; t < S * (m + 1); t += 64) {
         const int ss = t / (m + 1), tt = t - ss * (m + 1);
         const int cc = cbase + ss;
-        psig[t] = (cc < a.C) ? a.psig[(size_t)cc * (m + 1) + tt] : make_int2(0, 0);
+        psig[t] = (!gen && cc < a.C) ? a.psig[(size_t)cc * (m + 1) + tt] : make_int2(0, 0);
     }
-    for (int t = lane; t <= m; t += 64) rcp[t] = a.rcp[t];
+    for (int t = lane; t <= m; t += 64) rcp[t] = gen ? 0.f : a.rcp[t];
     for (int t = lane; t < WbMax * 16; t += 64) ((uint32_t*)vc)[t] = 0u;
     for (int t = lane; t < T * S * a.Ws; t += 64) acc[t] = 0.f;
     const int ci = cval ? c : 0;
-    const int crm1 = a.cRm1[ci * Bp + j];
-    const int dm1 = a.Dm1[ci * Bp + j];
-    const int crl = a.cRl[ci * Bp + j];
+    const int crm1 = gen ? 0 : a.cRm1[ci * Bp + j];
+    const int dm1 = gen ? 0 : a.Dm1[ci * Bp + j];
+    const int crl = gen ? 0 : a.cRl[ci * Bp + j];
     const bool binok = cval && (j < a.B);
     const bool w1ok = cval && (j < a.B - 1);
     const bool want_w1 = a.w1sum != nullptr;
@@ -144,7 +157,6 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
         const int ny = min(H - 1, y + r) - max(0, y - r) + 1;
         const bool own_row = (y >= y0) && (y < ye);
         int cP = 0;
-        double hs = 0.0;
         int slot = 0;
         for (int q = 0; q < Wb; ++q) {
             const int xl = xb0 + q;
@@ -165,7 +177,25 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
                 int cPm1 = lane_prev(cP);
                 if (j == 0) cPm1 = 0;
                 const int P = cP - cPm1;
-                if (n == m) {
+                if (gen) {
+                    // General reference (any nonnegative weights, mass M_R):
+                    // a = cP M_R, c_k = cR_k n, Phi(t) = sum_{k<B-1} (t - c_k)^+
+                    // summed directly in double precision.
+                    const double* cr = crw + sa * B;
+                    const double MR = cr[B - 1], dn = (double)n;
+                    const double au = (double)cPm1 * MR, av = (double)cP * MR;
+                    const double cm = (j >= 1 && j < B) ? dn * cr[j - 1] : 0.0;
+                    const double sc = fmin(fmax(cm, au), av);
+                    double pu = 0.0, pv = 0.0, ps = 0.0;
+                    for (int k = 0; k < B - 1; ++k) {
+                        const double ck = dn * cr[k];
+                        pu += fmax(au - ck, 0.0);
+                        pv += fmax(av - ck, 0.0);
+                        ps += fmax(sc - ck, 0.0);
+                    }
+                    const double I = (pu + pv - 2.0 * ps) + (double)j * (2.0 * sc - au - av);
+                    e = (binok && P > 0 && MR > 0.0) ? (float)(I / ((double)P * MR)) : 0.f;
+                } else if (n == m) {
                     // Interior window: equal masses, Phi(c P) = m Psi(cP).
                     const int psv = psig[sa * (m + 1) + cP].x;
                     int psu = lane_prev(psv);
@@ -194,23 +224,38 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
                     e = (binok && P > 0) ? (float)I * rcp[P] * inv_m : 0.f;
                 }
                 if (want_w1 && own_row && p >= x0 && p < xe) {
-                    int d = w1ok ? abs(cP * m - crl * n) : 0;
-                    for (int o = Bp >> 1; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
-                    if (cval && j == 0) {
-                        const double v = ((double)d * (a.delta[c] * a.fxs)) / ((double)n * (double)m);
-                        __hip_atomic_fetch_add(&a.w1sum[(size_t)y * W + p], __double2ll_rn(v), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+                    if (gen) {
+                        const double* cr = crw + sa * B;
+                        const double MR = cr[B - 1];
+                        double d = w1ok ? fabs((double)cP * MR - cr[j] * (double)n) : 0.0;
+                        for (int o = Bp >> 1; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+                        if (cval && j == 0 && MR > 0.0) {
+                            const double v = (d * (a.delta[c] * a.fxs)) / ((double)n * MR);
+                            __hip_atomic_fetch_add(&a.w1sum[(size_t)y * W + p], __double2ll_rn(v),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    } else {
+                        int d = w1ok ? abs(cP * m - crl * n) : 0;
+                        for (int o = Bp >> 1; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+                        if (cval && j == 0) {
+                            const double v = ((double)d * (a.delta[c] * a.fxs)) / ((double)n * (double)m);
+                            __hip_atomic_fetch_add(&a.w1sum[(size_t)y * W + p], __double2ll_rn(v),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
                     }
                 }
             }
             // Horizontal window sum of e over the T patch columns around
-            // output column p - r.
-            const float eold = (q >= T) ? ering[slot * 64 + lane] : 0.f;
+            // output column p - r (weighted by w(d) for a finite sigma_p),
+            // summed afresh in double from the oldest column to the newest,
+            // an order fixed by the image columns.
             ering[slot * 64 + lane] = e;
             slot = (slot + 1 == T) ? 0 : slot + 1;
-            hs += (double)e - (double)eold;
             const int xo = q - 4 * r;  // local output column
             if (xo >= 0) {
+                double hs = 0.0;
+                for (int i = 0, sl = slot; i < T; ++i, sl = (sl + 1 == T) ? 0 : sl + 1)
+                    hs += gauss ? (double)wgt[i] * (double)ering[sl * 64 + lane] : (double)ering[sl * 64 + lane];
                 const float hf = (float)hs;
                 for (int tc = 0; tc < T; tc += Bp) {
                     const int t = tc + j;
@@ -219,7 +264,10 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
                     int b = 0;
                     if (ok) b = ring[(size_t)(yo % T1) * S * WbMax + sa * WbMax + xo + 2 * r];
                     const float hv = __shfl(hf, sa * Bp + b, 64);
-                    if (ok) acc[((yo % T) * S + sa) * a.Ws + xo] += hv;
+                    if (ok) {
+                        float* ap = acc + ((yo % T) * S + sa) * a.Ws + xo;
+                        *ap = gauss ? __builtin_fmaf(wgt[t], hv, *ap) : *ap + hv;
+                    }
                 }
             }
         }
@@ -228,9 +276,17 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
         yo_lo = max(yo_lo, y0);
         yo_hi = min(yo_hi, ye - 1);
         __syncthreads();
+        // in-image weight of the windows along one axis around position x
+        // (their count for the box, the sum of w(d) for a finite sigma_p)
+        auto axis_weight = [&](int x, int len) -> double {
+            if (!gauss) return (double)(min(len - 1, x + r) - max(0, x - r) + 1);
+            double w = 0.0;
+            for (int i = 0; i < T; ++i)
+                if (x - r + i >= 0 && x - r + i < len) w += (double)wgt[i];
+            return w;
+        };
         for (int yo = yo_lo; yo <= yo_hi; ++yo) {
-            const int nyo = min(H - 1, yo + r) - max(0, yo - r) + 1;
-            const double rny = 1.0 / (double)nyo;
+            const double rny = 1.0 / axis_weight(yo, H);
             for (int t = lane; t < S * ws; t += 64) {
                 const int ss = t / ws, xo = t - ss * ws;
                 const int cc = cbase + ss;
@@ -239,8 +295,7 @@ __global__ __launch_bounds__(64) void k_score(KArgs a) {
                 *ap = 0.f;
                 if (cc < a.C) {
                     const int xg = x0 + xo;
-                    const int nxo = min(W - 1, xg + r) - max(0, xg - r) + 1;
-                    const double v = (((double)av * (a.delta[cc] * a.fxs)) * (1.0 / (double)nxo)) * rny;
+                    const double v = (((double)av * (a.delta[cc] * a.fxs)) * (1.0 / axis_weight(xg, W))) * rny;
                     if (a.achan) a.achan[((size_t)cc * H + yo) * W + xg] = (float)(v * (1.0 / a.fxs));
                     __hip_atomic_fetch_add(&a.asum[(size_t)yo * W + xg], __double2ll_rn(v), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
@@ -404,15 +459,18 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     a.r = L.T / 2;
     a.m = L.T * L.T;
     a.Hb = L.tile.Hb;
+    // a general reference or a finite sigma_p runs the column walk
+    const bool generic_only = L.tab.cRw != nullptr || L.tab.wgt != nullptr;
     const int variant =
-        (L.tile.variant == 1 && score_has_block_kernel(L.T) && L.tile.S <= score_block_max_S(L.T) &&
-         L.tile.Ws >= L.T) ? 1 : 0;
+        (!generic_only && L.tile.variant == 1 && score_has_block_kernel(L.T) &&
+         L.tile.S <= score_block_max_S(L.T) && L.tile.Ws >= L.T) ? 1 : 0;
     a.Ws = variant ? score_block_ws(L.T, L.tile.Ws) : L.tile.Ws;
     a.WbA = alloc_cols(L.T, a.Ws, variant);
     a.psig = L.tab.psig; a.cRm1 = L.tab.cRm1; a.Dm1 = L.tab.Dm1; a.cRl = L.tab.cRl;
     a.rcp = L.tab.rcp; a.delta = L.tab.delta;
     a.fxs = L.fxs; a.asum = L.asum; a.w1sum = L.w1sum; a.achan = L.achan;
     a.dbg_cp = L.dbg_cp; a.dbg_I = L.dbg_I;
+    a.cRw = L.tab.cRw; a.wgt = L.tab.wgt;
     const bool dbg = L.dbg_cp != nullptr;
     if (dbg && (!L.dbg_I || variant != 1)) return hipErrorInvalidValue;
     if (a.S < 1 || a.S * a.Bp > 64 || !a.asum) return hipErrorInvalidValue;

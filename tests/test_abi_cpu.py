@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_struct_layout():
     import ctypes
-    assert ctypes.sizeof(q.Params) == 36
+    assert ctypes.sizeof(q.Params) == 44
 
 
 @pytest.mark.parametrize("n", [1, 2, 5, 33, 128])
