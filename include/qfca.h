@@ -49,7 +49,11 @@ typedef enum {
 } qfca_status;
 
 enum { QFCA_PRE_NONE = 0,       /* plain QFCA: histogram the features as given */
-       QFCA_PRE_RESIDUAL = 1 }; /* QFCA+: histogram W - PCA^-1(PCA(W)), Sec. 3.3 */
+       QFCA_PRE_RESIDUAL = 1,   /* QFCA+: histogram W - PCA^-1(PCA(W)), Sec. 3.3 */
+       QFCA_PRE_COORDS = 2 };   /* histogram the k principal coordinates PCA(W) = V^T (W - mu)
+                                   and score each window by its 1-Wasserstein distance to the
+                                   reference (Sec. 3.1), box-averaged over the windows holding a
+                                   pixel, without per-bin association: bins are [k][H][W] */
 
 enum { QFCA_PREC_FP32 = 0,      /* projection in FP32 */
        QFCA_PREC_BF16 = 1 };    /* projection on BF16 MFMA, FP32 accumulate */
@@ -67,7 +71,8 @@ enum { QFCA_REF_MEDIAN_QUAN = 0,  /* rank-wise lower median of the sorted window
  * principal components (Sec. 4.5.2), sigma_p = infinity (box association),
  * sigma_s = 1 (Sec. 4.5.4), median -> quan reference (Sec. 4.5.3).
  *   C        channels, 1..2048
- *   k        principal components removed, 0..C-1 (ignored for PRE_NONE)
+ *   k        principal components removed, 0..min(64, C-1) (ignored for
+ *            PRE_NONE); for PRE_COORDS the histogrammed coordinates, 1..min(64, C)
  *   B        bins N of Sec. 3.1, 1..64
  *   T        patch side, odd, 1..63
  *   q_lo/hi  quantisation range as per-channel quantiles, 0 <= q_lo < q_hi <= 1
@@ -177,7 +182,9 @@ qfca_status qfca_model_set_reference(qfca_ctx ctx, qfca_model model, const doubl
  * bins: device [C][H][W] uint8 out, bins = #{m : r >= edge_m} with r the
  * residual (PRE_RESIDUAL) or the feature (PRE_NONE) in float32, compared
  * against the float32 edges (a value equal to an edge goes to the upper bin).
- * resid: optional device [C][H][W] float32 out (NULL to skip). */
+ * resid: optional device [C][H][W] float32 out (NULL to skip).
+ * For PRE_COORDS, bins and resid are [k][H][W]: the principal coordinates
+ * z = V^T (x - mu) (FP32 or BF16 MFMA with FP32 accumulation) and their bins. */
 qfca_status qfca_quantize(qfca_ctx ctx, qfca_model model, const float* X, int32_t H,
                           int32_t W, uint8_t* bins, float* resid);
 
@@ -201,6 +208,9 @@ qfca_status qfca_quantize(qfca_ctx ctx, qfca_model model, const float* X, int32_
  * sum), so it does not depend on the order of the channel groups; with the
  * block walk (T in 3..31) every output is bitwise independent of the tile.
  * Library scratch: 8 bytes per pixel (16 with w1).
+ * PRE_COORDS models (bins [k][H][W]): amap is the mean over the windows
+ * holding each pixel of the coordinate-mean window W1 map (w1), score its
+ * blur; achan must be NULL.
  * Requires a model with a reference (QFCA_E_STATE otherwise). */
 qfca_status qfca_score_map(qfca_ctx ctx, qfca_model model, const uint8_t* bins, int32_t H,
                            int32_t W, float* score, float* amap, float* w1, float* achan);

@@ -19,7 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqfca.so")
 
-QFCA_PRE_NONE, QFCA_PRE_RESIDUAL = 0, 1
+QFCA_PRE_NONE, QFCA_PRE_RESIDUAL, QFCA_PRE_COORDS = 0, 1, 2
 QFCA_PREC_FP32, QFCA_PREC_BF16 = 0, 1
 QFCA_REF_MEDIAN_QUAN, QFCA_REF_MEAN_QUAN, QFCA_REF_QUAN_MEDIAN, QFCA_REF_QUAN_MEAN = 0, 1, 2, 3
 
@@ -236,11 +236,18 @@ class Model:
         _check(lib().qfca_model_params(handle, ctypes.byref(p)))
         self.params = p
 
+    @property
+    def planes(self) -> int:
+        """Histogrammed planes: the k principal coordinates (PRE_COORDS) or the C channels."""
+        p = self.params
+        return p.k if p.preproc == QFCA_PRE_COORDS else p.C
+
     def read(self, field: str) -> np.ndarray:
         fid, dt = FIELDS[field]
         p = self.params
-        shape = {"mu": (p.C,), "V": (p.C, p.k), "edges": (p.C, max(p.B - 1, 0)), "delta": (p.C,),
-                 "cR": (p.C, p.B), "evals": (p.C,), "lo": (p.C,), "hi": (p.C,), "cRw": (p.C, p.B)}[field]
+        P = self.planes
+        shape = {"mu": (p.C,), "V": (p.C, p.k), "edges": (P, max(p.B - 1, 0)), "delta": (P,),
+                 "cR": (P, p.B), "evals": (p.C,), "lo": (P,), "hi": (P,), "cRw": (P, p.B)}[field]
         out = np.zeros(shape, dt)
         _check(lib().qfca_model_read(self.handle, fid, out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
         return out
@@ -285,13 +292,14 @@ def qfca_model_create(ctx: Context, params: Params, mu, V, edges, delta, cR=None
     mu, V, edges = host(mu, np.float32), host(V, np.float32), host(edges, np.float32)
     delta, cR = host(delta, np.float64), host(cR, np.int32)
     C, B, k = params.C, params.B, params.k
-    if edges is not None and edges.size != C * max(B - 1, 0):
-        raise ValueError("edges must be [C, B-1]")
-    if delta is None or delta.size != C:
-        raise ValueError("delta must be [C]")
-    if cR is not None and cR.size != C * B:
-        raise ValueError("cR must be [C, B]")
-    if params.preproc == QFCA_PRE_RESIDUAL and k > 0:
+    P = k if params.preproc == QFCA_PRE_COORDS else C  # histogrammed planes
+    if edges is not None and edges.size != P * max(B - 1, 0):
+        raise ValueError("edges must be [planes, B-1]")
+    if delta is None or delta.size != P:
+        raise ValueError("delta must be [planes]")
+    if cR is not None and cR.size != P * B:
+        raise ValueError("cR must be [planes, B]")
+    if params.preproc != QFCA_PRE_NONE and k > 0:
         if mu is None or V is None or mu.size != C or V.size != C * k:
             raise ValueError("mu [C] and V [C, k] are required")
 
@@ -333,10 +341,11 @@ def qfca_quantize(ctx: Context, model: Model, X, bins=None, resid=None, want_bin
     C, H, W = X.shape
     if C != model.params.C:
         raise ValueError("X.shape[0] != model C")
+    P = model.planes
     if bins is None and want_bins:
-        bins = torch.empty((C, H, W), dtype=torch.uint8, device=X.device)
+        bins = torch.empty((P, H, W), dtype=torch.uint8, device=X.device)
     if resid is True:
-        resid = torch.empty((C, H, W), dtype=torch.float32, device=X.device)
+        resid = torch.empty((P, H, W), dtype=torch.float32, device=X.device)
     elif resid is False:
         resid = None
     if bins is not None:
@@ -360,8 +369,8 @@ def qfca_score_map(ctx: Context, model: Model, bins, amap=False, w1=False, achan
     import torch
     bins = _dev_tensor(bins, torch.uint8, "bins", 3)
     C, H, W = bins.shape
-    if C != model.params.C:
-        raise ValueError("bins.shape[0] != model C")
+    if C != model.planes:
+        raise ValueError("bins.shape[0] != the model's histogrammed planes")
     dev = bins.device
     if out is None:
         out = ScoreMaps(torch.empty((H, W), dtype=torch.float32, device=dev))
@@ -412,8 +421,8 @@ def qfca_score_map_noalloc(ctx: Context, model: Model, bins, out: ScoreMaps):
     import torch
     bins = _dev_tensor(bins, torch.uint8, "bins", 3)
     C, H, W = bins.shape
-    if C != model.params.C:
-        raise ValueError("bins.shape[0] != model C")
+    if C != model.planes:
+        raise ValueError("bins.shape[0] != the model's histogrammed planes")
     _dev_tensor(out.score, torch.float32, "score", 2)
     for name, nd in (("amap", 2), ("w1", 2), ("achan", 3)):
         if getattr(out, name) is not None:

@@ -109,12 +109,14 @@ qfca_status check_params(const qfca_params* p) {
     if (p->C < 1 || p->C > 2048) return fail(QFCA_E_ARG, "C must be in [1, 2048]");
     if (p->B < 1 || p->B > 64) return fail(QFCA_E_UNSUPPORTED, "B must be in [1, 64]");
     if (p->T < 1 || p->T > 63 || (p->T % 2) == 0) return fail(QFCA_E_UNSUPPORTED, "T must be odd, 1..63");
-    if (p->preproc != QFCA_PRE_NONE && p->preproc != QFCA_PRE_RESIDUAL)
+    if (p->preproc != QFCA_PRE_NONE && p->preproc != QFCA_PRE_RESIDUAL && p->preproc != QFCA_PRE_COORDS)
         return fail(QFCA_E_ARG, "unknown preproc");
     if (p->proj_prec != QFCA_PREC_FP32 && p->proj_prec != QFCA_PREC_BF16)
         return fail(QFCA_E_ARG, "unknown proj_prec");
     if (p->preproc == QFCA_PRE_RESIDUAL && (p->k < 0 || p->k > 64 || p->k > p->C - 1))
         return fail(QFCA_E_UNSUPPORTED, "k must be in [0, min(64, C-1)]");
+    if (p->preproc == QFCA_PRE_COORDS && (p->k < 1 || p->k > 64 || p->k > p->C))
+        return fail(QFCA_E_UNSUPPORTED, "k must be in [1, min(64, C)] for principal coordinates");
     if (!(p->q_lo >= 0.f && p->q_lo < p->q_hi && p->q_hi <= 1.f))
         return fail(QFCA_E_ARG, "need 0 <= q_lo < q_hi <= 1");
     if (!(p->sigma_s >= 0.f && p->sigma_s <= 5.f)) return fail(QFCA_E_ARG, "sigma_s must be in [0, 5]");
@@ -123,6 +125,10 @@ qfca_status check_params(const qfca_params* p) {
         return fail(QFCA_E_ARG, "unknown reference");
     return QFCA_OK;
 }
+
+// Histogrammed planes of a model: the C channels (PRE_NONE, PRE_RESIDUAL) or
+// the k principal coordinates (PRE_COORDS).
+int planes(const qfca_params& p) { return p.preproc == QFCA_PRE_COORDS ? p.k : p.C; }
 
 qfca_status check_shape(int H, int W, int C) {
     if (H < 1 || W < 1) return fail(QFCA_E_SHAPE, "H and W must be >= 1");
@@ -181,7 +187,7 @@ int pow2_at_least(int v, int lo) {
 // Upload mu and V (float32, V padded to KP columns, plus a bf16 copy).
 qfca_status upload_projection(qfca_model m) {
     const int C = m->p.C, k = m->p.k;
-    const bool pre = m->p.preproc == QFCA_PRE_RESIDUAL;
+    const bool pre = m->p.preproc != QFCA_PRE_NONE;
     m->KP = (!pre || k == 0) ? 0 : (k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64);
     std::vector<float> muf(C, 0.f), Vf((size_t)C * std::max(m->KP, 1), 0.f);
     std::vector<uint16_t> Vb(Vf.size(), 0);
@@ -231,7 +237,7 @@ qfca_status upload_projection(qfca_model m) {
         // the persistent batch kernel is instantiated for fewer paddings: its
         // own copy of the tables when its padding differs
         int CMb = 0, KTb = 0;
-        if (batch_combo(C, k, m->p.proj_prec, &CMb, &KTb)) {
+        if (m->p.preproc == QFCA_PRE_RESIDUAL && batch_combo(C, k, m->p.proj_prec, &CMb, &KTb)) {
             if (CMb == CM && KTb == KT) {
                 m->d_V1b = m->d_V1;
                 m->d_V2b = m->d_V2;
@@ -247,7 +253,7 @@ qfca_status upload_projection(qfca_model m) {
 
 // Upload edges, lo, 1/delta and delta.
 qfca_status upload_quant(qfca_model m) {
-    const int C = m->p.C, B = m->p.B;
+    const int C = planes(m->p), B = m->p.B;
     std::vector<float> lof(C), invd(C);
     for (int c = 0; c < C; ++c) {
         lof[c] = (float)m->lo[c];
@@ -295,7 +301,7 @@ double fixed_point_scale(const std::vector<double>& delta, int B) {
 
 // Reference-dependent tables of the score kernel (see ScoreTables).
 qfca_status upload_tables(qfca_model m) {
-    const int C = m->p.C, B = m->p.B, T = m->p.T;
+    const int C = planes(m->p), B = m->p.B, T = m->p.T;
     const int mm = T * T, Bp = m->Bp;
     std::vector<int2> psig((size_t)C * (mm + 1));
     std::vector<int32_t> cRm1((size_t)C * Bp, 0), Dm1((size_t)C * Bp, 0), cRl((size_t)C * Bp, 0);
@@ -340,7 +346,7 @@ qfca_status upload_tables(qfca_model m) {
 // integer weights of mass T*T go to the integer tables, any other reference
 // to the column-walk kernel's double weights.
 qfca_status set_reference_weights(qfca_model m, const double* cRw) {
-    const int C = m->p.C, B = m->p.B, mm = m->p.T * m->p.T;
+    const int C = planes(m->p), B = m->p.B, mm = m->p.T * m->p.T;
     bool integral = true;
     for (size_t i = 0; i < (size_t)C * B && integral; ++i)
         integral = cRw[i] == floor(cRw[i]) && cRw[i] <= (double)mm;
@@ -456,12 +462,21 @@ ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
 qfca_status qfca::score_map_into(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int32_t H, int32_t W,
                                  float* score, float* amap, float* w1, float* achan, long long* asum,
                                  long long* w1sum, int* dbg_cp, int* dbg_I) {
+    const bool coords = m->p.preproc == QFCA_PRE_COORDS;
     ScoreLaunch L;
     L.dbg_cp = dbg_cp; L.dbg_I = dbg_I;
-    L.bins = bins; L.C = m->p.C; L.H = H; L.W = W; L.T = m->p.T; L.B = m->p.B;
+    L.bins = bins; L.C = planes(m->p); L.H = H; L.W = W; L.T = m->p.T; L.B = m->p.B;
     L.tab = m->tab;
     L.fxs = m->tab.fxs;
-    L.asum = asum; L.w1sum = w1 ? w1sum : nullptr; L.achan = achan;
+    if (coords) {
+        // principal coordinates: window W1 of every window into asum, its box
+        // mean into amap (or the w1sum buffer used as float scratch), blur
+        if (achan) return fail(QFCA_E_UNSUPPORTED, "principal-coordinate models have no per-channel maps");
+        if (!amap && !w1sum) return fail(QFCA_E_ARG, "internal: no scratch for the box-mean map");
+        L.asum = asum; L.w1sum = asum; L.achan = nullptr; L.w1only = true;
+    } else {
+        L.asum = asum; L.w1sum = w1 ? w1sum : nullptr; L.achan = achan;
+    }
     if (ctx->tile_override.Ws > 0) {
         L.tile = ctx->tile_override;
         if (L.tile.S * m->Bp > 64) return fail(QFCA_E_UNSUPPORTED, "S * lanes per channel exceeds 64");
@@ -471,7 +486,7 @@ qfca_status qfca::score_map_into(qfca_ctx ctx, qfca_model m, const uint8_t* bins
         if (score_lds_bytes(m->p.T, m->Bp, L.tile.S, L.tile.Ws, L.tile.variant) > 160 * 1024)
             return fail(QFCA_E_UNSUPPORTED, "tile does not fit in LDS");
     } else {
-        L.tile = choose_tile(ctx, m->p.C, H, W, m->p.T, m->p.B, m->Bp);
+        L.tile = choose_tile(ctx, L.C, H, W, m->p.T, m->p.B, m->Bp);
     }
     if (dbg_cp && L.tile.variant != 1)
         return fail(QFCA_E_UNSUPPORTED, "window inspection needs the block walk (T in 3..31, S within its limit)");
@@ -481,8 +496,12 @@ qfca_status qfca::score_map_into(qfca_ctx ctx, qfca_model m, const uint8_t* bins
     }
     {
         KernelTimer kt(ctx, K_FINISH);
-        HIP_TRY(launch_finish(asum, L.w1sum, 1.0 / (m->tab.fxs * (double)m->p.C), H, W, m->p.sigma_s, amap, w1,
-                              score, ctx->stream));
+        const double inv = 1.0 / (m->tab.fxs * (double)L.C);
+        if (coords)
+            HIP_TRY(launch_finish_w1(asum, inv, H, W, m->p.T, m->p.sigma_s, amap ? amap : (float*)w1sum, w1, score,
+                                     ctx->stream));
+        else
+            HIP_TRY(launch_finish(asum, L.w1sum, inv, H, W, m->p.sigma_s, amap, w1, score, ctx->stream));
     }
     return QFCA_OK;
 }
@@ -637,7 +656,7 @@ qfca_status qfca_model_params(qfca_model m, qfca_params* out) {
 
 qfca_status qfca_model_read(qfca_model m, int32_t field, void* dst, size_t bytes) {
     if (!m || !dst) return fail(QFCA_E_ARG, "NULL argument");
-    const int C = m->p.C, k = m->p.k, B = m->p.B;
+    const int C = m->p.C, k = m->p.k, B = m->p.B, P = planes(m->p);
     std::vector<float> tmp;
     const void* src = nullptr;
     size_t need = 0;
@@ -649,16 +668,16 @@ qfca_status qfca_model_read(qfca_model m, int32_t field, void* dst, size_t bytes
             src = tmp.data(); need = (size_t)C * 4; break;
         case 1:
             tmp.resize((size_t)C * k);
-            ok = m->p.preproc == QFCA_PRE_RESIDUAL && m->V.size() == tmp.size();
+            ok = m->p.preproc != QFCA_PRE_NONE && m->V.size() == tmp.size();
             for (size_t i = 0; ok && i < tmp.size(); ++i) tmp[i] = (float)m->V[i];
             src = tmp.data(); need = tmp.size() * 4; break;
-        case 2: src = m->edges.data(); need = (size_t)C * (B - 1) * 4; break;
-        case 3: src = m->delta.data(); need = (size_t)C * 8; break;
-        case 4: ok = m->has_ref && !m->ref_general; src = m->cR.data(); need = (size_t)C * B * 4; break;
-        case 8: ok = m->has_ref; src = m->cRw.data(); need = (size_t)C * B * 8; break;
+        case 2: src = m->edges.data(); need = (size_t)P * (B - 1) * 4; break;
+        case 3: src = m->delta.data(); need = (size_t)P * 8; break;
+        case 4: ok = m->has_ref && !m->ref_general; src = m->cR.data(); need = (size_t)P * B * 4; break;
+        case 8: ok = m->has_ref; src = m->cRw.data(); need = (size_t)P * B * 8; break;
         case 5: ok = m->has_evals; src = m->evals.data(); need = (size_t)C * 8; break;
-        case 6: ok = m->has_lohi; src = m->lo.data(); need = (size_t)C * 8; break;
-        case 7: ok = m->has_lohi; src = m->hi.data(); need = (size_t)C * 8; break;
+        case 6: ok = m->has_lohi; src = m->lo.data(); need = (size_t)P * 8; break;
+        case 7: ok = m->has_lohi; src = m->hi.data(); need = (size_t)P * 8; break;
         default: return fail(QFCA_E_ARG, "unknown field");
     }
     if (!ok) return fail(QFCA_E_STATE, "field not set on this model");
@@ -681,18 +700,18 @@ qfca_status build_model(qfca_ctx ctx, const qfca_params* p, const double* mu, co
     *out = nullptr;
     qfca_status st = check_params(p);
     if (st != QFCA_OK) return st;
-    const int C = p->C, k = p->k, B = p->B, T = p->T;
-    const bool pre = p->preproc == QFCA_PRE_RESIDUAL;
+    const int C = p->C, k = p->k, B = p->B, T = p->T, P = planes(*p);
+    const bool pre = p->preproc != QFCA_PRE_NONE;
     if ((B > 1 && !edges) || !delta) return fail(QFCA_E_ARG, "edges and delta are required");
     if (pre && k > 0 && (!mu || !V)) return fail(QFCA_E_ARG, "mu and V are required for k > 0");
-    for (int c = 0; c < C; ++c) {
+    for (int c = 0; c < P; ++c) {
         if (!(delta[c] >= 0.0) || !isfinite(delta[c])) return fail(QFCA_E_ARG, "delta must be finite, >= 0");
         for (int i = 1; i + 1 < B; ++i)
             if (!(edges[(size_t)c * (B - 1) + i] >= edges[(size_t)c * (B - 1) + i - 1]))
                 return fail(QFCA_E_ARG, "edges must be nondecreasing per channel");
     }
     if (cR) {
-        for (int c = 0; c < C; ++c) {
+        for (int c = 0; c < P; ++c) {
             if (cR[(size_t)c * B + B - 1] != T * T) return fail(QFCA_E_ARG, "cR[c][B-1] must equal T*T");
             for (int i = 0; i < B; ++i) {
                 const int32_t v = cR[(size_t)c * B + i];
@@ -711,17 +730,17 @@ qfca_status build_model(qfca_ctx ctx, const qfca_params* p, const double* mu, co
         m->V.assign((size_t)C * k, 0.0);
         for (size_t i = 0; i < m->V.size(); ++i) m->V[i] = V[i];
     }
-    if (B > 1) m->edges.assign(edges, edges + (size_t)C * (B - 1));
-    m->delta.assign(delta, delta + C);
-    m->lo.assign(C, 0.0);
-    for (int c = 0; c < C; ++c)
+    if (B > 1) m->edges.assign(edges, edges + (size_t)P * (B - 1));
+    m->delta.assign(delta, delta + P);
+    m->lo.assign(P, 0.0);
+    for (int c = 0; c < P; ++c)
         m->lo[c] = lo ? lo[c]
                       : ((B > 1 && m->delta[c] > 0.0) ? (double)m->edges[(size_t)c * (B - 1)] - m->delta[c] : 0.0);
     if ((st = upload_projection(m.get())) != QFCA_OK) return st;
     if ((st = upload_quant(m.get())) != QFCA_OK) return st;
     if ((st = upload_assoc_weights(m.get())) != QFCA_OK) return st;
     if (cR) {
-        m->cR.assign(cR, cR + (size_t)C * B);
+        m->cR.assign(cR, cR + (size_t)P * B);
         if ((st = upload_tables(m.get())) != QFCA_OK) return st;
     }
     *out = m.release();
@@ -750,14 +769,15 @@ struct ModelBlob {
 ModelBlob blob_sizes(const qfca_params& p, uint32_t flags, uint32_t version) {
     ModelBlob z;
     const size_t C = (size_t)p.C;
+    const size_t P = (size_t)planes(p);
     z.mu = C * 8;
-    z.V = p.preproc == QFCA_PRE_RESIDUAL ? C * (size_t)p.k * 8 : 0;
-    z.edges = C * (size_t)(p.B > 1 ? p.B - 1 : 0) * 4;
-    z.delta = C * 8;
-    z.cR = (flags & 1u) ? C * (size_t)p.B * 4 : 0;
+    z.V = p.preproc != QFCA_PRE_NONE ? C * (size_t)p.k * 8 : 0;
+    z.edges = P * (size_t)(p.B > 1 ? p.B - 1 : 0) * 4;
+    z.delta = P * 8;
+    z.cR = (flags & 1u) ? P * (size_t)p.B * 4 : 0;
     z.evals = (flags & 2u) ? C * 8 : 0;
-    z.lohi = (flags & 4u) ? C * 16 : 0;
-    z.cRw = (flags & 8u) ? C * (size_t)p.B * 8 : 0;
+    z.lohi = (flags & 4u) ? P * 16 : 0;
+    z.cRw = (flags & 8u) ? P * (size_t)p.B * 8 : 0;
     z.total = model_header(version) + z.mu + z.V + z.edges + z.delta + z.cR + z.evals + z.lohi + z.cRw;
     return z;
 }
@@ -872,7 +892,7 @@ qfca_status qfca_model_import(qfca_ctx ctx, const void* host_buf, size_t bytes, 
         return q;
     };
     const size_t C = (size_t)p.C;
-    std::vector<double> mu(C), V(z.V / 8), delta(C), evals(z.evals / 8), lo(z.lohi / 16), hi(z.lohi / 16);
+    std::vector<double> mu(C), V(z.V / 8), delta(z.delta / 8), evals(z.evals / 8), lo(z.lohi / 16), hi(z.lohi / 16);
     std::vector<float> edges(z.edges / 4);
     std::vector<int32_t> cR(z.cR / 4);
     memcpy(mu.data(), take(z.mu), z.mu);
@@ -928,7 +948,12 @@ qfca_status qfca_quantize(qfca_ctx ctx, qfca_model m, const float* X, int32_t H,
     L.inv_delta = m->d_invd; L.fastd = m->d_fastd; L.bins = bins; L.resid = resid;
     L.V1 = m->d_V1; L.V2 = m->d_V2;
     KernelTimer kt(ctx, K_PROJ);
-    HIP_TRY(launch_proj(L, ctx->stream));
+    if (m->p.preproc == QFCA_PRE_COORDS) {
+        if (!m->d_V1) return fail(QFCA_E_UNSUPPORTED, "principal coordinates need C <= 512");
+        HIP_TRY(launch_coords(L, ctx->stream));
+    } else {
+        HIP_TRY(launch_proj(L, ctx->stream));
+    }
     return QFCA_OK;
 }
 
@@ -936,7 +961,7 @@ qfca_status qfca_fit_reference(qfca_ctx ctx, qfca_model m, const uint8_t* bins, 
     if (!ctx || !m || !bins) return fail(QFCA_E_ARG, "NULL argument");
     qfca_status st = check_shape(H, W, m->p.C);
     if (st != QFCA_OK) return st;
-    const int C = m->p.C, B = m->p.B, T = m->p.T, mm = T * T;
+    const int C = planes(m->p), B = m->p.B, T = m->p.T, mm = T * T;
     if (H < T || W < T) return fail(QFCA_E_SHAPE, "the reference needs H, W >= T");
     if (m->p.reference == QFCA_REF_MEAN_QUAN)
         return fail(QFCA_E_UNSUPPORTED, "the mean -> quan reference needs the features: use qfca_fit_pca");
@@ -969,7 +994,7 @@ qfca_status qfca_fit_reference(qfca_ctx ctx, qfca_model m, const uint8_t* bins, 
 qfca_status qfca_model_set_reference(qfca_ctx ctx, qfca_model m, const double* cRw) {
     if (!ctx || !m || !cRw) return fail(QFCA_E_ARG, "NULL argument");
     if (m->device != ctx->device) return fail(QFCA_E_ARG, "model and context are on different devices");
-    const int C = m->p.C, B = m->p.B;
+    const int C = planes(m->p), B = m->p.B;
     for (int c = 0; c < C; ++c)
         for (int i = 0; i < B; ++i) {
             const double v = cRw[(size_t)c * B + i];
@@ -989,9 +1014,10 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
     if ((st = check_shape(H, W, p->C)) != QFCA_OK) return st;
     if (H < p->T || W < p->T) return fail(QFCA_E_SHAPE, "the fit needs H, W >= T");
     HIP_TRY(hipSetDevice(ctx->device));
-    const int C = p->C, k = p->k, B = p->B;
+    const int C = p->C, k = p->k, B = p->B, P = planes(*p);
     const long N = (long)H * W;
-    const bool pre = p->preproc == QFCA_PRE_RESIDUAL;
+    const bool pre = p->preproc != QFCA_PRE_NONE;
+    const bool coords = p->preproc == QFCA_PRE_COORDS;
     std::unique_ptr<qfca_model_s> m(new_model(ctx, p));
     if (!m) return fail(QFCA_E_NOMEM, "model allocation failed");
     hipStream_t s = ctx->stream;
@@ -1033,7 +1059,12 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
         L.edges = nullptr; L.lo = nullptr; L.inv_delta = nullptr; L.fastd = nullptr; L.bins = nullptr;
         L.resid = resid;
         L.V1 = m->d_V1; L.V2 = m->d_V2;
-        HIP_TRY(launch_proj(L, s));
+        if (coords) {
+            if (!m->d_V1) return fail(QFCA_E_UNSUPPORTED, "principal coordinates need C <= 512");
+            HIP_TRY(launch_coords(L, s));  // the k coordinates z into resid [k][N]
+        } else {
+            HIP_TRY(launch_proj(L, s));
+        }
     }
     const double hq[2] = {(double)(N - 1) * (double)p->q_lo, (double)(N - 1) * (double)p->q_hi};
     long long ranks[4];
@@ -1045,17 +1076,17 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
     long long* dranks = nullptr;
     float* dsel = nullptr;
     HIP_TRY(scratch(ctx, SL_RANKS, sizeof(ranks), &dranks));
-    HIP_TRY(scratch(ctx, SL_SEL, (size_t)C * 4 * 4, &dsel));
+    HIP_TRY(scratch(ctx, SL_SEL, (size_t)P * 4 * 4, &dsel));
     HIP_TRY(hipMemcpyAsync(dranks, ranks, sizeof(ranks), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_select(resid, C, N, dranks, 4, dsel, s));
-    std::vector<float> sel((size_t)C * 4);
+    HIP_TRY(launch_select(resid, P, N, dranks, 4, dsel, s));
+    std::vector<float> sel((size_t)P * 4);
     HIP_TRY(hipMemcpyAsync(sel.data(), dsel, sel.size() * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    m->lo.assign(C, 0.0);
-    m->hi.assign(C, 0.0);
-    m->delta.assign(C, 0.0);
-    m->edges.assign((size_t)C * (B - 1), 0.f);
-    for (int c = 0; c < C; ++c) {
+    m->lo.assign(P, 0.0);
+    m->hi.assign(P, 0.0);
+    m->delta.assign(P, 0.0);
+    m->edges.assign((size_t)P * (B - 1), 0.f);
+    for (int c = 0; c < P; ++c) {
         double qv[2];
         for (int q = 0; q < 2; ++q) {
             const double a = sel[(size_t)c * 4 + 2 * q], b = sel[(size_t)c * 4 + 2 * q + 1];
@@ -1081,18 +1112,18 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
 
     // 4. bins with the final edges, then the reference
     uint8_t* bins = nullptr;
-    HIP_TRY(scratch(ctx, SL_BINS, (size_t)C * N, &bins));
+    HIP_TRY(scratch(ctx, SL_BINS, (size_t)P * N, &bins));
     if ((st = qfca_quantize(ctx, m.get(), X, H, W, bins, nullptr)) != QFCA_OK) return st;
     if (p->reference == QFCA_REF_MEAN_QUAN) {
         // rank-wise mean of the sorted full windows of the residual, quantised
         int nparts = 0, NP = 0;
         double* part = nullptr;
         int32_t* dcR = nullptr;
-        HIP_TRY(scratch(ctx, SL_RMPART, refmean_part_bytes(C, p->T, &nparts, &NP), &part));
-        HIP_TRY(scratch(ctx, SL_CR, (size_t)C * B * 4, &dcR));
-        HIP_TRY(launch_refmean(resid, C, H, W, p->T, m->d_edges, B, part, dcR, s));
-        m->cR.assign((size_t)C * B, 0);
-        HIP_TRY(hipMemcpyAsync(m->cR.data(), dcR, (size_t)C * B * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(scratch(ctx, SL_RMPART, refmean_part_bytes(P, p->T, &nparts, &NP), &part));
+        HIP_TRY(scratch(ctx, SL_CR, (size_t)P * B * 4, &dcR));
+        HIP_TRY(launch_refmean(resid, P, H, W, p->T, m->d_edges, B, part, dcR, s));
+        m->cR.assign((size_t)P * B, 0);
+        HIP_TRY(hipMemcpyAsync(m->cR.data(), dcR, (size_t)P * B * 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if ((st = upload_tables(m.get())) != QFCA_OK) return st;
     } else if ((st = qfca_fit_reference(ctx, m.get(), bins, H, W)) != QFCA_OK) {
@@ -1109,7 +1140,8 @@ qfca_status qfca_inspect_windows(qfca_ctx ctx, qfca_model m, const uint8_t* bins
     if (st != QFCA_OK) return st;
     if (!m->has_ref) return fail(QFCA_E_STATE, "model has no reference");
     if (m->device != ctx->device) return fail(QFCA_E_ARG, "model and context are on different devices");
-    if (!score_has_block_kernel(m->p.T) || m->ref_general || !std::isinf(m->p.sigma_p))
+    if (!score_has_block_kernel(m->p.T) || m->ref_general || !std::isinf(m->p.sigma_p) ||
+        m->p.preproc == QFCA_PRE_COORDS)
         return fail(QFCA_E_UNSUPPORTED, "window inspection needs T in 3..31, sigma_p = INFINITY and an integer "
                                         "reference of mass T*T");
     HIP_TRY(hipSetDevice(ctx->device));
@@ -1129,7 +1161,7 @@ qfca_status qfca_score_map(qfca_ctx ctx, qfca_model m, const uint8_t* bins, int3
     long long* asum = nullptr;
     long long* w1sum = nullptr;
     HIP_TRY(scratch(ctx, SL_ASUM, N * 8, &asum));
-    if (w1) HIP_TRY(scratch(ctx, SL_W1SUM, N * 8, &w1sum));
+    if (w1 || (m->p.preproc == QFCA_PRE_COORDS && !amap)) HIP_TRY(scratch(ctx, SL_W1SUM, N * 8, &w1sum));
     return score_map_into(ctx, m, bins, H, W, score, amap, w1, achan, asum, w1sum);
 }
 

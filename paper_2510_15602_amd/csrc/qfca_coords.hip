@@ -1,0 +1,258 @@
+// Principal coordinates and their bins for gfx950: z = V^T (x - mu) (the
+// "PCA(W)" of Sec. 3.3 taken as the histogrammed quantity), then
+// bin = #{m : z_j >= edge_{j,m}} per coordinate j.  The variant of the method
+// that histograms the k coordinates instead of the C residual channels and
+// scores each window by its 1-Wasserstein distance to the reference.
+//
+// The product is the first GEMM of the residual projection (qfca_proj.hip)
+// alone: one block of four wavefronts owns a 16-pixel tile, wave w forms the
+// partial Z of its channel quarter on MFMA (FP32 v_mfma_f32_16x16x4f32 or
+// BF16 v_mfma_f32_16x16x32_bf16 with FP32 accumulation), the partials are
+// added through LDS in a fixed order, and wave w < KT then quantises the 16
+// components 16 w .. 16 w + 15 of the 16 pixels.  The grid is persistent
+// (contiguous runs of tiles per block), the operand table sits in LDS, and
+// the next tile's features are loaded while the current one is computed.
+// The only HBM traffic is the features in (4 C bytes per pixel) and k bytes
+// of bins out (plus 4 k bytes of coordinates when they are asked for).
+#include <algorithm>
+#include <atomic>
+
+#include "qfca_internal.h"
+#include "qfca_tiles.h"
+
+namespace qfca {
+namespace {
+using namespace tiles;
+
+constexpr size_t CO_LDS_MAX = 160 * 1024;
+constexpr size_t CO_LDS_TWO_BLOCKS = 80 * 1024;
+
+// LDS: mu [CMAX]; lo, 1/delta, margin [64] each; Z partials [4][KT][4][64];
+// bin staging [64][16] bytes; the operand table.
+__host__ __device__ inline size_t co_lds(int CMAX, int KT, int elt) {
+    return (size_t)CMAX * 4 + 3 * 64 * 4 + (size_t)4 * KT * 4 * 64 * 4 + 64 * 16 + (size_t)CMAX * KT * 16 * elt;
+}
+
+// Quantises the 16 components of wave w (< KT) for the tile's 16 pixels
+// from the reduced Z (register v of lane (g, n): component 16 w + 4 g + v,
+// pixel n) and stores the bins (and the coordinates when a.resid is set).
+__device__ __forceinline__ void co_emit(const MArgs& a, int tile, int w, int lane, const floatx4& zw,
+                                        const float* slo, const float* sid, const float* sfd, uint8_t* stg) {
+    const int g = lane >> 4, n = lane & 15;
+    const int px = tile * 16 + n;
+    int cs[4];
+    float rv[4];
+    bool valid[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int j = 16 * w + 4 * g + v;
+        cs[v] = j;
+        rv[v] = zw[v];
+        valid[v] = px < a.N && j < a.k;
+    }
+    emit_values<4>(a, px, cs, rv, valid, slo, sid, sfd, a.edges, stg);
+}
+
+// Bins of the tile from the staging area, one 16-byte row per component.
+__device__ __forceinline__ void co_store(const MArgs& a, int tile, const uint8_t* stg) {
+    const int p0 = tile * 16;
+    const int j = threadIdx.x;
+    if (j >= a.k) return;
+    if (p0 + 16 <= a.N && (a.N & 15) == 0 && (((uintptr_t)a.bins & 15) == 0)) {
+        *(uint4*)(a.bins + (size_t)j * a.N + p0) = *(const uint4*)(stg + j * 16);
+    } else {
+        uint8_t* dst = a.bins + (size_t)j * a.N + p0;
+        for (int q = 0; q < 16 && p0 + q < a.N; ++q) dst[q] = stg[j * 16 + q];
+    }
+}
+
+template <int CMAX, int KT, bool BF>
+__device__ __forceinline__ void coords_body(const MArgs& a) {
+    constexpr int ELT = BF ? 2 : 4;
+    constexpr int VSZ = CMAX * KT * 16;  // table elements
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float* smu = (float*)lds_raw;
+    float* slo = smu + CMAX;
+    float* sid = slo + 64;
+    float* sfd = sid + 64;
+    float* zp = sfd + 64;  // [4 waves][KT][4][64]
+    uint8_t* stg = (uint8_t*)(zp + 4 * KT * 4 * 64);
+    void* stab = stg + 64 * 16;
+    for (int i = threadIdx.x; i < CMAX; i += blockDim.x) {
+        const float vm = i < a.C ? a.mu[i] : 0.f;
+        smu[i] = vm;
+    }
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+        const bool ok = i < a.k;
+        const float vl = ok && a.lo ? a.lo[i] : 0.f;
+        const float vi = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
+        const float vf = ok && a.fastd ? a.fastd[i] : 1.f;
+        slo[i] = vl;
+        sid[i] = vi;
+        sfd[i] = vf;
+    }
+    {
+        const uint4* src = (const uint4*)a.V1;
+        uint4* dst = (uint4*)stab;
+        constexpr int NU = VSZ * ELT / 16;
+        for (int u = threadIdx.x; u < NU; u += blockDim.x) dst[u] = src[u];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int per = (a.ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    int tile = blockIdx.x * per;
+    const int tend = min(a.ntiles, tile + per);
+    if constexpr (BF) {
+        constexpr int NSW = CMAX / 128;
+        float x[NSW][8];
+        if (tile < tend) proj_load_bf16<CMAX>(a, tile, w, lane, x);
+        for (; tile < tend; ++tile) {
+            int lt = lane, wt = w;
+            asm volatile("" : "+v"(lt), "+s"(wt));
+            float xn[NSW][8];
+            const int nt = tile + 1;
+            proj_load_bf16<CMAX>(a, nt < tend ? nt : tend - 1, wt, lt, xn);
+            const bf16x8* V1 = opaque_lds((const bf16x8*)stab);
+            const int g = lt >> 4, n = lt & 15;
+            floatx4 z[KT];
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) z[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < NSW; ++i) {
+                const int s = wt * NSW + i;
+                bf16x8 bv;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) bv[t] = (__bf16)(x[i][t] - smu[32 * s + 8 * g + t]);
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt)
+                    z[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V1[((s * KT + kt) * 4 + g) * 16 + n], bv,
+                                                                    z[kt], 0, 0, 0);
+            }
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) zp[((wt * KT + kt) * 4 + v) * 64 + lt] = z[kt][v];
+            block_sync_lds();
+            if (wt < KT) {
+                floatx4 zw;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float acc = zp[((0 * KT + wt) * 4 + v) * 64 + lt];
+                    acc += zp[((1 * KT + wt) * 4 + v) * 64 + lt];
+                    acc += zp[((2 * KT + wt) * 4 + v) * 64 + lt];
+                    acc += zp[((3 * KT + wt) * 4 + v) * 64 + lt];
+                    zw[v] = acc;
+                }
+                co_emit(a, tile, wt, lt, zw, opaque_lds(slo), opaque_lds(sid), opaque_lds(sfd), stg);
+            }
+            block_sync_lds();
+            if (a.bins) co_store(a, tile, stg);
+#pragma unroll
+            for (int i = 0; i < NSW; ++i)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) x[i][t] = xn[i][t];
+        }
+    } else {
+        constexpr int NSW = CMAX / 16;
+        float x[NSW];
+        if (tile < tend) proj_load_f32<CMAX>(a, tile, w, lane, x);
+        for (; tile < tend; ++tile) {
+            int lt = lane, wt = w;
+            asm volatile("" : "+v"(lt), "+s"(wt));
+            float xn[NSW];
+            const int nt = tile + 1;
+            proj_load_f32<CMAX>(a, nt < tend ? nt : tend - 1, wt, lt, xn);
+            const float* V1 = opaque_lds((const float*)stab);
+            const int g = lt >> 4, n = lt & 15;
+            floatx4 z[KT];
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) z[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < NSW; ++i) {
+                const int s = wt * NSW + i;
+                const float d = x[i] - smu[4 * s + g];
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt)
+                    z[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(V1[((s * KT + kt) * 4 + g) * 16 + n], d, z[kt], 0,
+                                                                 0, 0);
+                if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) zp[((wt * KT + kt) * 4 + v) * 64 + lt] = z[kt][v];
+            block_sync_lds();
+            if (wt < KT) {
+                floatx4 zw;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float acc = zp[((0 * KT + wt) * 4 + v) * 64 + lt];
+                    acc += zp[((1 * KT + wt) * 4 + v) * 64 + lt];
+                    acc += zp[((2 * KT + wt) * 4 + v) * 64 + lt];
+                    acc += zp[((3 * KT + wt) * 4 + v) * 64 + lt];
+                    zw[v] = acc;
+                }
+                co_emit(a, tile, wt, lt, zw, opaque_lds(slo), opaque_lds(sid), opaque_lds(sfd), stg);
+            }
+            block_sync_lds();
+            if (a.bins) co_store(a, tile, stg);
+#pragma unroll
+            for (int i = 0; i < NSW; ++i) x[i] = xn[i];
+        }
+    }
+}
+
+template <int CMAX, int KT, bool BF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_coords(MArgs a) {
+    coords_body<CMAX, KT, BF>(a);
+}
+
+}  // namespace
+
+hipError_t launch_coords(const ProjLaunch& L, hipStream_t st) {
+    const int CM = mfma_cmax(L.C, L.prec), KT = mfma_kt(L.k, L.prec);
+    if (!CM || !KT || !L.V1 || L.k > 64) return hipErrorInvalidValue;
+    MArgs a;
+    a.X = L.X; a.C = L.C; a.N = L.N; a.k = L.k; a.B = L.B;
+    a.mu = L.mu; a.V1 = L.V1; a.V2 = nullptr;
+    a.edges = L.edges; a.lo = L.lo; a.inv_delta = L.inv_delta; a.fastd = L.fastd;
+    a.bins = L.bins; a.resid = L.resid;
+    a.ntiles = (L.N + 15) / 16;
+    const bool bf = L.prec == QFCA_PREC_BF16;
+    const size_t lds = co_lds(CM, KT, bf ? 2 : 4);
+    if (lds > CO_LDS_MAX) return hipErrorInvalidValue;
+    static std::atomic<int> ncu_cache[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int ncu = ncu_cache[dev & 63].load(std::memory_order_relaxed);
+    if (!ncu) {
+        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        ncu_cache[dev & 63].store(ncu, std::memory_order_relaxed);
+    }
+    const int per_cu = lds <= CO_LDS_TWO_BLOCKS ? 2 : 1;
+    const int grid = std::max(1, std::min(a.ntiles, ncu * per_cu));
+    auto go = [&](const void* k, auto launch) -> hipError_t {
+        if (lds > 65536) {
+            hipError_t e2 = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e2 != hipSuccess) return e2;
+        }
+        launch();
+        return hipGetLastError();
+    };
+#define QFCA_CO(CMV, KTV, BFV)                                                                   \
+    if (CM == CMV && KT == KTV && bf == BFV)                                                     \
+        return go((const void*)k_coords<CMV, KTV, BFV>,                                          \
+                  [&] { hipLaunchKernelGGL((k_coords<CMV, KTV, BFV>), dim3(grid), dim3(256), lds, st, a); });
+    QFCA_CO(64, 1, false) QFCA_CO(64, 2, false) QFCA_CO(64, 4, false)
+    QFCA_CO(128, 1, false) QFCA_CO(128, 2, false) QFCA_CO(128, 4, false)
+    QFCA_CO(256, 1, false) QFCA_CO(256, 2, false) QFCA_CO(256, 4, false)
+    QFCA_CO(512, 1, false) QFCA_CO(512, 2, false) QFCA_CO(512, 4, false)
+    QFCA_CO(128, 2, true) QFCA_CO(128, 4, true) QFCA_CO(256, 2, true) QFCA_CO(256, 4, true)
+    QFCA_CO(512, 2, true) QFCA_CO(512, 4, true)
+#undef QFCA_CO
+    return hipErrorInvalidValue;
+}
+
+}  // namespace qfca

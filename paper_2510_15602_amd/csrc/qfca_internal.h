@@ -154,6 +154,7 @@ struct ScoreLaunch {
     long long* asum;      // [H][W] fixed-point channel sum (zeroed by the launcher)
     long long* w1sum;     // [H][W] or nullptr
     float* achan;         // [C][H][W] out or nullptr
+    bool w1only = false;    // window W1 only (principal-coordinate models): w1sum required
     int* dbg_cp = nullptr;  // inspection kernel: [C][H][W][B] out (with dbg_I), or nullptr
     int* dbg_I = nullptr;
     ScoreTile tile;
@@ -171,6 +172,11 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st);
 // Channel mean A = asum * inv_scale (written to amap when given), its
 // sigma-blurred score, and the W1 channel mean w1 = w1sum * inv_scale when
 // both are given.
+// Principal-coordinate score: the plane mean of the window W1 map
+// (w1sum * inv_scale; to w1 when given), its box mean over the windows
+// holding each pixel (amap, required), and amap's sigma blur (score).
+hipError_t launch_finish_w1(const long long* w1sum, double inv_scale, int H, int W, int T, float sigma,
+                            float* amap, float* w1, float* score, hipStream_t st);
 hipError_t launch_finish(const long long* asum, const long long* w1sum, double inv_scale, int H, int W,
                          float sigma, float* amap, float* w1, float* score, hipStream_t st);
 
@@ -215,6 +221,10 @@ struct ProjLaunch {
     const void* V2 = nullptr;
 };
 hipError_t launch_proj(const ProjLaunch& L, hipStream_t st);
+// Principal coordinates z = V^T (x - mu) (k of them, L.k <= 64) and their
+// bins against the coordinate edges (qfca_coords.hip): L.bins [k][N], L.resid
+// [k][N] (the coordinates) when set; L.V1 the GEMM1 operand table.
+hipError_t launch_coords(const ProjLaunch& L, hipStream_t st);
 
 // MFMA projection: padded channel count (0 if C > 512), number of 16-wide
 // component tiles (0 if k is 0 or > 64), host builders of the operand

@@ -53,5 +53,7 @@ extern "C" qfca_status qfca_score_map_noalloc(qfca_ctx ctx, qfca_model m, const 
         base = (dev >= 0 && dev < MAX_DEVICES) ? g_ptr[dev] : nullptr;
     }
     if (!base) return status_fail(QFCA_E_STATE, "qfca_score_map_noalloc: scratch not resolved for this device");
-    return score_map_into(ctx, m, bins, H, W, score, amap, w1, achan, base, w1 ? base + NOALLOC_MAX_PIXELS : nullptr);
+    // the second half carries the W1 channel sum (or, for a principal-
+    // coordinate model, the box-mean map when amap is NULL)
+    return score_map_into(ctx, m, bins, H, W, score, amap, w1, achan, base, base + NOALLOC_MAX_PIXELS);
 }

@@ -326,11 +326,98 @@ struct BlurW {
     double w[RMAX + 1];
 };
 
+// Box mean over the windows holding each pixel (radius r, clipped to the
+// image) of the window-W1 map W = (float)(w1sum * inv): amap (float) and,
+// when w1 is given, W itself.  Separable, in double, in a fixed order.
+constexpr int BOXT = 16, BOXR = 31;
+__global__ __launch_bounds__(256) void k_box(const long long* __restrict__ w1sum, double inv, int H, int W, int r,
+                                             float* __restrict__ amap, float* __restrict__ w1) {
+    __shared__ double tile[BOXT + 2 * BOXR][BOXT + 2 * BOXR];
+    __shared__ double hp[BOXT + 2 * BOXR][BOXT];
+    const int tx = threadIdx.x % BOXT, ty = threadIdx.x / BOXT;
+    const int bx = blockIdx.x * BOXT, by = blockIdx.y * BOXT;
+    const int TS = BOXT + 2 * r;
+    for (int t = threadIdx.x; t < TS * TS; t += 256) {
+        const int ly = t / TS, lx = t - ly * TS;
+        const int gy = by + ly - r, gx = bx + lx - r;
+        tile[ly][lx] = (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                           ? (double)(float)((double)w1sum[(size_t)gy * W + gx] * inv) : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < TS * BOXT; t += 256) {
+        const int ly = t / BOXT, lx = t - ly * BOXT;
+        double sacc = 0.0;
+        for (int d = 0; d <= 2 * r; ++d) sacc += tile[ly][lx + d];
+        hp[ly][lx] = sacc;
+    }
+    __syncthreads();
+    const int gy = by + ty, gx = bx + tx;
+    if (gy >= H || gx >= W) return;
+    double sacc = 0.0;
+    for (int d = 0; d <= 2 * r; ++d) sacc += hp[ty + d][tx];
+    const int nx = min(W - 1, gx + r) - max(0, gx - r) + 1, ny = min(H - 1, gy + r) - max(0, gy - r) + 1;
+    amap[(size_t)gy * W + gx] = (float)(sacc / ((double)nx * (double)ny));
+    if (w1) w1[(size_t)gy * W + gx] = (float)tile[ty + r][tx + r];
+}
+
+// Separable Gaussian (radius R) of a float map, renormalised over the
+// in-image taps.
+__global__ __launch_bounds__(256) void k_blur_f32(const float* __restrict__ in, int H, int W, int R, BlurW wts,
+                                                  float* __restrict__ out) {
+    __shared__ double tile[BT + 2 * RMAX][BT + 2 * RMAX];
+    __shared__ double hpass[BT + 2 * RMAX][BT];
+    __shared__ double w[RMAX + 1];
+    const int tx = threadIdx.x % BT, ty = threadIdx.x / BT;
+    const int bx = blockIdx.x * BT, by = blockIdx.y * BT;
+    const int TS = BT + 2 * R;
+    if (threadIdx.x <= R) w[threadIdx.x] = wts.w[threadIdx.x];
+    for (int t = threadIdx.x; t < TS * TS; t += 256) {
+        const int ly = t / TS, lx = t - ly * TS;
+        const int gy = by + ly - R, gx = bx + lx - R;
+        tile[ly][lx] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? (double)in[(size_t)gy * W + gx] : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < TS * BT; t += 256) {
+        const int ly = t / BT, lx = t - ly * BT;
+        const int gx = bx + lx;
+        double sacc = 0.0, ws = 0.0;
+        for (int d = -R; d <= R; ++d) {
+            if (gx + d < 0 || gx + d >= W) continue;
+            const double wd = w[d < 0 ? -d : d];
+            sacc += wd * tile[ly][lx + R + d];
+            ws += wd;
+        }
+        hpass[ly][lx] = sacc / ws;
+    }
+    __syncthreads();
+    const int gy = by + ty, gx = bx + tx;
+    if (gy >= H || gx >= W) return;
+    double sacc = 0.0, ws = 0.0;
+    for (int d = -R; d <= R; ++d) {
+        if (gy + d < 0 || gy + d >= H) continue;
+        const double wd = w[d < 0 ? -d : d];
+        sacc += wd * hpass[ty + R + d][tx];
+        ws += wd;
+    }
+    out[(size_t)gy * W + gx] = (float)(sacc / ws);
+}
+
 __global__ __launch_bounds__(256) void k_zero64(long long* __restrict__ a, long long* __restrict__ b, size_t n) {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
         a[i] = 0;
         if (b) b[i] = 0;
     }
+}
+
+// Window 1-Wasserstein distances of every window (the principal-coordinate
+// variant of the score), summed over channels into a.w1sum.
+template <int T>
+__global__ __launch_bounds__(64) void k_score_w1(KArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* rcp4 = (float*)smem;
+    fill_rcp4<T>(rcp4, a.rcp, threadIdx.x, 64);
+    score_tile<T, false, true, false, true>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x,
+                                            smem + BLayout<T>::RCP_BYTES, rcp4);
 }
 
 // Inspection build of k_score_t: the same tile code, also storing every
@@ -473,6 +560,8 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     a.cRw = L.tab.cRw; a.wgt = L.tab.wgt;
     const bool dbg = L.dbg_cp != nullptr;
     if (dbg && (!L.dbg_I || variant != 1)) return hipErrorInvalidValue;
+    const bool w1o = L.w1only && variant == 1;
+    if (L.w1only && !a.w1sum) return hipErrorInvalidValue;
     if (a.S < 1 || a.S * a.Bp > 64 || !a.asum) return hipErrorInvalidValue;
     const size_t lds = score_lds_bytes(a.T, a.Bp, a.S, a.Ws, variant);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
@@ -496,12 +585,15 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     switch (a.T) {
 #define QFCA_T_CASE(TT)                                                          \
         case TT: {                                                               \
-            const void* kf = dbg ? (const void*)k_score_dbg<TT> : (const void*)k_score_t<TT>; \
-            hipError_t e = dbg ? no_static_lds_uncached(kf) : no_static_lds(kf, TT); \
+            const void* kf = dbg ? (const void*)k_score_dbg<TT>                  \
+                                 : (w1o ? (const void*)k_score_w1<TT> : (const void*)k_score_t<TT>); \
+            hipError_t e = (dbg || w1o) ? no_static_lds_uncached(kf) : no_static_lds(kf, TT); \
             if (e == hipSuccess) e = allow(kf);                                  \
             if (e != hipSuccess) return e;                                       \
             if (dbg)                                                             \
                 hipLaunchKernelGGL(k_score_dbg<TT>, grid, dim3(64), lds, st, a); \
+            else if (w1o)                                                        \
+                hipLaunchKernelGGL(k_score_w1<TT>, grid, dim3(64), lds, st, a);  \
             else                                                                 \
                 hipLaunchKernelGGL(k_score_t<TT>, grid, dim3(64), lds, st, a);   \
         } break;
@@ -511,6 +603,22 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
 #undef QFCA_T_CASE
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_w1(const long long* w1sum, double inv_scale, int H, int W, int T, float sigma,
+                            float* amap, float* w1, float* score, hipStream_t st) {
+    const int r = T / 2;
+    if (r > BOXR) return hipErrorInvalidValue;
+    dim3 grid((W + BOXT - 1) / BOXT, (H + BOXT - 1) / BOXT);
+    hipLaunchKernelGGL(k_box, grid, dim3(256), 0, st, w1sum, inv_scale, H, W, r, amap, w1);
+    const int R = sigma > 0.f ? (int)ceil(3.0 * (double)sigma) : 0;
+    if (R > RMAX) return hipErrorInvalidValue;
+    BlurW wts;
+    for (int d = 0; d <= RMAX; ++d)
+        wts.w[d] = d <= R ? (R > 0 ? exp(-(double)(d * d) / (2.0 * (double)sigma * (double)sigma)) : 1.0) : 0.0;
+    dim3 g2((W + BT - 1) / BT, (H + BT - 1) / BT);
+    hipLaunchKernelGGL(k_blur_f32, g2, dim3(256), 0, st, (const float*)amap, H, W, R, wts, score);
     return hipGetLastError();
 }
 

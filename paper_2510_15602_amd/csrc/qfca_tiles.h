@@ -151,7 +151,11 @@ __device__ __forceinline__ void fill_rcp4(float* rcp4, const float* rcp, int tid
 //   DBG: inspection build of the same code that also stores, for every
 //   window of the tile's own outputs, the cumulative count cP_j and the
 //   transport numerator I_j of every bin (a.dbg_cp, a.dbg_I, [C][H][W][B]).
-template <int T, bool FASTG, bool RCP0, bool DBG = false>
+//   W1O: window 1-Wasserstein distances only: for each of the tile's own
+//   windows, sum_j |cP_j m - cR_j n| / (n m) weighted by delta_c, added over
+//   the channel group into a.w1sum (fixed point); no per-bin errors, no
+//   association, no halo rows.
+template <int T, bool FASTG, bool RCP0, bool DBG = false, bool W1O = false>
 __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int bz, int lane,
                                            unsigned char* smem, const float* rcp4) {
     using BL = BLayout<T>;
@@ -325,8 +329,8 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     // a wavefront per SIMD)
     constexpr bool GATHER_AHEAD = (T <= 11) || (T == 15);
 
-    const int ys = max(0, y0 - r);
-    const int yend = min(H, ye + r);
+    const int ys = W1O ? y0 : max(0, y0 - r);
+    const int yend = W1O ? ye : min(H, ye + r);
     const int lo_add = max(0, ys - r);
     const int hi_add = min(H, ys + r);
 
@@ -489,7 +493,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                     gacc[it] = *dst;
                 }
             };
-            if (GATHER_AHEAD && gat) {
+            if (!W1O && GATHER_AHEAD && gat) {
                 if (FASTG && gin)
                     gather_ahead(bconst<true>());
                 else
@@ -523,6 +527,38 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                 const int u = lane_prev(cpv[k]);
                 cmv[k] = j0 ? bias : u;
             }
+            if constexpr (W1O) {
+                // each lane's |4 (cP_j m - cR_j n)| (bins j < B - 1) goes to the
+                // row buffer; lane k < T then sums the S x Bp entries of its
+                // patch column, scales each channel's sum and adds them up
+                int* hri = (int*)hrow;
+#pragma unroll
+                for (int k = 0; k < T; ++k) {
+                    const int p = x0 - r + i0 + k;
+                    const int nx = max(1, min(W - 1, p + r) - max(0, p - r) + 1);
+                    hri[lane * HS + k] = w1ok ? abs((cpv[k] - bias) * m - crl4 * (ny * nx)) : 0;
+                }
+                wave_sync();
+                if (lane < T) {
+                    const int p = x0 - r + i0 + lane;
+                    if (p >= x0 && p < xe) {
+                        const int nx = min(W - 1, p + r) - max(0, p - r) + 1;
+                        const int n = ny * nx;
+                        long long qs = 0;
+                        for (int ss = 0; ss < S; ++ss) {
+                            int d = 0;
+                            for (int jj = 0; jj < Bp; ++jj) d += hri[(ss * Bp + jj) * HS + lane];
+                            const int cc = cbase + ss;
+                            if (cc < a.C)
+                                qs += __double2ll_rn(((double)d * (a.delta[cc] * a.fxs * 0.25)) /
+                                                     ((double)n * (double)m));
+                        }
+                        __hip_atomic_fetch_add(&a.w1sum[(size_t)y * W + p], qs, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                wave_sync();
+            } else {
             float ev[T];
             if (full) {
                 int gv[T];
@@ -687,6 +723,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                     gather_chunks(bconst<false>());
             }
             wave_sync();
+            }
             if constexpr (WIN) {
 #pragma unroll
                 for (int i = 0; i < TPD; ++i) {
@@ -695,6 +732,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                 }
             }
         }
+        if constexpr (!W1O) {
         // the pending rows move down by one
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
@@ -762,6 +800,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
+        }
         }
         wave_sync();
     }
