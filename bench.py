@@ -101,6 +101,8 @@ def parse():
     ap.add_argument("--large", type=int, default=1,
                     help="measure the 8 x 1024^2 + 32 x 256^2, C=512, k=64 BF16, B=64, T=31 batch (0: skip)")
     ap.add_argument("--large-steps", type=int, default=3)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the projection-alone and method-variant legs")
     ap.add_argument("--no-flips", action="store_true",
                     help="skip the BF16 flip rates and score errors against the FP64 oracle")
     ap.add_argument("--sweep", action="store_true",
@@ -385,6 +387,80 @@ def serving_leg(args, q, torch, np, dev, tile=None):
     }
 
 
+def projection_leg(args, q, torch, np, dev):
+    """The projection kernels alone on one 1024 x 1024 map with C = 512
+    float32 channels (2 GiB): the residual projection with k = 64 (BF16 and
+    FP32 MFMA) and the principal-coordinate projection with k = 64 (BF16),
+    bins written; HBM bytes = 4 C (features in) + bins out, per launch."""
+    import qfca_synth
+    C, k, B, T, H, W = 512, 64, 64, 31, 1024, 1024
+    X, _, _ = qfca_synth.make_texture_torch(C, H, W, 500, dev)
+    ctx = q.Context(0)
+    out = {"workload": f"{H}x{W} feature map, C={C} float32, k={k}, B={B}: projection and bins only"}
+    for name, pre, prec in (("residual_bf16", q.QFCA_PRE_RESIDUAL, q.QFCA_PREC_BF16),
+                            ("residual_fp32", q.QFCA_PRE_RESIDUAL, q.QFCA_PREC_FP32),
+                            ("coords_bf16", q.QFCA_PRE_COORDS, q.QFCA_PREC_BF16)):
+        prm = q.Params.make(C=C, k=k, B=B, T=T, preproc=pre, proj_prec=prec)
+        m = q.qfca_fit_pca(ctx, prm, X)
+        bins = torch.empty((m.planes, H, W), dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            q.qfca_quantize(ctx, m, X, bins=bins)
+        torch.cuda.synchronize()
+        ctx.profile_read("proj")
+        ctx.profile(True, kernels=["proj"])
+        for _ in range(20):
+            q.qfca_quantize(ctx, m, X, bins=bins)
+        torch.cuda.synchronize()
+        ctx.profile(False)
+        ms, n = ctx.profile_read("proj")
+        ms /= max(n, 1)
+        nbytes = float(H) * W * (4 * C + m.planes)
+        out[name] = {"avg_ms": round(ms, 4), "bytes": nbytes, "hbm_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        m.close()
+    return out
+
+
+def variants_leg(args, q, torch, np, dev):
+    """The method's variants on the 256x256 x 256 image (k = 32, B = 32,
+    T = 15, FP32 projection): principal-coordinate window W1 (quantise +
+    score), finite sigma_p = 2 association, and the quan -> median reference
+    (general reference weights); per-step time of each."""
+    import qfca_synth
+    ts, p = qfca_synth.workload_256(args.seed)
+    X = torch.from_numpy(ts[0].X).to(dev)
+    C, H, W = ts[0].X.shape
+    ctx = q.Context(0)
+    out = {"workload": f"{H}x{W} feature map, C={C} float32, k={p['k']}, B={p['B']}, T={p['T']}"}
+
+    def timed(step, n=20):
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    for name, kw in (("coords_w1", dict(preproc=q.QFCA_PRE_COORDS)), ("sigma_p_2", dict(sigma_p=2.0)),
+                     ("quan_median_ref", dict(reference=q.QFCA_REF_QUAN_MEDIAN))):
+        prm = q.Params.make(C=C, k=p["k"], B=p["B"], T=p["T"], sigma_s=p["sigma_s"], **kw)
+        m = q.qfca_fit_pca(ctx, prm, X)
+        bins = torch.empty((m.planes, H, W), dtype=torch.uint8, device=dev)
+        o = q.ScoreMaps(torch.empty((H, W), device=dev), amap=torch.empty((H, W), device=dev))
+
+        def step():
+            q.qfca_quantize(ctx, m, X, bins=bins)
+            q.qfca_score_map(ctx, m, bins, out=o)
+        ms = timed(step)
+        out[name] = {"ms_per_step": round(ms, 3), "mpx_s": round(H * W / (ms * 1e-3) / 1e6, 2),
+                     "general_reference": kw.get("reference", 0) == q.QFCA_REF_QUAN_MEDIAN}
+        m.close()
+    return out
+
+
+
 def sweep(args, q, torch, np, dev):
     """Score-kernel time on the 256x256 x 256 image against the window side T
     (B = 32) and the bin count B (T = 15), FP32 projection, model fitted on
@@ -546,6 +622,12 @@ def main():
     if args.batch_images > 0:
         batched = batched_leg(args, q, torch, np, dev)
         torch.cuda.empty_cache()
+    proj_alone = variants = None
+    if not args.no_extra:
+        proj_alone = projection_leg(args, q, torch, np, dev)
+        torch.cuda.empty_cache()
+        variants = variants_leg(args, q, torch, np, dev)
+        torch.cuda.empty_cache()
     large = None
     if args.large:
         large = large_leg(args, q, torch, np, dev)
@@ -582,6 +664,8 @@ def main():
         "cpu_baseline": cpu,
         "batched_bf16": batched,
         "large_bf16": large,
+        "projection_1024x1024_C512": proj_alone,
+        "variants_256": variants,
         "serving_bf16": serving,
     }
     print(json.dumps(res), flush=True)

@@ -487,6 +487,9 @@ qfca_status qfca::score_map_into(qfca_ctx ctx, qfca_model m, const uint8_t* bins
             return fail(QFCA_E_UNSUPPORTED, "tile does not fit in LDS");
     } else {
         L.tile = choose_tile(ctx, L.C, H, W, m->p.T, m->p.B, m->Bp);
+        // the window-W1 walk has no halo rows: bands of 16 rows cost nothing
+        // extra and give the few coordinate planes enough tiles
+        if (coords) L.tile.Hb = 16;
     }
     if (dbg_cp && L.tile.variant != 1)
         return fail(QFCA_E_UNSUPPORTED, "window inspection needs the block walk (T in 3..31, S within its limit)");

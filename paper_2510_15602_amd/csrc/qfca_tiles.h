@@ -14,6 +14,19 @@ __device__ __forceinline__ int lane_prev(int v) {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
+// Sum of v over each aligned group of g lanes (g = 8, 16, 32 or 64), held
+// by every lane of the group: mirrored and quad-permuted DPP adds within
+// rows of 16 lanes, then exchanges across rows.  Called by all lanes.
+__device__ __forceinline__ int group_sum(int v, int g) {
+    v += __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, false);  // row_half_mirror: lanes l, 7 - l
+    v += __builtin_amdgcn_mov_dpp(v, 0x4E, 0xf, 0xf, false);   // quad_perm [2, 3, 0, 1]
+    v += __builtin_amdgcn_mov_dpp(v, 0xB1, 0xf, 0xf, false);   // quad_perm [1, 0, 3, 2]: 8-lane sums
+    if (g >= 16) v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xf, 0xf, false);  // row_mirror: 16-lane sums
+    if (g >= 32) v += __shfl_xor(v, 16, 64);
+    if (g >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
 // A compile-time boolean passed as a value (selects code paths of a lambda).
 template <bool V>
 struct bconst {
@@ -528,36 +541,23 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                 cmv[k] = j0 ? bias : u;
             }
             if constexpr (W1O) {
-                // each lane's |4 (cP_j m - cR_j n)| (bins j < B - 1) goes to the
-                // row buffer; lane k < T then sums the S x Bp entries of its
-                // patch column, scales each channel's sum and adds them up
-                int* hri = (int*)hrow;
+                // each lane's |4 (cP_j m - cR_j n)| (bins j < B - 1), summed over
+                // the channel's Bp lanes by cross-lane adds (every lane of the
+                // group ends with the sum), scaled by the group's first lane
+                // and added to the channel sum of the patch
 #pragma unroll
                 for (int k = 0; k < T; ++k) {
                     const int p = x0 - r + i0 + k;
                     const int nx = max(1, min(W - 1, p + r) - max(0, p - r) + 1);
-                    hri[lane * HS + k] = w1ok ? abs((cpv[k] - bias) * m - crl4 * (ny * nx)) : 0;
-                }
-                wave_sync();
-                if (lane < T) {
-                    const int p = x0 - r + i0 + lane;
-                    if (p >= x0 && p < xe) {
-                        const int nx = min(W - 1, p + r) - max(0, p - r) + 1;
-                        const int n = ny * nx;
-                        long long qs = 0;
-                        for (int ss = 0; ss < S; ++ss) {
-                            int d = 0;
-                            for (int jj = 0; jj < Bp; ++jj) d += hri[(ss * Bp + jj) * HS + lane];
-                            const int cc = cbase + ss;
-                            if (cc < a.C)
-                                qs += __double2ll_rn(((double)d * (a.delta[cc] * a.fxs * 0.25)) /
-                                                     ((double)n * (double)m));
-                        }
-                        __hip_atomic_fetch_add(&a.w1sum[(size_t)y * W + p], qs, __ATOMIC_RELAXED,
+                    const int n = ny * nx;
+                    int d = w1ok ? abs((cpv[k] - bias) * m - crl4 * n) : 0;
+                    d = group_sum(d, Bp);
+                    if (j0 && cval && p >= x0 && p < xe) {
+                        const double v = ((double)d * (a.delta[c] * a.fxs * 0.25)) / ((double)n * (double)m);
+                        __hip_atomic_fetch_add(&a.w1sum[(size_t)y * W + p], __double2ll_rn(v), __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
-                wave_sync();
             } else {
             float ev[T];
             if (full) {
