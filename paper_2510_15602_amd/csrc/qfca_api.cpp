@@ -428,10 +428,22 @@ struct KernelTimer {
     }
 };
 
+// Compute units of the context's device (read once).
+int device_cus(qfca_ctx ctx) {
+    if (!ctx->ncu) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) return 0;
+        ctx->ncu = prop.multiProcessorCount;
+        ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+    }
+    return ctx->ncu;
+}
+
 ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
     auto tn = ctx->tuned.find((long long)T * 128 + B);
     if (tn != ctx->tuned.end()) return tn->second;
-    const long long key = (((long long)T * 128 + B) * 4096 + std::min(W, 4095)) * 4096 + std::min(H, 4095);
+    const long long key =
+        ((((long long)T * 128 + B) * 4096 + std::min(W, 4095)) * 4096 + std::min(H, 4095)) * 8192 + std::min(C, 8191);
     auto it = ctx->tiles.find(key);
     if (it != ctx->tiles.end()) return it->second;
     ScoreTile t;
@@ -449,7 +461,21 @@ ScoreTile choose_tile(qfca_ctx ctx, int C, int H, int W, int T, int B, int Bp) {
     while (score_lds_bytes(T, Bp, t.S, t.Ws, t.variant) > 65536 && t.Ws > 8)
         t.Ws = t.variant ? (t.Ws > T ? t.Ws - T : 8) : t.Ws >> 1;
     if (t.variant == 1 && t.Ws < T) t.variant = 0;  // the block walk needs strips of at least T columns
-    (void)C;
+    if (t.variant == 1) {
+        // Bands: the tallest (least halo: a band walks 2r rows beyond its own)
+        // that still gives at least three tiles per SIMD, so that the
+        // dispatcher can even out the SIMDs' loads (with one or two long
+        // tiles per SIMD, some SIMDs run one wavefront and others two)
+        const long long nsimd = 4LL * std::max(1, device_cus(ctx));
+        const long long cols = (long long)((W + t.Ws - 1) / t.Ws) * ((C + t.S - 1) / t.S);
+        t.Hb = 32;
+        for (int hb : {256, 192, 128, 96, 64, 48}) {
+            if (cols * ((H + hb - 1) / hb) >= 3 * nsimd) {
+                t.Hb = hb;
+                break;
+            }
+        }
+    }
     ctx->tiles[key] = t;
     return t;
 }
@@ -1315,12 +1341,7 @@ qfca_status qfca::score_batch_ext(qfca_ctx ctx, const qfca_job* jobs, int32_t n,
     HIP_TRY(hipEventRecord(ctx->staged, ctx->stream));
 
     // grid: as many resident blocks as fit
-    if (!ctx->ncu) {
-        hipDeviceProp_t prop;
-        HIP_TRY(hipGetDeviceProperties(&prop, ctx->device));
-        ctx->ncu = prop.multiProcessorCount;
-        ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
-    }
+    if (!device_cus(ctx)) return fail(QFCA_E_DEVICE, "cannot read the device properties");
     const int ncu = ctx->ncu;
     const int per_cu = std::min(2, std::max(1, (int)(ctx->lds_per_cu / std::max<size_t>(lds, 1))));
     const int grid = ncu * per_cu;

@@ -124,7 +124,8 @@ __device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* job
                 const int rest = local / J.nstrips;
                 const int by = rest % J.nbands;
                 const int gz = rest / J.nbands;
-                score_tile<T, true, true>(J.sa, bx, by, 4 * gz + w, lane, smem + (size_t)w * wave_lds, rcp4);
+                score_tile<T, true, true>(J.sa, bx, by * J.sa.Hb, min(J.sa.H, (by + 1) * J.sa.Hb), 4 * gz + w, lane,
+                                          smem + (size_t)w * wave_lds, rcp4);
             }
         }
         __syncthreads();

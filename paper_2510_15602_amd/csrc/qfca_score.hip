@@ -313,8 +313,9 @@ __global__ __launch_bounds__(64) void k_score_t(KArgs a) {
     // launcher checks that), so the dynamic LDS starts there
     float* rcp4 = (float*)smem;
     fill_rcp4<T>(rcp4, a.rcp, threadIdx.x, 64);
-    score_tile<T, false, true>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, smem + BLayout<T>::RCP_BYTES,
-                               rcp4);
+    const int y0 = blockIdx.y * a.Hb;
+    score_tile<T, false, true>(a, blockIdx.x, y0, min(a.H, y0 + a.Hb), blockIdx.z, threadIdx.x,
+                               smem + BLayout<T>::RCP_BYTES, rcp4);
 }
 
 // Separable Gaussian, radius R, renormalised over in-image taps (the 2-D
@@ -416,7 +417,8 @@ __global__ __launch_bounds__(64) void k_score_w1(KArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     float* rcp4 = (float*)smem;
     fill_rcp4<T>(rcp4, a.rcp, threadIdx.x, 64);
-    score_tile<T, false, true, false, true>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x,
+    const int y0 = blockIdx.y * a.Hb;
+    score_tile<T, false, true, false, true>(a, blockIdx.x, y0, min(a.H, y0 + a.Hb), blockIdx.z, threadIdx.x,
                                             smem + BLayout<T>::RCP_BYTES, rcp4);
 }
 
@@ -427,7 +429,8 @@ __global__ __launch_bounds__(64) void k_score_dbg(KArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     float* rcp4 = (float*)smem;
     fill_rcp4<T>(rcp4, a.rcp, threadIdx.x, 64);
-    score_tile<T, false, true, true>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x,
+    const int y0 = blockIdx.y * a.Hb;
+    score_tile<T, false, true, true>(a, blockIdx.x, y0, min(a.H, y0 + a.Hb), blockIdx.z, threadIdx.x,
                                      smem + BLayout<T>::RCP_BYTES, rcp4);
 }
 

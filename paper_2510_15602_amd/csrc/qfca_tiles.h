@@ -116,7 +116,7 @@ struct BLayout {
         size_t off = 0;
         vc = off;   off += align16((size_t)64 * vs4 * 4);
         ring = off; off += align16((size_t)T1 * S * rowb);
-        acc = off;  off += align16((size_t)T * S * Ws * 4 + 64 * 4);
+        acc = off;  off += align16((size_t)T * S * Ws * 4);
         hrow = off; off += align16((size_t)64 * HS * 4);
         psi = off;  off += align16((size_t)S * PSI * 4);
         total = off;
@@ -150,9 +150,10 @@ __device__ __forceinline__ void fill_rcp4(float* rcp4, const float* rcp, int tid
     }
 }
 
-// One (strip bx, band by, channel group bz) tile, run by one wavefront whose
-// lanes are `lane`, with its private LDS region `smem` (BLayout) and the
-// block-shared table rcp4 (fill_rcp4, visible to the wave before the call).
+// One (strip bx, output rows [y0, ye), channel group bz) tile, run by one
+// wavefront whose lanes are `lane`, with its private LDS region `smem`
+// (BLayout) and the block-shared table rcp4 (fill_rcp4, visible to the wave
+// before the call).  Every map is the same for any split of the rows.
 // The tile synchronises only its own wavefront, so the wavefronts of a block
 // may run tiles of different geometry.
 //   FASTG: blocks whose output columns all lie inside the strip take a
@@ -169,7 +170,7 @@ __device__ __forceinline__ void fill_rcp4(float* rcp4, const float* rcp, int tid
 //   the channel group into a.w1sum (fixed point); no per-bin errors, no
 //   association, no halo rows.
 template <int T, bool FASTG, bool RCP0, bool DBG = false, bool W1O = false>
-__device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int bz, int lane,
+__device__ __forceinline__ void score_tile(const KArgs& a, int bx, int y0, int ye, int bz, int lane,
                                            unsigned char* smem, const float* rcp4) {
     using BL = BLayout<T>;
     constexpr int r = BL::r, m = BL::m, T1 = BL::T1, TP = BL::TP, PSI = BL::PSI, HS = BL::HS;
@@ -181,8 +182,6 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     const int x0 = bx * Ws;
     const int xe = min(W, x0 + Ws);
     const int ws = xe - x0;
-    const int y0 = by * a.Hb;
-    const int ye = min(H, y0 + a.Hb);
     const int cbase = bz * S;
     const int c = cbase + s;
     const bool cval = (s < S) && (c < a.C);
@@ -196,9 +195,11 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
     uint32_t* vc32 = (uint32_t*)(smem + L.vc);   // [64 lanes][vs4 dwords]
     uint8_t* vcl = (uint8_t*)(vc32 + lane * L.vs4);
     uint8_t* ring = smem + L.ring;               // [T1][S][rowb]
-    float* acc = (float*)(smem + L.acc);         // [T][S][Ws] + 64 trash slots
-    float* trash = acc + T * S * Ws;
+    float* acc = (float*)(smem + L.acc);         // [T][S][Ws]
     float* hrow = (float*)(smem + L.hrow);       // [64 lanes][HS]: the block's T window sums per lane
+    // the gather's stores of items with no output go to column T of the
+    // lane's own hrow row (padding, never read)
+    float* trash_l = hrow + lane * HS + T;
     int* psi = (int*)(smem + L.psi);             // [S][PSI]: 4 Psi_c(t)
 
     // psi4[t] = 4 Psi(t) for t <= m, and 4 Psi(m + 1) = 4 (Psi(m) + sigma(m));
@@ -221,7 +222,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
             if (t0 + 64 * i < S * PSI) psi[t0 + 64 * i] = v[i];
     }
     for (int t = lane; t < 64 * L.vs4; t += 64) vc32[t] = 0u;
-    for (int t = lane; t < T * S * Ws + 64; t += 64) acc[t] = 0.f;
+    for (int t = lane; t < T * S * Ws; t += 64) acc[t] = 0.f;
     const int ci = cval ? c : 0;
     const int crm1 = a.cRm1[ci * Bp + j];
     const int dm1 = a.Dm1[ci * Bp + j];
@@ -500,7 +501,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                     const uint32_t w0 = g_w0[it], w1 = g_w1[it];
                     const int xo = i0 + (int)(w1 & 63u) - 2 * r;
                     const bool ok = IN ? (w1 & 0x8000u) != 0u : ((w1 & 0x8000u) && (xo >= 0) && (xo < ws));
-                    const float* dst = ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : (trash + lane);
+                    const float* dst = ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : trash_l;
                     gbin[it] = ring[(w0 >> 16) + blk * TP];
                     gdst[it] = lds_addr(dst);
                     gacc[it] = *dst;
@@ -589,6 +590,15 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                 constexpr int G = (T <= 8) ? 4 : 5;  // keeps T = 7 within three wavefronts per SIMD and T = 15 within two
 #pragma unroll
                 for (int k0 = 0; k0 < T; k0 += G) {
+                    // a group whose patch columns all lie outside the image
+                    // contributes nothing (the same zeros its steps would give)
+                    const int pg = x0 - r + i0 + k0;
+                    if (pg + G - 1 < 0 || pg >= W) {
+#pragma unroll
+                        for (int kk = 0; kk < G; ++kk)
+                            if (k0 + kk < T) ev[k0 + kk] = 0.f;
+                        continue;
+                    }
                     int gn[G], gav[G], gq[G], gP[G], gau[G], gps0[G], gps1[G];
                     float grc[G];
 #pragma unroll
@@ -702,7 +712,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int by, int b
                                 const bool ok =
                                     IN ? (w1 & 0x8000u) != 0u : ((w1 & 0x8000u) && (xo >= 0) && (xo < ws));
                                 bv[q] = ring[(w0 >> 16) + blk * TP];
-                                da[q] = lds_addr(ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : (trash + lane));
+                                da[q] = lds_addr(ok ? (acc + (int)(w1 >> 16) + (i0 - 2 * r)) : trash_l);
                             }
                         }
 #pragma unroll
