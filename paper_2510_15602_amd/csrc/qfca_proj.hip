@@ -24,6 +24,7 @@
 // The subtraction, the comparisons with the edges and all counting stay FP32.
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "qfca_internal.h"
 #include "qfca_tiles.h"
@@ -248,6 +249,271 @@ __global__ __launch_bounds__(256) void k_proj_bf16_mfma_wide(MArgs a) {
     proj_bf16_body<CMAX, KT, VLDS, ELDS>(a);
 }
 
+// ------------------------------------------------------------------------
+// BF16 kernel for the widest maps (CMAX = 512): every wavefront runs whole
+// 16-pixel tiles on its own, all channels in both products, so there are no
+// Z partials to add across wavefronts and no barrier in the tile loop.  The
+// eight wavefronts of a block (two per SIMD, which hide each other's memory
+// and LDS latency) share the operand tables and the per-channel parameters
+// in LDS; each walks its own contiguous run of tiles.  Lane (g, n) holds the
+// channels 32 s + 8 g + t of pixel n in d[s][t] (the first product's B
+// operand), and the second product's outputs land on the same channels.
+// The bins of four consecutive channels of a pixel (one lane) are packed in
+// a dword and transposed within each group of four lanes (two quad-permute
+// exchanges and two byte permutes), so that a lane holds four consecutive
+// pixels of one channel and writes them with one dword store.
+//
+// LDS: mu, lo, 1/delta, bin margin [CMAX] each; the two operand tables.
+__host__ __device__ inline size_t solo_lds(int CMAX, int KT) {
+    return (size_t)16 * CMAX + (size_t)2 * CMAX * KT * 16 * 2;
+}
+
+// Calls f(std::integral_constant<int, S>) for S = I .. N - 1 in order: an
+// unrolled loop whose index is a constant in every copy of the body (a body
+// too large for the loop unroller would otherwise index register arrays at
+// run time, which puts them in scratch memory).
+template <int I, int N>
+struct StaticFor {
+    template <class F>
+    __device__ __forceinline__ static void run(F& f) {
+        f(std::integral_constant<int, I>{});
+        StaticFor<I + 1, N>::run(f);
+    }
+};
+template <int N>
+struct StaticFor<N, N> {
+    template <class F>
+    __device__ __forceinline__ static void run(F&) {}
+};
+
+// Transposes the 4x4 bytes of a lane quad: lane p's byte v becomes lane v's
+// byte p.
+__device__ __forceinline__ uint32_t quad_transpose_bytes(uint32_t d, uint32_t selA, uint32_t selB) {
+    const uint32_t pa = (uint32_t)__builtin_amdgcn_mov_dpp((int)d, 0xB1, 0xf, 0xf, false);  // lane p ^ 1
+    const uint32_t a1 = __builtin_amdgcn_perm(d, pa, selA);
+    const uint32_t pb = (uint32_t)__builtin_amdgcn_mov_dpp((int)a1, 0x4E, 0xf, 0xf, false);  // lane p ^ 2
+    return __builtin_amdgcn_perm(a1, pb, selB);
+}
+
+template <int CMAX, int KT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_proj_bf16_solo(MArgs a) {
+    constexpr int NS = CMAX / 32;        // first-product K steps (32 channels each)
+    constexpr int NU = KT / 2;           // second-product K steps (32 components each)
+    constexpr int VSZ = CMAX * KT * 16;  // bf16 elements per table
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float* smu = (float*)lds_raw;
+    float* slo = smu + CMAX;
+    float* sid = slo + CMAX;
+    float* sfd = sid + CMAX;
+    bf16x8* sv1 = (bf16x8*)(lds_raw + 16 * CMAX);
+    bf16x8* sv2 = sv1 + VSZ / 8;
+    for (int i = threadIdx.x; i < CMAX; i += blockDim.x) {
+        const bool ok = i < a.C;
+        const float vm = ok ? a.mu[i] : 0.f;
+        const float vl = ok && a.lo ? a.lo[i] : 0.f;
+        const float vi = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
+        const float vf = ok && a.fastd ? a.fastd[i] : 1.f;
+        smu[i] = vm;
+        slo[i] = vl;
+        sid[i] = vi;
+        sfd[i] = vf;
+    }
+    {
+        // tables: 16-byte units, eight loads per thread in flight before
+        // their stores
+        constexpr int NUNIT = VSZ / 8;
+        const uint4* g1 = (const uint4*)a.V1;
+        const uint4* g2 = (const uint4*)a.V2;
+        uint4* d1 = (uint4*)sv1;
+        uint4* d2 = (uint4*)sv2;
+        for (int u0 = threadIdx.x; u0 < NUNIT; u0 += 4 * 512) {
+            uint4 t1[4], t2[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = u0 + 512 * i;
+                if (u < NUNIT) {
+                    t1[i] = g1[u];
+                    t2[i] = g2[u];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = u0 + 512 * i;
+                if (u < NUNIT) {
+                    d1[u] = t1[i];
+                    d2[u] = t2[i];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = (int)gridDim.x * 8;
+    const int per = (a.ntiles + nw - 1) / nw;
+    int tile = ((int)blockIdx.x * 8 + w) * per;
+    const int tend = min(a.ntiles, tile + per);
+    const bool rows_dw = ((a.N & 3) == 0) && (((uintptr_t)a.bins & 3) == 0);
+    for (; tile < tend; ++tile) {
+        // the lane index made opaque per tile: every address and test derived
+        // from the lane's channels is formed in the loop where it is used
+        // (hoisted out of it, the 128 channels' offsets and tests would take
+        // far more registers than the wavefront has)
+        int lane = threadIdx.x & 63;
+        asm volatile("" : "+v"(lane));
+        const int g = lane >> 4, n = lane & 15, p = n & 3, qd = n >> 2;
+        // byte selectors of the quad transpose (first exchange with lane
+        // p ^ 1, then with lane p ^ 2; own dword is the first perm source)
+        const uint32_t selA = (p & 1) ? 0x07030501u : 0x02060004u;
+        const uint32_t selB = (p & 2) ? 0x07060302u : 0x01000504u;
+        const int px = tile * 16 + n;
+        const bool pxok = px < a.N;
+        const int pxc = pxok ? px : a.N - 1;
+        // features of the whole tile, every load issued before the first use:
+        // channel 32 s + t + 8 g of pixel pxc is at the uniform row base of
+        // channel 32 s + t plus the lane's 32-bit byte offset (8 g N + pxc) 4
+        // (channels past C read channel C - 1 from their own row base)
+        // (a lane whose channel is past C reads the uniform channel's row, or
+        // channel C - 1 when that is past C too: real features that meet
+        // zero table rows and whose residuals are never stored)
+        float d[NS][8];
+        const uint32_t voff = ((uint32_t)(8 * g) * (uint32_t)a.N + (uint32_t)pxc) * 4u;
+        const uint32_t voff0 = (uint32_t)pxc * 4u;
+        // the base made opaque per tile: the 128 row bases are then formed in
+        // the loop as they are used (hoisted out of it they would be 256
+        // live registers)
+        const float* Xt = a.X;
+        asm volatile("" : "+s"(Xt));
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int cu = 32 * s + t;  // uniform part of the channel
+                const char* rb = (const char*)(Xt + (size_t)(cu < a.C ? cu : a.C - 1) * a.N);
+                d[s][t] = *(const float*)(rb + (cu + 8 * g < a.C ? voff : voff0));
+            }
+        const bf16x8* V1 = opaque_lds((const bf16x8*)sv1);
+        const bf16x8* V2 = opaque_lds((const bf16x8*)sv2);
+        const float* mu = opaque_lds((const float*)smu);
+        floatx4 z[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) z[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            // mu of the lane's eight channels: two 16-byte reads
+            const float4 m0 = *(const float4*)(mu + 32 * s + 8 * g);
+            const float4 m1 = *(const float4*)(mu + 32 * s + 8 * g + 4);
+            const float mv[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+            bf16x8 bv;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                d[s][t] -= mv[t];
+                bv[t] = (__bf16)d[s][t];
+            }
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+                z[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V1[((s * KT + kt) * 4 + g) * 16 + n], bv, z[kt], 0, 0,
+                                                                0);
+            // keeps the scheduler from hoisting later steps' table reads
+            // (all of them in flight at once would not fit the registers)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        bf16x8 zb[NU];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zb[kt >> 1][4 * (kt & 1) + v] = (__bf16)z[kt][v];
+        const float* plo = opaque_lds((const float*)slo);
+        const float* pid = opaque_lds((const float*)sid);
+        const float* pfd = opaque_lds((const float*)sfd);
+        const int B = a.B;
+        const float top = (float)max(B - 1, 0);
+        const uint32_t needmask = B > 1 ? 0xFu : 0u;  // one bin: every value's bin is 0
+        // the other bases opaque per tile too, for the same reason
+        const float* Et = a.edges;
+        float* Rt = a.resid;
+        uint8_t* Bt = a.bins;
+        asm volatile("" : "+s"(Et), "+s"(Rt), "+s"(Bt));
+        auto step = [&](auto sc) __attribute__((always_inline)) {
+            constexpr int s = decltype(sc)::value;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int u = 0; u < NU; ++u)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V2[(((2 * s + h) * NU + u) * 4 + g) * 16 + n],
+                                                                  zb[u], acc, 0, 0, 0);
+                const int c0 = 32 * s + 8 * g + 4 * h;  // channels c0 .. c0 + 3 of pixel px
+                float rv[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) rv[v] = d[s][4 * h + v] - acc[v];
+                if (Rt) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (pxok && c0 + v < a.C) Rt[(size_t)(c0 + v) * a.N + px] = rv[v];
+                }
+                if (!Bt) continue;
+                // bin = #{m : r >= e_m}, decided by the margin test or, next
+                // to an edge, by the edge search (as emit_values)
+                // the four channels' parameters: one 16-byte read each (c0 is a
+                // multiple of 4); tests combined without branches
+                const float4 l4 = *(const float4*)(plo + c0);
+                const float4 i4 = *(const float4*)(pid + c0);
+                const float4 f4 = *(const float4*)(pfd + c0);
+                const float lov[4] = {l4.x, l4.y, l4.z, l4.w};
+                const float idv[4] = {i4.x, i4.y, i4.z, i4.w};
+                const float dlv[4] = {f4.x, f4.y, f4.z, f4.w};
+                uint32_t bq[4];
+                uint32_t need = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float tt = (rv[v] - lov[v]) * idv[v];
+                    const float near = __builtin_amdgcn_fmed3f(rintf(tt), 1.f, top);
+                    const bool dec = (fabsf(tt - near) >= dlv[v]) & (dlv[v] < 0.5f) & (idv[v] != 0.f);
+                    bq[v] = (uint32_t)__builtin_amdgcn_fmed3f(floorf(tt), 0.f, top);
+                    need |= ((!dec) & pxok & (c0 + v < a.C)) ? (1u << v) : 0u;
+                }
+                need &= needmask;
+                if (__ballot(need != 0u)) {
+                    // one edge search per round for the lowest flagged value
+                    // of each lane (one copy of the search code per step)
+                    uint32_t nd = need;
+                    while (__ballot(nd != 0u)) {
+                        const int v = nd ? __builtin_ctz(nd) : 0;
+                        const float r = v == 0 ? rv[0] : (v == 1 ? rv[1] : (v == 2 ? rv[2] : rv[3]));
+                        const int c = c0 + v;
+                        const uint32_t b = nd ? (uint32_t)bin_fast(r, Et + (size_t)c * (B - 1), plo[c], pid[c], B)
+                                              : 0u;
+                        if (nd) {
+                            bq[0] = v == 0 ? b : bq[0];
+                            bq[1] = v == 1 ? b : bq[1];
+                            bq[2] = v == 2 ? b : bq[2];
+                            bq[3] = v == 3 ? b : bq[3];
+                        }
+                        nd &= nd - 1u;
+                    }
+                }
+                const uint32_t pk = bq[0] | (bq[1] << 8) | (bq[2] << 16) | (bq[3] << 24);
+                // lane (g, 4 qd + p) now holds channel c0' + p, pixels 4 qd .. 4 qd + 3
+                const uint32_t tr = quad_transpose_bytes(pk, selA, selB);
+                const int cw = 32 * s + 8 * g + 4 * h + p;
+                const int pw = tile * 16 + 4 * qd;
+                if (cw < a.C) {
+                    uint8_t* dst = Bt + (size_t)cw * a.N + pw;
+                    if (rows_dw && pw + 3 < a.N) {
+                        *(uint32_t*)dst = tr;
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (pw + i < a.N) dst[i] = (uint8_t)(tr >> (8 * i));
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        };
+        StaticFor<0, NS>::run(step);
+    }
+}
+
 constexpr size_t LDS_MAX = 160 * 1024;
 constexpr size_t LDS_TWO_BLOCKS = 80 * 1024;
 
@@ -370,6 +636,23 @@ hipError_t launch_proj_mfma(const ProjLaunch& L, const void* V1, const void* V2,
     if (!CM || !KT) return hipErrorInvalidValue;
     const bool bf = L.prec == QFCA_PREC_BF16;
     const int elt = bf ? 2 : 4;
+    // (the lane byte offsets of its feature loads are 32-bit: (24 N + N) 4 < 2^32)
+    if (bf && CM == 512 && (KT == 2 || KT == 4) && (unsigned long long)L.N * 100ULL < (1ULL << 32)) {
+        // whole tiles per wavefront, eight wavefronts per block, one block per CU
+        int ncu = 0;
+        const hipError_t e = device_cus(&ncu);
+        if (e != hipSuccess) return e;
+        const size_t lds = solo_lds(CM, KT);
+        const void* kf = KT == 4 ? (const void*)k_proj_bf16_solo<512, 4> : (const void*)k_proj_bf16_solo<512, 2>;
+        const hipError_t ea = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (ea != hipSuccess) return ea;
+        const int blocks = std::max(1, std::min((a.ntiles + 7) / 8, ncu));
+        if (KT == 4)
+            hipLaunchKernelGGL((k_proj_bf16_solo<512, 4>), dim3(blocks), dim3(512), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_proj_bf16_solo<512, 2>), dim3(blocks), dim3(512), lds, st, a);
+        return hipGetLastError();
+    }
     // tables in LDS when they fit; the edges are read through the cache
     // (the bin decision needs them only for values next to an edge)
     const bool vl = proj_lds(CM, KT, elt, true, false, L.C, L.B).total <= LDS_MAX;

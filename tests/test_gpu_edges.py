@@ -44,16 +44,25 @@ def planted_values(edges, rng, n):
     return rng.permutation(np.resize(v, n))
 
 
-@pytest.mark.parametrize("C,prec,grid", [(64, q.QFCA_PREC_FP32, True), (256, q.QFCA_PREC_FP32, True),
-                                         (256, q.QFCA_PREC_BF16, True), (64, q.QFCA_PREC_FP32, False)],
-                         ids=["C64_fp32", "C256_fp32", "C256_bf16", "C64_fp32_irregular_edges"])
-def test_bins_of_values_on_edges(ctx, C, prec, grid):
+@pytest.mark.parametrize("C,prec,grid,H,W", [(64, q.QFCA_PREC_FP32, True, 40, 48),
+                                             (256, q.QFCA_PREC_FP32, True, 40, 48),
+                                             (256, q.QFCA_PREC_BF16, True, 40, 48),
+                                             (64, q.QFCA_PREC_FP32, False, 40, 48),
+                                             (512, q.QFCA_PREC_BF16, True, 40, 48),
+                                             (500, q.QFCA_PREC_BF16, False, 37, 41),
+                                             (449, q.QFCA_PREC_BF16, True, 9, 12)],
+                         ids=["C64_fp32", "C256_fp32", "C256_bf16", "C64_fp32_irregular_edges", "C512_bf16",
+                              "C500_bf16_irregular_ragged", "C449_bf16_one_ragged_tile"])
+def test_bins_of_values_on_edges(ctx, C, prec, grid, H, W):
     """With mu = 0 and an all-zero basis the residual is the feature itself,
     so values can be placed exactly on the edges; the bins must equal
     #{m : r >= e_m} for every one (regular grid edges take the arithmetic
-    shortcut away from edges; irregular edges are always searched)."""
+    shortcut away from edges; irregular edges are always searched).  C > 256
+    in BF16 runs the kernel whose wavefronts own whole tiles and write bins
+    four pixels to a dword (byte by byte when a row is not a whole number of
+    dwords: the 37 x 41 and 9 x 12 maps)."""
     rng = np.random.Generator(np.random.PCG64(C + prec + grid))
-    B, H, W = 32, 40, 48
+    B = 32
     lo = rng.uniform(-3, -1, C)
     delta = rng.uniform(0.05, 0.3, C)
     if grid:
@@ -73,7 +82,38 @@ def test_bins_of_values_on_edges(ctx, C, prec, grid):
     for c in range(C):
         np.testing.assert_array_equal(g[c], np.searchsorted(edges[c], X[c], side="right"),
                                       err_msg=f"channel {c}")
-    say(f"[edges] C={C} prec={prec} grid={grid}: {g.size} bins exact")
+    say(f"[edges] C={C} prec={prec} grid={grid} {H}x{W}: {g.size} bins exact")
+
+
+@pytest.mark.parametrize("C,k,H,W", [(512, 64, 48, 80), (512, 32, 33, 47), (300, 50, 20, 31)],
+                         ids=["C512_k64", "C512_k32_ragged", "C300_k50"])
+def test_bf16_projection_wide(ctx, C, k, H, W):
+    """BF16 projection of the widest maps (C > 256) against the FP64
+    oracle: the residual within the BF16 operand rounding, and the bins
+    exactly #{m : r >= e_m} of the GPU's own residual."""
+    rng = np.random.Generator(np.random.PCG64(C * 7 + k))
+    say(f"[bf16 wide] C={C} k={k} {H}x{W}")
+    X = rng.standard_normal((C, H, W)).astype(np.float32) * rng.uniform(0.5, 2.0, (C, 1, 1)).astype(np.float32)
+    mu = X.reshape(C, -1).mean(1)
+    V, _ = np.linalg.qr(rng.standard_normal((C, k)))
+    B = 32
+    Rr = oracle.residual(X, mu.astype(np.float32).astype(np.float64), V.astype(np.float32).astype(np.float64))
+    _, _, delta, edges = oracle.edges(Rr, B)
+    prm = q.Params.make(C=C, k=k, B=B, T=5, proj_prec=q.QFCA_PREC_BF16)
+    cR = np.full((C, B), 25, np.int32)
+    m = q.qfca_model_create(ctx, prm, mu.astype(np.float32), V.astype(np.float32), edges, delta, cR)
+    bins, resid = q.qfca_quantize(ctx, m, torch.from_numpy(X).cuda(), resid=True)
+    torch.cuda.synchronize()
+    r = resid.cpu().numpy().astype(np.float64)
+    # BF16 operands (8 significant bits) with FP32 accumulation: the
+    # reconstruction's error is a few 2^-8 of |x - mu| summed over C
+    scale = np.abs(X - mu[:, None, None]).reshape(C, -1).max()
+    assert np.abs(r - Rr).max() <= 0.05 * scale
+    g = bins.cpu().numpy()
+    e32 = edges.astype(np.float32)
+    for c in range(C):
+        np.testing.assert_array_equal(g[c], np.searchsorted(e32[c], resid[c].cpu().numpy(), side="right"),
+                                      err_msg=f"channel {c}")
 
 
 def rand_problem(seed, C, H, W, T, B):
