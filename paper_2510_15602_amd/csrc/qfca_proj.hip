@@ -264,6 +264,10 @@ __global__ __launch_bounds__(256) void k_proj_bf16_mfma_wide(MArgs a) {
 // pixels of one channel and writes them with one dword store.
 //
 // LDS: mu, lo, 1/delta, bin margin [CMAX] each; the two operand tables.
+// Wavefronts per block of k_proj_bf16_solo (a multiple of 4: NW / 4 per SIMD).
+#ifndef SOLO_WAVES
+#define SOLO_WAVES 12
+#endif
 __host__ __device__ inline size_t solo_lds(int CMAX, int KT) {
     return (size_t)16 * CMAX + (size_t)2 * CMAX * KT * 16 * 2;
 }
@@ -295,8 +299,9 @@ __device__ __forceinline__ uint32_t quad_transpose_bytes(uint32_t d, uint32_t se
     return __builtin_amdgcn_perm(a1, pb, selB);
 }
 
-template <int CMAX, int KT>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_proj_bf16_solo(MArgs a) {
+template <int CMAX, int KT, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4))) void k_proj_bf16_solo(
+    MArgs a) {
     constexpr int NS = CMAX / 32;        // first-product K steps (32 channels each)
     constexpr int NU = KT / 2;           // second-product K steps (32 components each)
     constexpr int VSZ = CMAX * KT * 16;  // bf16 elements per table
@@ -326,11 +331,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const uint4* g2 = (const uint4*)a.V2;
         uint4* d1 = (uint4*)sv1;
         uint4* d2 = (uint4*)sv2;
-        for (int u0 = threadIdx.x; u0 < NUNIT; u0 += 4 * 512) {
+        for (int u0 = threadIdx.x; u0 < NUNIT; u0 += 4 * 64 * NW) {
             uint4 t1[4], t2[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int u = u0 + 512 * i;
+                const int u = u0 + 64 * NW * i;
                 if (u < NUNIT) {
                     t1[i] = g1[u];
                     t2[i] = g2[u];
@@ -338,7 +343,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int u = u0 + 512 * i;
+                const int u = u0 + 64 * NW * i;
                 if (u < NUNIT) {
                     d1[u] = t1[i];
                     d2[u] = t2[i];
@@ -348,12 +353,42 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = (int)gridDim.x * 8;
-    const int per = (a.ntiles + nw - 1) / nw;
-    int tile = ((int)blockIdx.x * 8 + w) * per;
-    const int tend = min(a.ntiles, tile + per);
+    // A block walks a contiguous run of tiles, its NW wavefronts interleaved
+    // (wave w takes tiles w, w + NW, ...): the block's current tiles are
+    // 16 NW consecutive pixels, so its bin stores fill whole 128-byte lines
+    // of each channel row and its feature loads whole lines too.
+    const int per = ((a.ntiles + (int)gridDim.x - 1) / (int)gridDim.x + NW - 1) / NW * NW;
+    const int b0 = (int)blockIdx.x * per;
+    const int tend = min(a.ntiles, b0 + per);
+    int tile = b0 + w;
     const bool rows_dw = ((a.N & 3) == 0) && (((uintptr_t)a.bins & 3) == 0);
-    for (; tile < tend; ++tile) {
+    // features of a tile: channel 32 s + t + 8 g of pixel px is at the uniform
+    // row base of channel 32 s + t plus the lane's 32-bit byte offset
+    // (8 g N + px) 4.  A lane whose channel is past C reads the uniform
+    // channel's row, or channel C - 1 when that is past C too: real features
+    // that meet zero table rows and whose residuals are never stored.
+    // d[s] of the next tile is loaded as soon as the current tile's step s
+    // has used it, so the loads of a tile are in flight during the previous
+    // one's second product and quantisation.
+    auto load_row = [&](float (&dr)[8], int s, const float* Xb, uint32_t vo, uint32_t vo0, int gg)
+        __attribute__((always_inline)) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int cu = 32 * s + t;  // uniform part of the channel
+            const char* rb = (const char*)(Xb + (size_t)(cu < a.C ? cu : a.C - 1) * a.N);
+            dr[t] = *(const float*)(rb + (cu + 8 * gg < a.C ? vo : vo0));
+        }
+    };
+    float d[NS][8];
+    if (tile < tend) {
+        const int lane = threadIdx.x & 63;
+        const int g = lane >> 4;
+        const int pxc = min(tile * 16 + (lane & 15), a.N - 1);
+        const uint32_t vo = ((uint32_t)(8 * g) * (uint32_t)a.N + (uint32_t)pxc) * 4u;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) load_row(d[s], s, a.X, vo, (uint32_t)pxc * 4u, g);
+    }
+    for (; tile < tend; tile += NW) {
         // the lane index made opaque per tile: every address and test derived
         // from the lane's channels is formed in the loop where it is used
         // (hoisted out of it, the 128 channels' offsets and tests would take
@@ -367,30 +402,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const uint32_t selB = (p & 2) ? 0x07060302u : 0x01000504u;
         const int px = tile * 16 + n;
         const bool pxok = px < a.N;
-        const int pxc = pxok ? px : a.N - 1;
-        // features of the whole tile, every load issued before the first use:
-        // channel 32 s + t + 8 g of pixel pxc is at the uniform row base of
-        // channel 32 s + t plus the lane's 32-bit byte offset (8 g N + pxc) 4
-        // (channels past C read channel C - 1 from their own row base)
-        // (a lane whose channel is past C reads the uniform channel's row, or
-        // channel C - 1 when that is past C too: real features that meet
-        // zero table rows and whose residuals are never stored)
-        float d[NS][8];
-        const uint32_t voff = ((uint32_t)(8 * g) * (uint32_t)a.N + (uint32_t)pxc) * 4u;
-        const uint32_t voff0 = (uint32_t)pxc * 4u;
-        // the base made opaque per tile: the 128 row bases are then formed in
-        // the loop as they are used (hoisted out of it they would be 256
-        // live registers)
+        const bool more = tile + NW < tend;
+        const int pxn = min((tile + NW) * 16 + n, a.N - 1);
+        const uint32_t von = ((uint32_t)(8 * g) * (uint32_t)a.N + (uint32_t)pxn) * 4u;
+        const uint32_t von0 = (uint32_t)pxn * 4u;
+        // the base made opaque per tile, as the lane index
         const float* Xt = a.X;
         asm volatile("" : "+s"(Xt));
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int cu = 32 * s + t;  // uniform part of the channel
-                const char* rb = (const char*)(Xt + (size_t)(cu < a.C ? cu : a.C - 1) * a.N);
-                d[s][t] = *(const float*)(rb + (cu + 8 * g < a.C ? voff : voff0));
-            }
         const bf16x8* V1 = opaque_lds((const bf16x8*)sv1);
         const bf16x8* V2 = opaque_lds((const bf16x8*)sv2);
         const float* mu = opaque_lds((const float*)smu);
@@ -509,6 +527,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
+            if (more) load_row(d[s], s, Xt, von, von0, g);
         };
         StaticFor<0, NS>::run(step);
     }
@@ -643,14 +662,16 @@ hipError_t launch_proj_mfma(const ProjLaunch& L, const void* V1, const void* V2,
         const hipError_t e = device_cus(&ncu);
         if (e != hipSuccess) return e;
         const size_t lds = solo_lds(CM, KT);
-        const void* kf = KT == 4 ? (const void*)k_proj_bf16_solo<512, 4> : (const void*)k_proj_bf16_solo<512, 2>;
+        constexpr int NW = SOLO_WAVES;
+        const void* kf =
+            KT == 4 ? (const void*)k_proj_bf16_solo<512, 4, NW> : (const void*)k_proj_bf16_solo<512, 2, NW>;
         const hipError_t ea = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (ea != hipSuccess) return ea;
-        const int blocks = std::max(1, std::min((a.ntiles + 7) / 8, ncu));
+        const int blocks = std::max(1, std::min((a.ntiles + NW - 1) / NW, ncu));
         if (KT == 4)
-            hipLaunchKernelGGL((k_proj_bf16_solo<512, 4>), dim3(blocks), dim3(512), lds, st, a);
+            hipLaunchKernelGGL((k_proj_bf16_solo<512, 4, NW>), dim3(blocks), dim3(64 * NW), lds, st, a);
         else
-            hipLaunchKernelGGL((k_proj_bf16_solo<512, 2>), dim3(blocks), dim3(512), lds, st, a);
+            hipLaunchKernelGGL((k_proj_bf16_solo<512, 2, NW>), dim3(blocks), dim3(64 * NW), lds, st, a);
         return hipGetLastError();
     }
     // tables in LDS when they fit; the edges are read through the cache
