@@ -24,7 +24,7 @@ HIPCC_FLAGS = [
 
 
 # Sources with host code only, compiled by the host C++ compiler.
-HOST_ONLY = {"qfca_eig.cpp"}
+HOST_ONLY = {"qfca_eig.cpp", "qfca_blob.cpp"}
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall"]
 
 

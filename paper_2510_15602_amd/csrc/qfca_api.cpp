@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "qfca_blob.h"
 #include "qfca_internal.h"
 
 namespace qfca {
@@ -105,25 +106,9 @@ qfca_status hip_fail(hipError_t e, const char* where) {
     } while (0)
 
 qfca_status check_params(const qfca_params* p) {
-    if (!p) return fail(QFCA_E_ARG, "params is NULL");
-    if (p->C < 1 || p->C > 2048) return fail(QFCA_E_ARG, "C must be in [1, 2048]");
-    if (p->B < 1 || p->B > 64) return fail(QFCA_E_UNSUPPORTED, "B must be in [1, 64]");
-    if (p->T < 1 || p->T > 63 || (p->T % 2) == 0) return fail(QFCA_E_UNSUPPORTED, "T must be odd, 1..63");
-    if (p->preproc != QFCA_PRE_NONE && p->preproc != QFCA_PRE_RESIDUAL && p->preproc != QFCA_PRE_COORDS)
-        return fail(QFCA_E_ARG, "unknown preproc");
-    if (p->proj_prec != QFCA_PREC_FP32 && p->proj_prec != QFCA_PREC_BF16)
-        return fail(QFCA_E_ARG, "unknown proj_prec");
-    if (p->preproc == QFCA_PRE_RESIDUAL && (p->k < 0 || p->k > 64 || p->k > p->C - 1))
-        return fail(QFCA_E_UNSUPPORTED, "k must be in [0, min(64, C-1)]");
-    if (p->preproc == QFCA_PRE_COORDS && (p->k < 1 || p->k > 64 || p->k > p->C))
-        return fail(QFCA_E_UNSUPPORTED, "k must be in [1, min(64, C)] for principal coordinates");
-    if (!(p->q_lo >= 0.f && p->q_lo < p->q_hi && p->q_hi <= 1.f))
-        return fail(QFCA_E_ARG, "need 0 <= q_lo < q_hi <= 1");
-    if (!(p->sigma_s >= 0.f && p->sigma_s <= 5.f)) return fail(QFCA_E_ARG, "sigma_s must be in [0, 5]");
-    if (!(p->sigma_p > 0.f)) return fail(QFCA_E_ARG, "sigma_p must be > 0 (INFINITY: plain mean)");
-    if (p->reference < QFCA_REF_MEDIAN_QUAN || p->reference > QFCA_REF_QUAN_MEAN)
-        return fail(QFCA_E_ARG, "unknown reference");
-    return QFCA_OK;
+    std::string err;
+    const qfca_status st = host_check_params(p, &err);
+    return st == QFCA_OK ? st : fail(st, err);
 }
 
 // Histogrammed planes of a model: the C channels (PRE_NONE, PRE_RESIDUAL) or
@@ -731,24 +716,12 @@ qfca_status build_model(qfca_ctx ctx, const qfca_params* p, const double* mu, co
     if (st != QFCA_OK) return st;
     const int C = p->C, k = p->k, B = p->B, T = p->T, P = planes(*p);
     const bool pre = p->preproc != QFCA_PRE_NONE;
-    if ((B > 1 && !edges) || !delta) return fail(QFCA_E_ARG, "edges and delta are required");
     if (pre && k > 0 && (!mu || !V)) return fail(QFCA_E_ARG, "mu and V are required for k > 0");
-    for (int c = 0; c < P; ++c) {
-        if (!(delta[c] >= 0.0) || !isfinite(delta[c])) return fail(QFCA_E_ARG, "delta must be finite, >= 0");
-        for (int i = 1; i + 1 < B; ++i)
-            if (!(edges[(size_t)c * (B - 1) + i] >= edges[(size_t)c * (B - 1) + i - 1]))
-                return fail(QFCA_E_ARG, "edges must be nondecreasing per channel");
+    {
+        std::string err;
+        if ((st = host_check_arrays(*p, edges, delta, cR, &err)) != QFCA_OK) return fail(st, err);
     }
-    if (cR) {
-        for (int c = 0; c < P; ++c) {
-            if (cR[(size_t)c * B + B - 1] != T * T) return fail(QFCA_E_ARG, "cR[c][B-1] must equal T*T");
-            for (int i = 0; i < B; ++i) {
-                const int32_t v = cR[(size_t)c * B + i];
-                if (v < 0 || (i > 0 && v < cR[(size_t)c * B + i - 1]))
-                    return fail(QFCA_E_ARG, "cR must be nondecreasing and >= 0");
-            }
-        }
-    }
+    (void)T;
     HIP_TRY(hipSetDevice(ctx->device));
     std::unique_ptr<qfca_model_s> m(new_model(ctx, p));
     if (!m) return fail(QFCA_E_NOMEM, "model allocation failed");
@@ -776,71 +749,7 @@ qfca_status build_model(qfca_ctx ctx, const qfca_params* p, const double* mu, co
     return QFCA_OK;
 }
 
-// Serialised model: an 8-byte magic, u32 version, u32 flags (bit 0 integer
-// reference, bit 1 eigenvalues, bit 2 lo/hi, bit 3 general reference), the
-// parameters (C k B T as int32, q_lo q_hi sigma_s as float32, preproc
-// proj_prec as int32, then in version 2 sigma_p as float32 and reference as
-// int32), then mu [C] f64, V [C][k] f64 (residual models only), edges
-// [C][B-1] f32, delta [C] f64, and, by flag, cR [C][B] i32, eigenvalues [C]
-// f64, lo [C] f64, hi [C] f64 and the general reference weights [C][B] f64.
-// Host byte order.  Version 1 (no sigma_p, reference) is read with
-// sigma_p = INFINITY and the median -> quan reference.
-constexpr char kModelMagic[8] = {'Q', 'F', 'C', 'A', 'M', 'D', 'L', '\0'};
-constexpr uint32_t kModelVersion = 2;
-constexpr size_t kParamBytes[3] = {0, 40, 44};
-
-size_t model_header(uint32_t version) { return 8 + 4 + 4 + kParamBytes[version]; }
-
-struct ModelBlob {
-    size_t mu, V, edges, delta, cR, evals, lohi, cRw, total;
-};
-
-ModelBlob blob_sizes(const qfca_params& p, uint32_t flags, uint32_t version) {
-    ModelBlob z;
-    const size_t C = (size_t)p.C;
-    const size_t P = (size_t)planes(p);
-    z.mu = C * 8;
-    z.V = p.preproc != QFCA_PRE_NONE ? C * (size_t)p.k * 8 : 0;
-    z.edges = P * (size_t)(p.B > 1 ? p.B - 1 : 0) * 4;
-    z.delta = P * 8;
-    z.cR = (flags & 1u) ? P * (size_t)p.B * 4 : 0;
-    z.evals = (flags & 2u) ? C * 8 : 0;
-    z.lohi = (flags & 4u) ? P * 16 : 0;
-    z.cRw = (flags & 8u) ? P * (size_t)p.B * 8 : 0;
-    z.total = model_header(version) + z.mu + z.V + z.edges + z.delta + z.cR + z.evals + z.lohi + z.cRw;
-    return z;
-}
-
-void put_params(unsigned char* d, const qfca_params& p) {
-    const int32_t iv[4] = {p.C, p.k, p.B, p.T};
-    const float fv[3] = {p.q_lo, p.q_hi, p.sigma_s};
-    const int32_t jv[2] = {p.preproc, p.proj_prec};
-    memcpy(d, iv, 16);
-    memcpy(d + 16, fv, 12);
-    memcpy(d + 28, jv, 8);
-    memcpy(d + 36, &p.sigma_p, 4);
-    memcpy(d + 40, &p.reference, 4);
-}
-
-qfca_params get_params(const unsigned char* d, uint32_t version) {
-    int32_t iv[4];
-    float fv[3];
-    int32_t jv[2];
-    memcpy(iv, d, 16);
-    memcpy(fv, d + 16, 12);
-    memcpy(jv, d + 28, 8);
-    qfca_params p{};
-    p.C = iv[0]; p.k = iv[1]; p.B = iv[2]; p.T = iv[3];
-    p.q_lo = fv[0]; p.q_hi = fv[1]; p.sigma_s = fv[2];
-    p.preproc = jv[0]; p.proj_prec = jv[1];
-    p.sigma_p = INFINITY;
-    p.reference = QFCA_REF_MEDIAN_QUAN;
-    if (version >= 2) {
-        memcpy(&p.sigma_p, d + 36, 4);
-        memcpy(&p.reference, d + 40, 4);
-    }
-    return p;
-}
+// The serialised model format is described in qfca_blob.h.
 
 }  // namespace
 
@@ -861,100 +770,60 @@ qfca_status qfca_model_export(qfca_model m, void* host_buf, size_t* inout_bytes)
     if (!m || !inout_bytes) return fail(QFCA_E_ARG, "NULL argument");
     const uint32_t flags = ((m->has_ref && !m->ref_general) ? 1u : 0u) | (m->has_evals ? 2u : 0u) |
                            (m->has_lohi ? 4u : 0u) | ((m->has_ref && m->ref_general) ? 8u : 0u);
-    const ModelBlob z = blob_sizes(m->p, flags, kModelVersion);
+    const size_t total = blob_bytes(m->p, flags);
     if (!host_buf) {
-        *inout_bytes = z.total;
+        *inout_bytes = total;
         return QFCA_OK;
     }
-    if (*inout_bytes < z.total) {
-        *inout_bytes = z.total;
+    if (*inout_bytes < total) {
+        *inout_bytes = total;
         return fail(QFCA_E_ARG, "buffer smaller than the serialised model");
     }
-    unsigned char* d = (unsigned char*)host_buf;
-    memcpy(d, kModelMagic, 8);
-    memcpy(d + 8, &kModelVersion, 4);
-    memcpy(d + 12, &flags, 4);
-    put_params(d + 16, m->p);
-    size_t o = model_header(kModelVersion);
-    auto put = [&](const void* src, size_t n) {
-        if (n) memcpy(d + o, src, n);
-        o += n;
-    };
-    std::vector<double> mu(m->p.C, 0.0);
-    for (int c = 0; c < m->p.C && c < (int)m->mu.size(); ++c) mu[c] = m->mu[c];
-    put(mu.data(), z.mu);
-    put(m->V.data(), z.V);
-    put(m->edges.data(), z.edges);
-    put(m->delta.data(), z.delta);
-    put(m->cR.data(), z.cR);
-    put(m->evals.data(), z.evals);
-    if (z.lohi) {
-        put(m->lo.data(), z.lohi / 2);
-        put(m->hi.data(), z.lohi / 2);
+    ModelArrays a;
+    a.p = m->p;
+    a.flags = flags;
+    a.mu.assign(m->p.C, 0.0);
+    for (int c = 0; c < m->p.C && c < (int)m->mu.size(); ++c) a.mu[c] = m->mu[c];
+    a.V = m->V;
+    a.edges = m->edges;
+    a.delta = m->delta;
+    if (flags & 1u) a.cR = m->cR;
+    if (flags & 2u) a.evals = m->evals;
+    if (flags & 4u) {
+        a.lo = m->lo;
+        a.hi = m->hi;
     }
-    put(m->cRw.data(), z.cRw);
-    *inout_bytes = z.total;
+    if (flags & 8u) a.cRw = m->cRw;
+    blob_write(a, (unsigned char*)host_buf);
+    *inout_bytes = total;
     return QFCA_OK;
 }
 
 qfca_status qfca_model_import(qfca_ctx ctx, const void* host_buf, size_t bytes, qfca_model* out) {
     if (!ctx || !host_buf || !out) return fail(QFCA_E_ARG, "NULL argument");
     *out = nullptr;
-    const unsigned char* d = (const unsigned char*)host_buf;
-    if (bytes < model_header(1) || memcmp(d, kModelMagic, 8) != 0) return fail(QFCA_E_ARG, "not a serialised model");
-    uint32_t version = 0, flags = 0;
-    memcpy(&version, d + 8, 4);
-    memcpy(&flags, d + 12, 4);
-    if (version < 1 || version > kModelVersion) return fail(QFCA_E_UNSUPPORTED, "unknown model format version");
-    if (bytes < model_header(version)) return fail(QFCA_E_ARG, "not a serialised model");
-    if (flags & ~15u) return fail(QFCA_E_ARG, "unknown model flags");
-    if ((flags & 1u) && (flags & 8u)) return fail(QFCA_E_ARG, "two references in one model");
-    const qfca_params p = get_params(d + 16, version);
-    qfca_status st = check_params(&p);
-    if (st != QFCA_OK) return st;
-    const ModelBlob z = blob_sizes(p, flags, version);
-    if (bytes != z.total) return fail(QFCA_E_ARG, "byte count does not match the serialised model");
-    size_t o = model_header(version);
-    auto take = [&](size_t n) {
-        const unsigned char* q = d + o;
-        o += n;
-        return q;
-    };
-    const size_t C = (size_t)p.C;
-    std::vector<double> mu(C), V(z.V / 8), delta(z.delta / 8), evals(z.evals / 8), lo(z.lohi / 16), hi(z.lohi / 16);
-    std::vector<float> edges(z.edges / 4);
-    std::vector<int32_t> cR(z.cR / 4);
-    memcpy(mu.data(), take(z.mu), z.mu);
-    if (z.V) memcpy(V.data(), take(z.V), z.V);
-    if (z.edges) memcpy(edges.data(), take(z.edges), z.edges);
-    memcpy(delta.data(), take(z.delta), z.delta);
-    if (z.cR) memcpy(cR.data(), take(z.cR), z.cR);
-    if (z.evals) memcpy(evals.data(), take(z.evals), z.evals);
-    if (z.lohi) {
-        memcpy(lo.data(), take(z.lohi / 2), z.lohi / 2);
-        memcpy(hi.data(), take(z.lohi / 2), z.lohi / 2);
+    ModelArrays a;
+    {
+        std::string err;
+        const qfca_status st = blob_read(host_buf, bytes, &a, &err);
+        if (st != QFCA_OK) return fail(st, err);
     }
-    std::vector<double> cRw(z.cRw / 8);
-    if (z.cRw) memcpy(cRw.data(), take(z.cRw), z.cRw);
+    const bool pca = a.p.preproc != QFCA_PRE_NONE;
     qfca_model m = nullptr;
-    st = build_model(ctx, &p, mu.data(), z.V ? V.data() : nullptr, z.edges ? edges.data() : nullptr, delta.data(),
-                     z.cR ? cR.data() : nullptr, z.lohi ? lo.data() : nullptr, &m);
+    qfca_status st = build_model(ctx, &a.p, a.mu.data(), pca ? a.V.data() : nullptr,
+                                 a.edges.empty() ? nullptr : a.edges.data(), a.delta.data(),
+                                 a.cR.empty() ? nullptr : a.cR.data(), a.lo.empty() ? nullptr : a.lo.data(), &m);
     if (st != QFCA_OK) return st;
-    if (z.evals) {
-        m->evals = evals;
+    if (a.flags & 2u) {
+        m->evals = a.evals;
         m->has_evals = true;
     }
-    if (z.lohi) {
-        m->hi = hi;
+    if (a.flags & 4u) {
+        m->hi = a.hi;
         m->has_lohi = true;
     }
-    if (z.cRw) {
-        for (size_t i = 0; i < cRw.size(); ++i)
-            if (!std::isfinite(cRw[i]) || cRw[i] < 0.0 || (i % p.B && cRw[i] < cRw[i - 1])) {
-                delete m;
-                return fail(QFCA_E_ARG, "malformed reference weights");
-            }
-        if ((st = set_reference_weights(m, cRw.data())) != QFCA_OK) {
+    if (a.flags & 8u) {
+        if ((st = set_reference_weights(m, a.cRw.data())) != QFCA_OK) {
             delete m;
             return st;
         }

@@ -548,9 +548,11 @@ struct PArgs {
     float* resid;
 };
 
+// bin = #{m : rr >= e[m]} for the channel's ascending edges e: a guess from
+// (rr - lo) / delta corrected edge by edge (a zero-width channel, idl = 0,
+// has no guess and walks the edges from bin 0).
 __device__ __forceinline__ int bin_of(float rr, const float* __restrict__ e, float lo, float idl, int B) {
-    if (idl == 0.f) return 0;
-    int b = (int)floorf((rr - lo) * idl);
+    int b = idl == 0.f ? 0 : (int)floorf((rr - lo) * idl);
     b = b < 0 ? 0 : (b > B - 1 ? B - 1 : b);
     while (b > 0 && rr < e[b - 1]) --b;
     while (b < B - 1 && rr >= e[b]) ++b;

@@ -20,12 +20,13 @@
 //           = Phi(a_{j-1}) + Phi(a_j) - 2 Phi(s) + j (2 s - a_{j-1} - a_j),
 //     s = clamp(c_{j-1}, a_{j-1}, a_j).  This is exactly what the two-pointer
 //     loop of Alg. 1 accumulates; e_j = I_j / (P_j m) in bin units.
-//   * e is summed over the T patch columns around each output column (a
-//     double-precision running sum in this generic kernel, whose bits
-//     therefore follow the strip's start; the block-walk kernel k_score_t
-//     sums in an order fixed by the image columns), and the result for the
-//     pixel's own bin is gathered across lanes and added to the pixel's
-//     accumulator for each of the T patch rows that cover it.
+//   * e is summed over the T patch columns around each output column (in
+//     this generic kernel each window sum is formed afresh, in image-column
+//     order, in double precision; the block-walk kernel k_score_t sums in an
+//     order fixed by the image columns too, so either kernel's maps are the
+//     same for every tiling), and the result for the pixel's own bin is
+//     gathered across lanes and added to the pixel's accumulator for each of
+//     the T patch rows that cover it (rows in image order).
 // All counts are exact integers; each per-channel value is rounded once to
 // 64-bit fixed point and added to the channel sum with an integer atomic
 // (order-free); k_finish turns the sum into the channel mean and blurs it.

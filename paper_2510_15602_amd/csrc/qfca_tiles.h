@@ -822,8 +822,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 
 __device__ __forceinline__ int bin_of_m(float rr, const float* __restrict__ e, float lo, float idl, int B) {
-    if (idl == 0.f) return 0;
-    int b = (int)floorf((rr - lo) * idl);
+    int b = idl == 0.f ? 0 : (int)floorf((rr - lo) * idl);  // zero width: walk from bin 0
     b = b < 0 ? 0 : (b > B - 1 ? B - 1 : b);
     while (b > 0 && rr < e[b - 1]) --b;
     while (b < B - 1 && rr >= e[b]) ++b;
@@ -832,10 +831,10 @@ __device__ __forceinline__ int bin_of_m(float rr, const float* __restrict__ e, f
 
 // bin = #{m : rr >= e[m]} (B >= 2): the arithmetic guess from (rr - lo) / delta
 // is checked against its two neighbouring edges (read together); only when
-// that moves it is the search continued edge by edge.
+// that moves it is the search continued edge by edge.  A zero-width channel
+// (idl = 0) starts the search at bin 0.
 __device__ __forceinline__ int bin_fast(float rr, const float* __restrict__ e, float lo, float idl, int B) {
-    if (idl == 0.f) return 0;
-    int b = (int)floorf((rr - lo) * idl);
+    int b = idl == 0.f ? 0 : (int)floorf((rr - lo) * idl);
     b = b < 0 ? 0 : (b > B - 1 ? B - 1 : b);
     const float el = e[b > 0 ? b - 1 : 0];
     const float eh = e[b < B - 1 ? b : B - 2];

@@ -85,6 +85,40 @@ def test_bins_of_values_on_edges(ctx, C, prec, grid, H, W):
     say(f"[edges] C={C} prec={prec} grid={grid} {H}x{W}: {g.size} bins exact")
 
 
+@pytest.mark.parametrize("path", ["valu", "fp32", "bf16", "bf16_wide"])
+def test_zero_width_channel(ctx, path):
+    """A channel of zero width (delta = 0, every edge at one value) still
+    takes #{m : r >= e_m}: bin 0 below the edge value, B - 1 at or above it,
+    on the VALU projection, the MFMA projections and the wide BF16 kernel."""
+    C = 300 if path == "bf16_wide" else 8
+    B, H, W = 16, 9, 20
+    rng = np.random.Generator(np.random.PCG64(77))
+    lo = rng.uniform(-2, -1, C)
+    delta = rng.uniform(0.1, 0.2, C)
+    edges = np.stack([(lo[c] + delta[c] * np.arange(1, B)).astype(np.float32) for c in range(C)])
+    z = 3  # the zero-width channel
+    delta[z] = 0.0
+    edges[z] = np.float32(0.5)
+    X = rng.uniform(-3, 3, (C, H, W)).astype(np.float32)
+    X[z] = rng.choice(np.array([0.25, 0.5, 0.75, np.nextafter(np.float32(0.5), np.float32(0))], np.float32),
+                      (H, W))
+    if path == "valu":
+        prm = q.Params.make(C=C, k=0, B=B, T=3, preproc=q.QFCA_PRE_NONE)
+        mu, V = None, None
+    else:
+        k = 1 if path == "fp32" else min(32, C - 1)
+        prec = q.QFCA_PREC_FP32 if path == "fp32" else q.QFCA_PREC_BF16
+        prm = q.Params.make(C=C, k=k, B=B, T=3, proj_prec=prec)
+        mu, V = np.zeros(C, np.float32), np.zeros((C, k), np.float32)
+    cR = np.full((C, B), 9, np.int32)
+    m = q.qfca_model_create(ctx, prm, mu, V, edges, delta, cR)
+    bins, _ = q.qfca_quantize(ctx, m, torch.from_numpy(X).cuda())
+    torch.cuda.synchronize()
+    g = bins.cpu().numpy()
+    for c in range(C):
+        np.testing.assert_array_equal(g[c], np.searchsorted(edges[c], X[c], side="right"), err_msg=f"channel {c}")
+
+
 @pytest.mark.parametrize("C,k,H,W", [(512, 64, 48, 80), (512, 32, 33, 47), (300, 50, 20, 31)],
                          ids=["C512_k64", "C512_k32_ragged", "C300_k50"])
 def test_bf16_projection_wide(ctx, C, k, H, W):
