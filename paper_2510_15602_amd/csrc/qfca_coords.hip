@@ -207,6 +207,177 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     coords_body<CMAX, KT, BF>(a);
 }
 
+// Whole-tile kernel for 512 channels in BF16: every wavefront computes the
+// full Z of its own 16-pixel tiles (all channels, so no partials are added
+// across wavefronts and the tile loop has no barrier), sixteen wavefronts
+// per block (four per SIMD) share the operand table and the parameters in
+// LDS, and a block's wavefronts take interleaved tiles of one contiguous run.
+// The centred features are not needed after the product, so they stream
+// through a ring of PF + 1 register groups: step s + PF is loaded while step
+// s is multiplied.  Lane (g, n) ends with components 16 kt + 4 g + v of pixel
+// n; the bins of those four consecutive components are packed in a dword,
+// byte-transposed across each lane quad and written four pixels per dword.
+// LDS: mu [CMAX]; lo, 1/delta, margin [64] each; the operand table.
+// CS_WAVES wavefronts per block, CS_BLOCKS blocks per compute unit (four
+// wavefronts per SIMD; two blocks of ten, five per SIMD, ran no faster and
+// spilled).
+constexpr int CS_WAVES = 16, CS_BLOCKS = 1;
+__host__ __device__ inline size_t cs_lds(int CMAX, int KT) {
+    return (size_t)4 * CMAX + 3 * 64 * 4 + (size_t)CMAX * KT * 16 * 2;
+}
+
+template <int CMAX, int KT, int NW, int WPE>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_coords_solo(MArgs a) {
+    constexpr int NS = CMAX / 32;        // product K steps (32 channels each)
+    constexpr int VSZ = CMAX * KT * 16;  // bf16 table elements
+    constexpr int PF = 4;                // steps of features in flight ahead
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float* smu = (float*)lds_raw;
+    float* slo = smu + CMAX;
+    float* sid = slo + 64;
+    float* sfd = sid + 64;
+    bf16x8* stab = (bf16x8*)(lds_raw + 4 * CMAX + 3 * 64 * 4);
+    for (int i = threadIdx.x; i < CMAX; i += blockDim.x) {
+        const float vm = i < a.C ? a.mu[i] : 0.f;
+        smu[i] = vm;
+    }
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+        const bool ok = i < a.k;
+        const float vl = ok && a.lo ? a.lo[i] : 0.f;
+        const float vi = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
+        const float vf = ok && a.fastd ? a.fastd[i] : 1.f;
+        slo[i] = vl;
+        sid[i] = vi;
+        sfd[i] = vf;
+    }
+    {
+        constexpr int NUNIT = VSZ / 8;
+        const uint4* src = (const uint4*)a.V1;
+        uint4* dst = (uint4*)stab;
+        for (int u0 = threadIdx.x; u0 < NUNIT; u0 += 4 * 64 * NW) {
+            uint4 t[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (u0 + 64 * NW * i < NUNIT) t[i] = src[u0 + 64 * NW * i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (u0 + 64 * NW * i < NUNIT) dst[u0 + 64 * NW * i] = t[i];
+        }
+    }
+    __syncthreads();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int per = ((a.ntiles + (int)gridDim.x - 1) / (int)gridDim.x + NW - 1) / NW * NW;
+    const int b0 = (int)blockIdx.x * per;
+    const int tend = min(a.ntiles, b0 + per);
+    const bool rows_dw = ((a.N & 3) == 0) && (((uintptr_t)a.bins & 3) == 0);
+    for (int tile = b0 + w; tile < tend; tile += NW) {
+        // lane index and bases opaque per tile (nothing lane- or base-derived
+        // is hoisted out of the loop into registers)
+        int lane = threadIdx.x & 63;
+        asm volatile("" : "+v"(lane));
+        const float* Xt = a.X;
+        float* Rt = a.resid;
+        uint8_t* Bt = a.bins;
+        const float* Et = a.edges;
+        asm volatile("" : "+s"(Xt), "+s"(Rt), "+s"(Bt), "+s"(Et));
+        const int g = lane >> 4, n = lane & 15, p = n & 3, qd = n >> 2;
+        const uint32_t selA = (p & 1) ? 0x07030501u : 0x02060004u;
+        const uint32_t selB = (p & 2) ? 0x07060302u : 0x01000504u;
+        const int px = tile * 16 + n;
+        const bool pxok = px < a.N;
+        const int pxc = pxok ? px : a.N - 1;
+        // channel 32 s + t + 8 g of pixel pxc: the uniform row base of channel
+        // 32 s + t plus the lane's 32-bit byte offset (channels past C read a
+        // real row; their table rows are zero)
+        const uint32_t voff = ((uint32_t)(8 * g) * (uint32_t)a.N + (uint32_t)pxc) * 4u;
+        const uint32_t voff0 = (uint32_t)pxc * 4u;
+        float ring[PF + 1][8];
+        auto load = [&](auto sc) __attribute__((always_inline)) {
+            constexpr int s = decltype(sc)::value;
+            if constexpr (s < NS) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int cu = 32 * s + t;
+                    const char* rb = (const char*)(Xt + (size_t)(cu < a.C ? cu : a.C - 1) * a.N);
+                    ring[s % (PF + 1)][t] = *(const float*)(rb + (cu + 8 * g < a.C ? voff : voff0));
+                }
+            }
+        };
+        StaticFor<0, PF>::run(load);
+        const bf16x8* V1 = opaque_lds((const bf16x8*)stab);
+        const float* mu = opaque_lds((const float*)smu);
+        floatx4 z[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) z[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        auto step = [&](auto sc) __attribute__((always_inline)) {
+            constexpr int s = decltype(sc)::value;
+            load(std::integral_constant<int, s + PF>{});
+            const float4 m0 = *(const float4*)(mu + 32 * s + 8 * g);
+            const float4 m1 = *(const float4*)(mu + 32 * s + 8 * g + 4);
+            const float mv[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+            bf16x8 bv;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) bv[t] = (__bf16)(ring[s % (PF + 1)][t] - mv[t]);
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+                z[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V1[((s * KT + kt) * 4 + g) * 16 + n], bv, z[kt], 0,
+                                                                0, 0);
+        };
+        StaticFor<0, NS>::run(step);
+        const float* plo = opaque_lds((const float*)slo);
+        const float* pid = opaque_lds((const float*)sid);
+        const float* pfd = opaque_lds((const float*)sfd);
+        const int B = a.B;
+        const float top = (float)max(B - 1, 0);
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            const int j0 = 16 * kt + 4 * g;  // components j0 .. j0 + 3 of pixel px
+            if (Rt) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (pxok && j0 + v < a.k) Rt[(size_t)(j0 + v) * a.N + px] = z[kt][v];
+            }
+            if (!Bt) continue;
+            const float4 l4 = *(const float4*)(plo + j0);
+            const float4 i4 = *(const float4*)(pid + j0);
+            const float4 f4 = *(const float4*)(pfd + j0);
+            const float lov[4] = {l4.x, l4.y, l4.z, l4.w};
+            const float idv[4] = {i4.x, i4.y, i4.z, i4.w};
+            const float dlv[4] = {f4.x, f4.y, f4.z, f4.w};
+            uint32_t bq[4];
+            uint32_t need = 0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float tt = (z[kt][v] - lov[v]) * idv[v];
+                const float near = __builtin_amdgcn_fmed3f(rintf(tt), 1.f, top);
+                const bool dec = (fabsf(tt - near) >= dlv[v]) & (dlv[v] < 0.5f) & (idv[v] != 0.f);
+                bq[v] = (uint32_t)__builtin_amdgcn_fmed3f(floorf(tt), 0.f, top);
+                need |= ((!dec) & pxok & (j0 + v < a.k) & (B > 1)) ? (1u << v) : 0u;
+            }
+            if (__ballot(need != 0u)) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (need & (1u << v))
+                        bq[v] = (uint32_t)bin_fast(z[kt][v], Et + (size_t)(j0 + v) * (B - 1), lov[v], idv[v], B);
+            }
+            const uint32_t tr = quad_transpose_bytes(bq[0] | (bq[1] << 8) | (bq[2] << 16) | (bq[3] << 24), selA, selB);
+            // lane (g, 4 qd + p): component j0' + p, pixels 4 qd .. 4 qd + 3
+            const int jw = 16 * kt + 4 * g + p;
+            const int pw = tile * 16 + 4 * qd;
+            if (jw < a.k) {
+                uint8_t* dst = Bt + (size_t)jw * a.N + pw;
+                if (rows_dw && pw + 3 < a.N) {
+                    *(uint32_t*)dst = tr;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (pw + i < a.N) dst[i] = (uint8_t)(tr >> (8 * i));
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_coords(const ProjLaunch& L, hipStream_t st) {
@@ -219,6 +390,26 @@ hipError_t launch_coords(const ProjLaunch& L, hipStream_t st) {
     a.bins = L.bins; a.resid = L.resid;
     a.ntiles = (L.N + 15) / 16;
     const bool bf = L.prec == QFCA_PREC_BF16;
+    if (bf && CM == 512 && (KT == 2 || KT == 4) && (unsigned long long)L.N * 100ULL < (1ULL << 32)) {
+        // whole tiles per wavefront (32-bit lane offsets of the feature loads)
+        int ncu = 0, dev0 = 0;
+        hipError_t e0 = hipGetDevice(&dev0);
+        if (e0 != hipSuccess) return e0;
+        if ((e0 = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev0)) != hipSuccess) return e0;
+        const size_t lds = cs_lds(CM, KT);
+        constexpr int NW = CS_WAVES;
+        constexpr int WPE = NW * CS_BLOCKS / 4;
+        const void* kf =
+            KT == 4 ? (const void*)k_coords_solo<512, 4, NW, WPE> : (const void*)k_coords_solo<512, 2, NW, WPE>;
+        if ((e0 = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+            return e0;
+        const int blocks = std::max(1, std::min((a.ntiles + NW - 1) / NW, ncu * CS_BLOCKS));
+        if (KT == 4)
+            hipLaunchKernelGGL((k_coords_solo<512, 4, NW, WPE>), dim3(blocks), dim3(64 * NW), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_coords_solo<512, 2, NW, WPE>), dim3(blocks), dim3(64 * NW), lds, st, a);
+        return hipGetLastError();
+    }
     const size_t lds = co_lds(CM, KT, bf ? 2 : 4);
     if (lds > CO_LDS_MAX) return hipErrorInvalidValue;
     static std::atomic<int> ncu_cache[64];

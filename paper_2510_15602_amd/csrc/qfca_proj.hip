@@ -24,7 +24,6 @@
 // The subtraction, the comparisons with the edges and all counting stay FP32.
 #include <algorithm>
 #include <atomic>
-#include <type_traits>
 
 #include "qfca_internal.h"
 #include "qfca_tiles.h"
@@ -270,33 +269,6 @@ __global__ __launch_bounds__(256) void k_proj_bf16_mfma_wide(MArgs a) {
 #endif
 __host__ __device__ inline size_t solo_lds(int CMAX, int KT) {
     return (size_t)16 * CMAX + (size_t)2 * CMAX * KT * 16 * 2;
-}
-
-// Calls f(std::integral_constant<int, S>) for S = I .. N - 1 in order: an
-// unrolled loop whose index is a constant in every copy of the body (a body
-// too large for the loop unroller would otherwise index register arrays at
-// run time, which puts them in scratch memory).
-template <int I, int N>
-struct StaticFor {
-    template <class F>
-    __device__ __forceinline__ static void run(F& f) {
-        f(std::integral_constant<int, I>{});
-        StaticFor<I + 1, N>::run(f);
-    }
-};
-template <int N>
-struct StaticFor<N, N> {
-    template <class F>
-    __device__ __forceinline__ static void run(F&) {}
-};
-
-// Transposes the 4x4 bytes of a lane quad: lane p's byte v becomes lane v's
-// byte p.
-__device__ __forceinline__ uint32_t quad_transpose_bytes(uint32_t d, uint32_t selA, uint32_t selB) {
-    const uint32_t pa = (uint32_t)__builtin_amdgcn_mov_dpp((int)d, 0xB1, 0xf, 0xf, false);  // lane p ^ 1
-    const uint32_t a1 = __builtin_amdgcn_perm(d, pa, selA);
-    const uint32_t pb = (uint32_t)__builtin_amdgcn_mov_dpp((int)a1, 0x4E, 0xf, 0xf, false);  // lane p ^ 2
-    return __builtin_amdgcn_perm(a1, pb, selB);
 }
 
 template <int CMAX, int KT, int NW>

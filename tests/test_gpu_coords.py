@@ -83,6 +83,37 @@ def test_coords_score_against_oracle(ctx, case):
     assert torch.equal(o0.w1, out.w1)
 
 
+@pytest.mark.parametrize("C,k,H,W", [(512, 64, 40, 48), (500, 30, 37, 41), (512, 17, 9, 12)],
+                         ids=["C512_k64", "C500_k30_ragged", "C512_k17_one_tile"])
+def test_coords_bf16_wide(ctx, C, k, H, W):
+    """BF16 coordinates of the widest maps (C > 256: every wavefront owns
+    whole tiles): z within the BF16 operand rounding of the oracle's, and the
+    bins exactly #{m : z >= e_m} of the GPU's own z, four pixels per dword
+    store (byte stores where a row is not whole dwords)."""
+    say(f"[coords bf16 wide] C={C} k={k} {H}x{W}")
+    t = qfca_synth.make_texture(C, H, W, 4200 + k, anomalies=[])
+    B, T = 16, 5
+    rng = np.random.Generator(np.random.PCG64(4300 + k))
+    V, _ = np.linalg.qr(rng.standard_normal((C, k)))  # any orthonormal basis serves
+    mu = t.X.reshape(C, -1).mean(1).astype(np.float32)
+    V32 = V.astype(np.float32)
+    Z = oracle.project(t.X, mu.astype(np.float64), V32.astype(np.float64))
+    _, _, delta, edges = oracle.edges(Z, B)
+    cR = np.full((k, B), 0, np.int32)
+    cR[:, -1] = T * T
+    prm = q.Params.make(C=C, k=k, B=B, T=T, preproc=q.QFCA_PRE_COORDS, proj_prec=q.QFCA_PREC_BF16)
+    m = q.qfca_model_create(ctx, prm, mu, V32, edges, delta, cR)
+    gb, gz = q.qfca_quantize(ctx, m, torch.from_numpy(t.X).cuda(), resid=True)
+    torch.cuda.synchronize()
+    gz, gb = gz.cpu().numpy(), gb.cpu().numpy()
+    assert gb.shape == (k, H, W)
+    scale = np.abs(t.X.astype(np.float64) - mu[:, None, None]).max() * np.sqrt(C)
+    assert np.abs(gz - Z).max() <= 0.02 * scale
+    for j in range(k):
+        np.testing.assert_array_equal(gb[j], np.searchsorted(edges[j], gz[j], side="right"),
+                                      err_msg=f"component {j}")
+
+
 def test_coords_tile_independent(ctx):
     C, k, H, W, B, T = 64, 16, 70, 81, 16, 9
     t = qfca_synth.make_texture(C, H, W, 4100, anomalies=[("shift", 4, 10)])

@@ -390,7 +390,10 @@ def test_quantize_bf16_flip_rate_256(ctx, oracle_256):
     ref = oracle.score(obins, p["T"], p["B"], om.cR, om.delta, 1.0)
     err = np.abs(out.score.cpu().numpy() - ref.score).max() / np.abs(ref.score).max()
     say(f"  bf16 flip rate {flips:.4%}, max score error {err:.3e} of max score")
-    assert flips < 0.05 and err < 0.05
+    # measured on MI355X: 1.1% of bins and 0.2% of the maximum score; the
+    # bounds leave a factor of about two (flips) and five (score) for other
+    # seeds of the same workload
+    assert flips < 0.02 and err < 0.01
 
 
 def test_fit_with_fewer_pixels_than_channels(ctx):
