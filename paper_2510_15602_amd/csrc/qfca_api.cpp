@@ -881,8 +881,7 @@ qfca_status qfca_fit_reference(qfca_ctx ctx, qfca_model m, const uint8_t* bins, 
     }
     int32_t* dcR = nullptr;
     HIP_TRY(scratch(ctx, SL_CR, (size_t)C * B * 4, &dcR));
-    HIP_TRY(launch_refcount(bins, C, H, W, T, B, counts, ctx->stream));
-    HIP_TRY(launch_refselect(counts, C, B, mm, (P + 1) / 2, dcR, ctx->stream));
+    HIP_TRY(launch_refmedian(bins, C, H, W, T, B, counts, (P + 1) / 2, dcR, ctx->stream));
     m->cR.assign((size_t)C * B, 0);
     HIP_TRY(hipMemcpyAsync(m->cR.data(), dcR, (size_t)C * B * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));

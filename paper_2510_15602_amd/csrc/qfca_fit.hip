@@ -192,7 +192,13 @@ struct RArgs {
     const uint8_t* bins;
     int C, H, W, T, B, Bp, S, r, m, Ws, Hb, nsplit;
     int perbin;  // 1: count the windows' bin counts P(j) instead of their cumulative counts cP(j)
-    uint32_t* counts;
+    // what a window's count v in [0, m] adds to: mode 0 its own counter v
+    // (mcnt = m); mode 1 the counter v >> sh (coarse pass of a median,
+    // mcnt = m >> sh); mode 2, only when v >> sh equals sel[c][j], the
+    // counter v & (2^sh - 1) (fine pass, mcnt = 2^sh - 1)
+    int mode, sh, mcnt;
+    const int32_t* sel;
+    uint32_t* counts;  // [C][B][mcnt + 1]
 };
 
 __host__ __device__ inline size_t ralign16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -228,7 +234,9 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
     const int per = Bp / a.nsplit;
     const int jlo = split * per;
     const bool counting = cv && (j < a.B) && (j >= jlo) && (j < jlo + per);
-    const RefLayout L(a.Ws, r, S, per, m);
+    const int mcnt = a.mcnt;
+    const int selj = (a.mode == 2 && counting) ? a.sel[(size_t)c * a.B + j] : -1;
+    const RefLayout L(a.Ws, r, S, per, mcnt);
     const int WbP = L.WbP;
     const int Wb = ws + 2 * r;  // bin columns [x0-r, xe+r)
     const int xb0 = x0 - r;
@@ -372,8 +380,10 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
                     // (the exchange runs in every lane, outside any branch:
                     // a lane with execution off would give 0 to its neighbour)
                     const int pv = lane_prev(cP);
-                    const int cu = a.perbin ? cP - (j == 0 ? 0 : pv) : cP;
-                    if (counting && q < Wb && q >= T - 1 && px >= pxlo && px < pxhi)
+                    const int cv0 = a.perbin ? cP - (j == 0 ? 0 : pv) : cP;
+                    const int cu = a.mode == 0 ? cv0 : (a.mode == 1 ? cv0 >> a.sh : cv0 & ((1 << a.sh) - 1));
+                    const bool take = a.mode != 2 || (cv0 >> a.sh) == selj;
+                    if (counting && take && q < Wb && q >= T - 1 && px >= pxlo && px < pxhi)
                         atomicAdd(mycnt + (cu >> 1), 1u << ((cu & 1) << 4));
                 }
             }
@@ -387,9 +397,9 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
         const int cc = cbase + ss;
         const uint32_t v = cnt[t];
         if (v && cc < a.C && jj < a.B) {
-            uint32_t* dst = a.counts + ((size_t)cc * a.B + jj) * (m + 1) + 2 * w;
+            uint32_t* dst = a.counts + ((size_t)cc * a.B + jj) * (mcnt + 1) + 2 * w;
             if (v & 0xFFFFu) atomicAdd(dst, v & 0xFFFFu);
-            if ((v >> 16) && 2 * w + 1 <= m) atomicAdd(dst + 1, v >> 16);
+            if ((v >> 16) && 2 * w + 1 <= mcnt) atomicAdd(dst + 1, v >> 16);
         }
     }
 }
@@ -532,6 +542,43 @@ __global__ void k_refselect(const uint32_t* __restrict__ counts, int C, int B, i
     cR[t] = v;
 }
 
+// Two-pass median, pass 1: for every (channel, bin), the coarse bucket
+// (count >> sh) that holds the h-th largest window count, and that count's
+// rank among the bucket's windows (counted from the top).
+__global__ void k_refsel_coarse(const uint32_t* __restrict__ counts, int C, int B, int nb, long long h,
+                                int32_t* __restrict__ sel, long long* __restrict__ hrem) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * B) return;
+    const uint32_t* cnt = counts + (size_t)t * nb;
+    long long seen = 0;
+    int b = nb - 1;
+    for (; b > 0; --b) {
+        if (seen + cnt[b] >= h) break;
+        seen += cnt[b];
+    }
+    sel[t] = b;
+    hrem[t] = h - seen;
+}
+
+// Pass 2: the h'-th largest of the counts in the selected bucket, from the
+// bucket's fine table (count & (2^sh - 1)).
+__global__ void k_refsel_fine(const uint32_t* __restrict__ counts, int C, int B, int sh,
+                              const int32_t* __restrict__ sel, const long long* __restrict__ hrem,
+                              int32_t* __restrict__ cR) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * B) return;
+    const int nf = 1 << sh;
+    const uint32_t* cnt = counts + (size_t)t * nf;
+    const long long h = hrem[t];
+    long long seen = 0;
+    int v = nf - 1;
+    for (; v > 0; --v) {
+        seen += cnt[v];
+        if (seen >= h) break;
+    }
+    cR[t] = (sel[t] << sh) + v;
+}
+
 // ------------------------------------------------------------------------
 // Projection + quantisation, FP32 on the vector ALUs: one thread per pixel;
 // z = V^T (x - mu) (KP accumulators, V zero-padded to KP columns), then
@@ -625,8 +672,12 @@ hipError_t launch_select(const float* vals, int C, long N, const long long* rank
     return hipGetLastError();
 }
 
-hipError_t launch_refcount(const uint8_t* bins, int C, int H, int W, int T, int B,
-                           uint32_t* counts, hipStream_t st, int perbin) {
+// Count-table pass: mode, shift and selected buckets as in RArgs; counts
+// [C][B][mcnt + 1] is zeroed first.  nsplit_out (if given) receives the bin
+// splits the mode-0 table needs to fit in LDS.
+static hipError_t refcount_pass(const uint8_t* bins, int C, int H, int W, int T, int B, uint32_t* counts,
+                                hipStream_t st, int perbin, int mode, int sh, const int32_t* sel,
+                                int* nsplit_out, bool launch) {
     RArgs a;
     a.bins = bins; a.C = C; a.H = H; a.W = W; a.T = T; a.B = B;
     a.perbin = perbin;
@@ -634,21 +685,62 @@ hipError_t launch_refcount(const uint8_t* bins, int C, int H, int W, int T, int 
     while (Bp < B) Bp <<= 1;
     a.Bp = Bp;
     a.r = T / 2; a.m = T * T;
+    a.mode = mode; a.sh = sh; a.sel = sel;
+    a.mcnt = mode == 0 ? a.m : (mode == 1 ? (a.m >> sh) : (1 << sh) - 1);
     a.Ws = 64; a.Hb = 64;
     a.counts = counts;
-    hipError_t e = hipMemsetAsync(counts, 0, (size_t)C * B * (a.m + 1) * sizeof(uint32_t), st);
-    if (e != hipSuccess) return e;
     // channels per wave and bin splits so the private histograms fit in LDS;
     // a tile's counters are 16 bits wide
     if (a.Ws * a.Hb >= 65536) return hipErrorInvalidValue;
     int S = 64 / Bp, nsplit = 1;
-    auto lds = [&](int S_, int ns_) { return RefLayout(a.Ws, a.r, S_, Bp / ns_, a.m).total; };
+    auto lds = [&](int S_, int ns_) { return RefLayout(a.Ws, a.r, S_, Bp / ns_, a.mcnt).total; };
     while (lds(S, nsplit) > 60000 && S > 1) S >>= 1;
     while (lds(S, nsplit) > 60000 && nsplit < Bp) nsplit <<= 1;
     if (lds(S, nsplit) > 65536) return hipErrorInvalidValue;
+    if (nsplit_out) *nsplit_out = nsplit;
+    if (!launch) return hipSuccess;
+    hipError_t e = hipMemsetAsync(counts, 0, (size_t)C * B * (a.mcnt + 1) * sizeof(uint32_t), st);
+    if (e != hipSuccess) return e;
     a.S = S; a.nsplit = nsplit;
     dim3 grid((W + a.Ws - 1) / a.Ws, (H + a.Hb - 1) / a.Hb, ((C + S - 1) / S) * nsplit);
     hipLaunchKernelGGL(k_refcount, grid, dim3(64), lds(S, nsplit), st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_refcount(const uint8_t* bins, int C, int H, int W, int T, int B,
+                           uint32_t* counts, hipStream_t st, int perbin) {
+    return refcount_pass(bins, C, H, W, T, B, counts, st, perbin, 0, 0, nullptr, nullptr, true);
+}
+
+hipError_t launch_refmedian(const uint8_t* bins, int C, int H, int W, int T, int B, uint32_t* counts,
+                            long long h, int32_t* cR, hipStream_t st) {
+    const int m = T * T;
+    int nsplit = 1;
+    hipError_t e = refcount_pass(bins, C, H, W, T, B, counts, st, 0, 0, 0, nullptr, &nsplit, false);
+    if (e != hipSuccess) return e;
+    if (nsplit == 1) {
+        // the whole table of counts 0 .. m fits: one pass
+        if ((e = launch_refcount(bins, C, H, W, T, B, counts, st)) != hipSuccess) return e;
+        return launch_refselect(counts, C, B, m, h, cR, st);
+    }
+    // Two passes over the map with small tables instead of nsplit passes with
+    // the whole one: buckets of 2^sh counts (at most 64 buckets, 64 counts
+    // each), then the counts inside each (channel, bin)'s median bucket.
+    int sh = 0;
+    while ((m >> sh) + 1 > 64) ++sh;
+    const size_t n = (size_t)C * B;
+    // carved from the caller's table of n (m + 1) words (m + 1 > 128 here)
+    uint32_t* c1 = counts;
+    uint32_t* c2 = counts + n * 64;
+    int32_t* sel = (int32_t*)(counts + n * 128);
+    long long* hrem = (long long*)(counts + n * 130);  // 8-byte aligned: n * 130 words from an aligned base
+    if ((size_t)m + 1 < 134) return hipErrorInvalidValue;
+    if ((e = refcount_pass(bins, C, H, W, T, B, c1, st, 0, 1, sh, nullptr, nullptr, true)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_refsel_coarse, dim3((int)((n + 255) / 256)), dim3(256), 0, st, c1, C, B, (m >> sh) + 1, h,
+                       sel, hrem);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = refcount_pass(bins, C, H, W, T, B, c2, st, 0, 2, sh, sel, nullptr, true)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_refsel_fine, dim3((int)((n + 255) / 256)), dim3(256), 0, st, c2, C, B, sh, sel, hrem, cR);
     return hipGetLastError();
 }
 

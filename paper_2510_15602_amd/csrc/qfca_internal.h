@@ -198,6 +198,13 @@ hipError_t launch_refmean(const float* R, int C, int H, int W, int T, const floa
                           int32_t* cR, hipStream_t st);
 hipError_t launch_refselect(const uint32_t* counts, int C, int B, int m, long long h,
                             int32_t* cR, hipStream_t st);
+// The median -> quan reference in one call: cR [C][B] = the h-th largest
+// full-window cumulative count per (channel, bin).  counts: scratch of
+// C B (T^2 + 1) words.  One pass with the whole count table when it fits
+// in LDS, else a coarse pass (buckets of counts) and a fine pass inside each
+// (channel, bin)'s median bucket.
+hipError_t launch_refmedian(const uint8_t* bins, int C, int H, int W, int T, int B, uint32_t* counts,
+                            long long h, int32_t* cR, hipStream_t st);
 
 // Projection + quantisation.
 struct ProjLaunch {

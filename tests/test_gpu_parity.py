@@ -216,9 +216,13 @@ def test_integer_stages_exact_full_size(ctx, oracle_256):
 
 
 @pytest.mark.parametrize("case", [(3, 20, 17, 5, 6), (2, 64, 70, 7, 16), (2, 130, 100, 15, 32),
-                                  (1, 40, 45, 31, 64), (3, 9, 9, 9, 5), (2, 30, 30, 1, 7)],
+                                  (1, 40, 45, 31, 64), (3, 9, 9, 9, 5), (2, 30, 30, 1, 7),
+                                  (2, 70, 64, 21, 64), (3, 45, 50, 25, 48), (2, 64, 64, 31, 40)],
                          ids=lambda c: "C%d_H%d_W%d_T%d_B%d" % c)
 def test_reference_exact(ctx, case):
+    """The median -> quan reference from the GPU's window counts equals the
+    oracle's exactly (large T and B take the two-pass count: coarse buckets,
+    then the median bucket's counts)."""
     C, H, W, T, B = case
     say(f"[reference] C={C} H={H} W={W} T={T} B={B}")
     bins, delta, e, cR = rand_problem(100 + sum(case), C, H, W, T, B)
