@@ -604,6 +604,10 @@ def main():
     kernels["proj"]["hbm_gbs"] = round(proj_bytes / (proj_ms * 1e-3) / 1e9, 1)
     kernels["proj"]["hbm_frac"] = round(proj_bytes / (proj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
+    def done(what):
+        print(f"bench: {what} done", file=sys.stderr, flush=True)
+
+    done(f"single-image step ({ms_per_step:.3f} ms)")
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -617,21 +621,26 @@ def main():
                "kind": "oracle", "seconds": round(dt, 3),
                "sample": f"the full {H}x{W} image, C={C}: FP64 residual, quantisation and score "
                          f"(window counts, literal Alg. 1, direct association, direct blur)"}
+        done("cpu baseline")
 
     batched = None
     if args.batch_images > 0:
         batched = batched_leg(args, q, torch, np, dev)
         torch.cuda.empty_cache()
+        done("batched leg")
     proj_alone = variants = None
     if not args.no_extra:
         proj_alone = projection_leg(args, q, torch, np, dev)
         torch.cuda.empty_cache()
+        done("projection leg")
         variants = variants_leg(args, q, torch, np, dev)
         torch.cuda.empty_cache()
+        done("variants leg")
     large = None
     if args.large:
         large = large_leg(args, q, torch, np, dev)
         torch.cuda.empty_cache()
+        done("large batch leg")
     serving = None
     if args.serve_seconds > 0:
         serving = serving_leg(args, q, torch, np, dev, tile=batched["tile"] if batched else None)

@@ -229,6 +229,7 @@ __host__ __device__ inline size_t cs_lds(int CMAX, int KT) {
 template <int CMAX, int KT, int NW, int WPE>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_coords_solo(MArgs a) {
     constexpr int NS = CMAX / 32;        // product K steps (32 channels each)
+    constexpr int QS = NS / 4;           // K steps of one quarter (one wavefront's share in k_coords)
     constexpr int VSZ = CMAX * KT * 16;  // bf16 table elements
     constexpr int PF = 4;                // steps of features in flight ahead
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -306,11 +307,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
         StaticFor<0, PF>::run(load);
         const bf16x8* V1 = opaque_lds((const bf16x8*)stab);
         const float* mu = opaque_lds((const float*)smu);
-        floatx4 z[KT];
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) z[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        // Z in the order of the block-split kernel: four quarters of the K
+        // steps, each a chain from zero, the quarters added in order
+        floatx4 z[KT], zq[KT];
         auto step = [&](auto sc) __attribute__((always_inline)) {
             constexpr int s = decltype(sc)::value;
+            if constexpr (s % QS == 0) {
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt) zq[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
             load(std::integral_constant<int, s + PF>{});
             const float4 m0 = *(const float4*)(mu + 32 * s + 8 * g);
             const float4 m1 = *(const float4*)(mu + 32 * s + 8 * g + 4);
@@ -320,8 +325,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
             for (int t = 0; t < 8; ++t) bv[t] = (__bf16)(ring[s % (PF + 1)][t] - mv[t]);
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt)
-                z[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V1[((s * KT + kt) * 4 + g) * 16 + n], bv, z[kt], 0,
-                                                                0, 0);
+                zq[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V1[((s * KT + kt) * 4 + g) * 16 + n], bv, zq[kt], 0,
+                                                                 0, 0);
+            if constexpr (s % QS == QS - 1) {
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) z[kt][v] = (s == QS - 1) ? zq[kt][v] : z[kt][v] + zq[kt][v];
+            }
         };
         StaticFor<0, NS>::run(step);
         const float* plo = opaque_lds((const float*)slo);

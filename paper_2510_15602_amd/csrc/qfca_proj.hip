@@ -275,6 +275,7 @@ template <int CMAX, int KT, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4))) void k_proj_bf16_solo(
     MArgs a) {
     constexpr int NS = CMAX / 32;        // first-product K steps (32 channels each)
+    constexpr int QS = NS / 4;           // K steps of one quarter (one wavefront's share in k_proj_bf16_mfma)
     constexpr int NU = KT / 2;           // second-product K steps (32 components each)
     constexpr int VSZ = CMAX * KT * 16;  // bf16 elements per table
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -384,11 +385,16 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
         const bf16x8* V1 = opaque_lds((const bf16x8*)sv1);
         const bf16x8* V2 = opaque_lds((const bf16x8*)sv2);
         const float* mu = opaque_lds((const float*)smu);
-        floatx4 z[KT];
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) z[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        // Z in the order of the block-split kernels (and of the batch
+        // kernel): four quarters of the K steps, each a chain from zero, the
+        // quarters added in order, so that every path gives the same bits
+        floatx4 z[KT], zq[KT];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
+            if (s % QS == 0) {
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt) zq[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
             // mu of the lane's eight channels: two 16-byte reads
             const float4 m0 = *(const float4*)(mu + 32 * s + 8 * g);
             const float4 m1 = *(const float4*)(mu + 32 * s + 8 * g + 4);
@@ -401,8 +407,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
             }
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt)
-                z[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V1[((s * KT + kt) * 4 + g) * 16 + n], bv, z[kt], 0, 0,
-                                                                0);
+                zq[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(V1[((s * KT + kt) * 4 + g) * 16 + n], bv, zq[kt], 0,
+                                                                 0, 0);
+            if (s % QS == QS - 1) {
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) z[kt][v] = (s == QS - 1) ? zq[kt][v] : z[kt][v] + zq[kt][v];
+            }
             // keeps the scheduler from hoisting later steps' table reads
             // (all of them in flight at once would not fit the registers)
             __builtin_amdgcn_sched_barrier(0);
