@@ -463,22 +463,19 @@ def variants_leg(args, q, torch, np, dev):
 
 def sweep(args, q, torch, np, dev):
     """Score-kernel time on the 256x256 x 256 image against the window side T
-    (B = 32) and the bin count B (T = 15), FP32 projection, model fitted on
-    the image: the T-independence of the association and the linear cost in
-    B (one JSON line)."""
+    (B = 32), the bin count B (T = 15) and the tile (strip width Ws and band
+    height Hb at T = 15, B = 32, each map compared bit for bit with the one
+    of the automatic tile), FP32 projection, model fitted on the image (one
+    JSON line)."""
     import qfca_synth
     ts, p = qfca_synth.workload_256(args.seed)
     X = torch.from_numpy(ts[0].X).to(dev)
     C, H, W = ts[0].X.shape
     ctx = q.Context(0)
     out = {"workload": f"{H}x{W} feature map, C={C} float32, PCA residual k={p['k']}, score kernel only",
-           "kappa": SCORE_OPS_PER_PCB, "T_sweep": [], "B_sweep": []}
+           "kappa": SCORE_OPS_PER_PCB, "T_sweep": [], "B_sweep": [], "tile_sweep": []}
 
-    def one(T, B):
-        prm = q.Params.make(C=C, k=p["k"], B=B, T=T, sigma_s=p["sigma_s"])
-        m = q.qfca_fit_pca(ctx, prm, X)
-        bins, _ = q.qfca_quantize(ctx, m, X)
-        o = q.qfca_score_map(ctx, m, bins)
+    def timed(m, bins, o):
         for _ in range(3):
             q.qfca_score_map(ctx, m, bins, out=o)
         torch.cuda.synchronize()
@@ -489,16 +486,34 @@ def sweep(args, q, torch, np, dev):
         torch.cuda.synchronize()
         ctx.profile(False)
         ms, n = ctx.profile_read("score")
-        m.close()
-        ms /= max(n, 1)
+        return ms / max(n, 1)
+
+    def one(T, B, tiles=()):
+        prm = q.Params.make(C=C, k=p["k"], B=B, T=T, sigma_s=p["sigma_s"])
+        m = q.qfca_fit_pca(ctx, prm, X)
+        bins, _ = q.qfca_quantize(ctx, m, X)
+        o = q.qfca_score_map(ctx, m, bins)
+        ms = timed(m, bins, o)
         ops = float(H) * W * C * B * SCORE_OPS_PER_PCB
-        return {"T": T, "B": B, "score_ms": round(ms, 4), "mpx_s": round(H * W / (ms * 1e-3) / 1e6, 2),
-                "valu_frac": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)}
+        res = {"T": T, "B": B, "score_ms": round(ms, 4), "mpx_s": round(H * W / (ms * 1e-3) / 1e6, 2),
+               "valu_frac": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)}
+        ref = o.score.clone()
+        for Ws, Hb in tiles:
+            ctx.set_tile(Ws=Ws, Hb=Hb, S=min(2, 64 // B), variant=1)
+            try:
+                tms = timed(m, bins, o)
+                out["tile_sweep"].append({"Ws": Ws, "Hb": Hb, "score_ms": round(tms, 4),
+                                          "same_bits": bool(torch.equal(o.score, ref))})
+            finally:
+                ctx.set_tile(Ws=0)
+        m.close()
+        return res
 
     for T in range(3, 32, 2):
         out["T_sweep"].append(one(T, 32))
     for B in (4, 8, 12, 16, 24, 32, 48, 64):
-        out["B_sweep"].append(one(15, B))
+        tiles = [(Ws, Hb) for Ws in (30, 45, 60, 75, 90) for Hb in (32, 48, 64, 96, 128, 256)] if B == 32 else ()
+        out["B_sweep"].append(one(15, B, tiles))
     print(json.dumps(out), flush=True)
 
 

@@ -271,7 +271,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
     const int b0 = (int)blockIdx.x * per;
     const int tend = min(a.ntiles, b0 + per);
     const bool rows_dw = ((a.N & 3) == 0) && (((uintptr_t)a.bins & 3) == 0);
-    for (int tile = b0 + w; tile < tend; tile += NW) {
+    // every wavefront of the block runs the same number of rounds and meets
+    // the others at the start of each (a bare barrier), so the block's
+    // stores to a line of bins come close together in time
+    const int nround = tend > b0 ? (tend - b0 + NW - 1) / NW : 0;
+    int tile = b0 + w;
+    for (int rd = 0; rd < nround; ++rd, tile += NW) {
+        __builtin_amdgcn_s_barrier();
+        if (tile >= tend) continue;
         // lane index and bases opaque per tile (nothing lane- or base-derived
         // is hoisted out of the loop into registers)
         int lane = threadIdx.x & 63;

@@ -361,7 +361,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
 #pragma unroll
         for (int s = 0; s < NS; ++s) load_row(d[s], s, a.X, vo, (uint32_t)pxc * 4u, g);
     }
-    for (; tile < tend; tile += NW) {
+    // Every wavefront of the block runs the same number of rounds and meets
+    // the others at the start of each (a bare barrier: loads in flight stay
+    // in flight), so the block's stores to a line of bins, and its loads of a
+    // line of features, come close together in time.
+    const int nround = tend > b0 ? (tend - b0 + NW - 1) / NW : 0;
+    for (int rd = 0; rd < nround; ++rd, tile += NW) {
+        __builtin_amdgcn_s_barrier();
+        if (tile >= tend) continue;
         // the lane index made opaque per tile: every address and test derived
         // from the lane's channels is formed in the loop where it is used
         // (hoisted out of it, the 128 channels' offsets and tests would take
