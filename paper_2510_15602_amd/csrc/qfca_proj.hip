@@ -276,6 +276,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
     MArgs a) {
     constexpr int NS = CMAX / 32;        // first-product K steps (32 channels each)
     constexpr int QS = NS / 4;           // K steps of one quarter (one wavefront's share in k_proj_bf16_mfma)
+    constexpr int SB = 4;                // second-product steps between the block's barriers
     constexpr int NU = KT / 2;           // second-product K steps (32 components each)
     constexpr int VSZ = CMAX * KT * 16;  // bf16 elements per table
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -368,7 +369,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
     const int nround = tend > b0 ? (tend - b0 + NW - 1) / NW : 0;
     for (int rd = 0; rd < nround; ++rd, tile += NW) {
         __builtin_amdgcn_s_barrier();
-        if (tile >= tend) continue;
+        if (tile >= tend) {
+            // the barriers of the steps the others run
+#pragma unroll
+            for (int i = 0; i < NS / SB - 1; ++i) __builtin_amdgcn_s_barrier();
+            continue;
+        }
         // the lane index made opaque per tile: every address and test derived
         // from the lane's channels is formed in the loop where it is used
         // (hoisted out of it, the 128 channels' offsets and tests would take
@@ -444,6 +450,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
         asm volatile("" : "+s"(Et), "+s"(Rt), "+s"(Bt));
         auto step = [&](auto sc) __attribute__((always_inline)) {
             constexpr int s = decltype(sc)::value;
+            // the block's wavefronts meet every SB steps, so that their
+            // stores to each channel's line of bins stay close in time
+            if constexpr (s > 0 && s % SB == 0) __builtin_amdgcn_s_barrier();
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
