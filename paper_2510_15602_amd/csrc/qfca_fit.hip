@@ -219,6 +219,8 @@ struct RefLayout {
     }
 };
 
+// MODE: what a window's count adds to (RArgs::mode); PERBIN: RArgs::perbin.
+template <int MODE, bool PERBIN>
 __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
@@ -359,33 +361,54 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
             __syncthreads();
             // window sums along the row: cP = sum of the counts of columns
             // [q - T + 1, q]; the window ending at column q is centred on
-            // image column xb0 + q - r
-            int cP = 0;
-            constexpr int CW = 8;
-            for (int q0 = 0; q0 < Wb; q0 += CW) {
-                int vn[CW], vo[CW];
-#pragma unroll
-                for (int i = 0; i < CW; ++i) {
-                    const int q = q0 + i;
-                    vn[i] = q < Wb ? (int)vb[q] : 0;
-                    vo[i] = (q >= T && q < Wb) ? (int)vb[q - T] : 0;
-                }
-#pragma unroll
-                for (int i = 0; i < CW; ++i) {
-                    const int q = q0 + i;
-                    cP += vn[i] - vo[i];
-                    const int px = xb0 + q - r;
-                    // the bin's own count: its cumulative count minus the
-                    // previous bin's (the neighbouring lane of the channel)
-                    // (the exchange runs in every lane, outside any branch:
-                    // a lane with execution off would give 0 to its neighbour)
-                    const int pv = lane_prev(cP);
-                    const int cv0 = a.perbin ? cP - (j == 0 ? 0 : pv) : cP;
-                    const int cu = a.mode == 0 ? cv0 : (a.mode == 1 ? cv0 >> a.sh : cv0 & ((1 << a.sh) - 1));
-                    const bool take = a.mode != 2 || (cv0 >> a.sh) == selj;
-                    if (counting && take && q < Wb && q >= T - 1 && px >= pxlo && px < pxhi)
+            // image column xb0 + q - r, and is counted for q in [qc0, qc1)
+            // (a full window of the tile's own centres)
+            const int qc0 = max(T - 1, pxlo - xb0 + r), qc1 = min(Wb, pxhi - xb0 + r);
+            const uint32_t* __restrict__ vw = vc32 + lane * L.vsd;
+            auto count = [&](int cP) __attribute__((always_inline)) {
+                // the bin's own count: its cumulative count minus the previous
+                // bin's (the neighbouring lane of the channel); the exchange
+                // runs in every lane
+                const int pv = lane_prev(cP);
+                const int cv0 = PERBIN ? cP - (j == 0 ? 0 : pv) : cP;
+                if constexpr (MODE == 2) {
+                    if (counting && (cv0 >> a.sh) == selj) {
+                        const int cu = cv0 & ((1 << a.sh) - 1);
                         atomicAdd(mycnt + (cu >> 1), 1u << ((cu & 1) << 4));
+                    }
+                } else {
+                    // lanes that do not count add zero to a counter of their
+                    // own channel's table (every cu lies in [0, mcnt])
+                    const int cu = MODE == 0 ? cv0 : cv0 >> a.sh;
+                    atomicAdd(mycnt + (cu >> 1), counting ? 1u << ((cu & 1) << 4) : 0u);
                 }
+            };
+            int cP = 0;
+            for (int q = qc0 - T + 1; q <= qc0; ++q) cP += (int)vb[q];
+            count(cP);
+            // then four columns per step: the entering bytes are one dword,
+            // the leaving ones (T columns back) the dword pair's bytes at a
+            // fixed offset
+            int q = qc0 + 1;
+            for (; q < qc1 && (q & 3); ++q) {
+                cP += (int)vb[q] - (int)vb[q - T];
+                count(cP);
+            }
+            const int osh = (4 - (T & 3)) & 3;  // (q - T) & 3 for q a multiple of 4
+            for (; q + 4 <= qc1; q += 4) {
+                const uint32_t xn = vw[q >> 2];
+                const int qo = q - T - osh;  // a multiple of 4
+                const uint32_t lo = vw[qo >> 2], hi = vw[(qo >> 2) + 1];
+                const uint32_t xo = osh ? __builtin_amdgcn_alignbyte(hi, lo, osh) : lo;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    cP += (int)((xn >> (8 * i)) & 0xFFu) - (int)((xo >> (8 * i)) & 0xFFu);
+                    count(cP);
+                }
+            }
+            for (; q < qc1; ++q) {
+                cP += (int)vb[q] - (int)vb[q - T];
+                count(cP);
             }
         }
     }
@@ -703,7 +726,19 @@ static hipError_t refcount_pass(const uint8_t* bins, int C, int H, int W, int T,
     if (e != hipSuccess) return e;
     a.S = S; a.nsplit = nsplit;
     dim3 grid((W + a.Ws - 1) / a.Ws, (H + a.Hb - 1) / a.Hb, ((C + S - 1) / S) * nsplit);
-    hipLaunchKernelGGL(k_refcount, grid, dim3(64), lds(S, nsplit), st, a);
+    const size_t ldsb = lds(S, nsplit);
+    if (mode == 0 && !perbin)
+        hipLaunchKernelGGL((k_refcount<0, false>), grid, dim3(64), ldsb, st, a);
+    else if (mode == 0)
+        hipLaunchKernelGGL((k_refcount<0, true>), grid, dim3(64), ldsb, st, a);
+    else if (mode == 1 && !perbin)
+        hipLaunchKernelGGL((k_refcount<1, false>), grid, dim3(64), ldsb, st, a);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_refcount<1, true>), grid, dim3(64), ldsb, st, a);
+    else if (!perbin)
+        hipLaunchKernelGGL((k_refcount<2, false>), grid, dim3(64), ldsb, st, a);
+    else
+        hipLaunchKernelGGL((k_refcount<2, true>), grid, dim3(64), ldsb, st, a);
     return hipGetLastError();
 }
 
