@@ -11,6 +11,7 @@
 namespace qfca {
 namespace {
 using tiles::lane_prev;
+using tiles::wave_sync;
 
 // ------------------------------------------------------------------------
 // Mean: one block per channel, FP64 tree reduction in a fixed order.
@@ -203,32 +204,42 @@ struct RArgs {
 
 __host__ __device__ inline size_t ralign16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// LDS of a k_refcount block of nw wavefronts: the count table shared by the
+// block, then each wavefront's column counts and staged rows.
 struct RefLayout {
     int WbP, vsd, mw;
-    size_t vc, cnt, rows, total;
-    __host__ __device__ RefLayout(int Ws, int r, int S, int per, int m) {
+    size_t cnt, wave, total;
+    __host__ __device__ RefLayout(int Ws, int r, int S, int per, int m, int nw) {
         const int WbMax = Ws + 2 * r;       // bin columns of the widest tile
         WbP = (WbMax + 3) & ~3;
         vsd = WbP / 4;
         if ((vsd & 1) == 0) vsd += 1;       // odd dword stride between lanes
         mw = (m + 2) / 2;                   // words holding counters 0 .. m
-        vc = 0;
-        cnt = ralign16((size_t)64 * vsd * 4);
-        rows = cnt + ralign16((size_t)S * per * mw * 4);
-        total = rows + ralign16((size_t)2 * S * WbP);
+        cnt = ralign16((size_t)S * per * mw * 4);
+        wave = ralign16((size_t)64 * vsd * 4) + ralign16((size_t)2 * S * WbP);
+        total = cnt + (size_t)nw * wave;
     }
+    __host__ __device__ size_t vc(int w) const { return cnt + (size_t)w * wave; }
+    __host__ __device__ size_t rows(int w) const { return vc(w) + ralign16((size_t)64 * vsd * 4); }
 };
 
 // MODE: what a window's count adds to (RArgs::mode); PERBIN: RArgs::perbin.
+// A block of nw wavefronts (blockDim.x / 64, at most 4) shares one count
+// table: wavefront w walks band blockIdx.y * nw + w of the strip with its own
+// column counts and staged rows, synchronising with itself only, and adds to
+// the shared counters with LDS atomics; the block adds the table to the
+// global one at the end.
 template <int MODE, bool PERBIN>
-__global__ __launch_bounds__(64) void k_refcount(RArgs a) {
+__global__ __launch_bounds__(256) void k_refcount(RArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int nw = (int)blockDim.x >> 6;
     const int Bp = a.Bp, S = a.S, T = a.T, r = a.r, m = a.m, H = a.H, W = a.W;
     const int s = lane / Bp, j = lane - s * Bp;
     const int sa = s < S ? s : S - 1;
     const int x0 = blockIdx.x * a.Ws, xe = min(W, x0 + a.Ws), ws = xe - x0;
-    const int y0 = blockIdx.y * a.Hb, ye = min(H, y0 + a.Hb);
+    const int y0 = ((int)blockIdx.y * nw + w) * a.Hb, ye = min(H, y0 + a.Hb);
     const int split = blockIdx.z % a.nsplit;
     const int cbase = (blockIdx.z / a.nsplit) * S;
     const int c = cbase + s;
@@ -238,15 +249,15 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
     const bool counting = cv && (j < a.B) && (j >= jlo) && (j < jlo + per);
     const int mcnt = a.mcnt;
     const int selj = (a.mode == 2 && counting) ? a.sel[(size_t)c * a.B + j] : -1;
-    const RefLayout L(a.Ws, r, S, per, mcnt);
+    const RefLayout L(a.Ws, r, S, per, mcnt, nw);
     const int WbP = L.WbP;
     const int Wb = ws + 2 * r;  // bin columns [x0-r, xe+r)
     const int xb0 = x0 - r;
-    uint32_t* vc32 = (uint32_t*)(smem + L.vc);  // [64 lanes][vsd]
-    uint32_t* cnt = (uint32_t*)(smem + L.cnt);  // [S][per][mw]
-    uint8_t* rows = smem + L.rows;              // [2][S][WbP]
+    uint32_t* cnt = (uint32_t*)smem;               // [S][per][mw], shared
+    uint32_t* vc32 = (uint32_t*)(smem + L.vc(w));  // [64 lanes][vsd]
+    uint8_t* rows = smem + L.rows(w);              // [2][S][WbP]
     for (int t = lane; t < 64 * L.vsd; t += 64) vc32[t] = 0u;
-    for (int t = lane; t < S * per * L.mw; t += 64) cnt[t] = 0u;
+    for (int t = threadIdx.x; t < S * per * L.mw; t += blockDim.x) cnt[t] = 0u;
     __syncthreads();
     uint32_t* mycnt = cnt + ((size_t)sa * per + (counting ? j - jlo : 0)) * L.mw;
     const uint32_t jhi = ((uint32_t)j * 0x01010101u) | 0x80808080u;
@@ -331,20 +342,20 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
         };
         if (lfast) issue(pa, ys - r);
         for (int yy = ys - r; yy < ys + r; ++yy) {
-            __syncthreads();
+            wave_sync();
             if (lfast) {
                 commit(pa, 0, yy);
                 issue(pa, yy + 1);  // the next warm-up row, or row ys + r
             } else {
                 stage(0, yy);
             }
-            __syncthreads();
+            wave_sync();
             update(true, false);
         }
         const uint8_t* __restrict__ vb = (const uint8_t*)(vc32 + lane * L.vsd);
         for (int yc = ys; yc < yend; ++yc) {
             const bool rem = yc > ys;
-            __syncthreads();
+            wave_sync();
             if (lfast) {
                 commit(pa, 0, yc + r);
                 if (rem) commit(pr, 1, yc - r - 1);
@@ -356,9 +367,9 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
                 stage(0, yc + r);
                 if (rem) stage(1, yc - r - 1);
             }
-            __syncthreads();
+            wave_sync();
             update(true, rem);
-            __syncthreads();
+            wave_sync();
             // window sums along the row: cP = sum of the counts of columns
             // [q - T + 1, q]; the window ending at column q is centred on
             // image column xb0 + q - r, and is counted for q in [qc0, qc1)
@@ -413,7 +424,7 @@ __global__ __launch_bounds__(64) void k_refcount(RArgs a) {
         }
     }
     __syncthreads();
-    for (int t = lane; t < S * per * L.mw; t += 64) {
+    for (int t = threadIdx.x; t < S * per * L.mw; t += blockDim.x) {
         const int ss = t / (per * L.mw);
         const int rest = t - ss * per * L.mw;
         const int jj = rest / L.mw + jlo, w = rest - (rest / L.mw) * L.mw;
@@ -714,31 +725,35 @@ static hipError_t refcount_pass(const uint8_t* bins, int C, int H, int W, int T,
     a.counts = counts;
     // channels per wave and bin splits so the private histograms fit in LDS;
     // a tile's counters are 16 bits wide
-    if (a.Ws * a.Hb >= 65536) return hipErrorInvalidValue;
     int S = 64 / Bp, nsplit = 1;
-    auto lds = [&](int S_, int ns_) { return RefLayout(a.Ws, a.r, S_, Bp / ns_, a.mcnt).total; };
-    while (lds(S, nsplit) > 60000 && S > 1) S >>= 1;
-    while (lds(S, nsplit) > 60000 && nsplit < Bp) nsplit <<= 1;
-    if (lds(S, nsplit) > 65536) return hipErrorInvalidValue;
+    auto lds = [&](int S_, int ns_, int nw_) { return RefLayout(a.Ws, a.r, S_, Bp / ns_, a.mcnt, nw_).total; };
+    while (lds(S, nsplit, 1) > 60000 && S > 1) S >>= 1;
+    while (lds(S, nsplit, 1) > 60000 && nsplit < Bp) nsplit <<= 1;
+    if (lds(S, nsplit, 1) > 65536) return hipErrorInvalidValue;
+    // four wavefronts share a table where it fits (a counter then sees at
+    // most 4 Ws Hb windows, within its 16 bits)
+    const int nw = lds(S, nsplit, 4) <= 60000 ? 4 : 1;
+    if ((long)nw * a.Ws * a.Hb >= 65536) return hipErrorInvalidValue;
     if (nsplit_out) *nsplit_out = nsplit;
     if (!launch) return hipSuccess;
     hipError_t e = hipMemsetAsync(counts, 0, (size_t)C * B * (a.mcnt + 1) * sizeof(uint32_t), st);
     if (e != hipSuccess) return e;
     a.S = S; a.nsplit = nsplit;
-    dim3 grid((W + a.Ws - 1) / a.Ws, (H + a.Hb - 1) / a.Hb, ((C + S - 1) / S) * nsplit);
-    const size_t ldsb = lds(S, nsplit);
+    dim3 grid((W + a.Ws - 1) / a.Ws, (H + a.Hb * nw - 1) / (a.Hb * nw), ((C + S - 1) / S) * nsplit);
+    const size_t ldsb = lds(S, nsplit, nw);
+    const dim3 block(64 * nw);
     if (mode == 0 && !perbin)
-        hipLaunchKernelGGL((k_refcount<0, false>), grid, dim3(64), ldsb, st, a);
+        hipLaunchKernelGGL((k_refcount<0, false>), grid, block, ldsb, st, a);
     else if (mode == 0)
-        hipLaunchKernelGGL((k_refcount<0, true>), grid, dim3(64), ldsb, st, a);
+        hipLaunchKernelGGL((k_refcount<0, true>), grid, block, ldsb, st, a);
     else if (mode == 1 && !perbin)
-        hipLaunchKernelGGL((k_refcount<1, false>), grid, dim3(64), ldsb, st, a);
+        hipLaunchKernelGGL((k_refcount<1, false>), grid, block, ldsb, st, a);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_refcount<1, true>), grid, dim3(64), ldsb, st, a);
+        hipLaunchKernelGGL((k_refcount<1, true>), grid, block, ldsb, st, a);
     else if (!perbin)
-        hipLaunchKernelGGL((k_refcount<2, false>), grid, dim3(64), ldsb, st, a);
+        hipLaunchKernelGGL((k_refcount<2, false>), grid, block, ldsb, st, a);
     else
-        hipLaunchKernelGGL((k_refcount<2, true>), grid, dim3(64), ldsb, st, a);
+        hipLaunchKernelGGL((k_refcount<2, true>), grid, block, ldsb, st, a);
     return hipGetLastError();
 }
 
