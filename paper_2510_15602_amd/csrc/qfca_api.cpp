@@ -923,18 +923,24 @@ qfca_status qfca_fit_pca(qfca_ctx ctx, const qfca_params* p, const float* X, int
     double* dmu = nullptr;
     HIP_TRY(scratch(ctx, SL_MU, (size_t)C * 8, &dmu));
     HIP_TRY(launch_mean(X, C, N, dmu, s));
+    // the covariance is queued behind the mean before either comes back (a
+    // copy to pageable memory may wait for the stream); the features'
+    // finiteness (a non-finite mean) is checked once both are back
+    std::vector<double> cov;
+    double* dcov = nullptr;
+    if (pre) {
+        cov.resize((size_t)C * C);
+        HIP_TRY(scratch(ctx, SL_COV, (size_t)C * C * 8, &dcov));
+        HIP_TRY(launch_cov(X, C, N, dmu, dcov, s));
+    }
     m->mu.assign(C, 0.0);
     HIP_TRY(hipMemcpyAsync(m->mu.data(), dmu, (size_t)C * 8, hipMemcpyDeviceToHost, s));
+    if (pre) HIP_TRY(hipMemcpyAsync(cov.data(), dcov, cov.size() * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (int c = 0; c < C; ++c)
         if (!isfinite(m->mu[c])) return fail(QFCA_E_NONFINITE, "non-finite value in the features");
     if (pre) {
-        std::vector<double> cov((size_t)C * C), vecs((size_t)C * k);
-        double* dcov = nullptr;
-        HIP_TRY(scratch(ctx, SL_COV, (size_t)C * C * 8, &dcov));
-        HIP_TRY(launch_cov(X, C, N, dmu, dcov, s));
-        HIP_TRY(hipMemcpyAsync(cov.data(), dcov, cov.size() * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        std::vector<double> vecs((size_t)C * k);
         m->evals.assign(C, 0.0);
         // 2. eigenvectors of the k largest eigenvalues (host, FP64)
         if (sym_eig_top(cov.data(), C, k, m->evals.data(), vecs.data()) != 0)

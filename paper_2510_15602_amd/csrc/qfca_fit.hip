@@ -120,7 +120,9 @@ __device__ __forceinline__ float funkey(uint32_t k) {
     return __uint_as_float(u);
 }
 
-__global__ __launch_bounds__(256) void k_select(const float* __restrict__ vals, long N,
+constexpr int SEL_THREADS = 1024;  // per channel: enough loads in flight to cover the memory latency
+
+__global__ __launch_bounds__(SEL_THREADS) void k_select(const float* __restrict__ vals, long N,
                                                 const long long* __restrict__ ranks, int nr,
                                                 float* __restrict__ out) {
     __shared__ uint32_t hist[MAXR][256];
@@ -135,23 +137,23 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ vals, 
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 24 - 8 * pass;
         const uint32_t mask = pass == 0 ? 0u : (0xFFFFFFFFu << (32 - 8 * pass));
-        for (int t = threadIdx.x; t < MAXR * 256; t += 256) (&hist[0][0])[t] = 0u;
+        for (int t = threadIdx.x; t < MAXR * 256; t += SEL_THREADS) (&hist[0][0])[t] = 0u;
         __syncthreads();
         uint32_t pf[MAXR];
 #pragma unroll
         for (int q = 0; q < MAXR; ++q) pf[q] = q < nr ? prefix[q] : 0u;
         // U loads per thread in flight before their histogram updates
         constexpr int U = 16;
-        for (long i0 = threadIdx.x; i0 < N; i0 += 256 * U) {
+        for (long i0 = threadIdx.x; i0 < N; i0 += SEL_THREADS * U) {
             float x[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const long i = i0 + (long)u * 256;
+                const long i = i0 + (long)u * SEL_THREADS;
                 x[u] = v[i < N ? i : N - 1];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (i0 + (long)u * 256 >= N) break;
+                if (i0 + (long)u * SEL_THREADS >= N) break;
                 const uint32_t k = fkey(x[u]);
 #pragma unroll
                 for (int q = 0; q < MAXR; ++q)
@@ -185,10 +187,11 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ vals, 
 //      dword: for 7-bit bytes b and j < 64, 0x80 + j - b never borrows across
 //      bytes and its top bit is set exactly when b <= j;
 //   3. the lane walks the columns with a running window sum cP and counts
-//      each full window's cP in its private table of uint16 counters, two per
+//      each full window's cP in its bin's table of uint16 counters, two per
 //      word, by LDS atomic adds that return nothing (no wait per window).
-// The counts of a tile (at most Ws * Hb = 4096 windows) fit in 16 bits; they
-// are flushed with global atomics at the end.
+// The four wavefronts of a block (one band each) share the tables; their
+// counts (at most 4 Ws Hb = 16384 windows) fit in 16 bits and are flushed
+// with global atomics at the end.
 struct RArgs {
     const uint8_t* bins;
     int C, H, W, T, B, Bp, S, r, m, Ws, Hb, nsplit;
@@ -702,7 +705,7 @@ hipError_t launch_cov(const float* X, int C, long N, const double* mu, double* c
 hipError_t launch_select(const float* vals, int C, long N, const long long* ranks_dev, int nr,
                          float* out, hipStream_t st) {
     if (nr > MAXR) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_select, dim3(C), dim3(256), 0, st, vals, N, ranks_dev, nr, out);
+    hipLaunchKernelGGL(k_select, dim3(C), dim3(SEL_THREADS), 0, st, vals, N, ranks_dev, nr, out);
     return hipGetLastError();
 }
 
