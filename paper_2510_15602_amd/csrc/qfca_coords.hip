@@ -209,9 +209,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 // Whole-tile kernel for 512 channels in BF16: every wavefront computes the
 // full Z of its own 16-pixel tiles (all channels, so no partials are added
-// across wavefronts and the tile loop has no barrier), sixteen wavefronts
-// per block (four per SIMD) share the operand table and the parameters in
-// LDS, and a block's wavefronts take interleaved tiles of one contiguous run.
+// across wavefronts), sixteen wavefronts per block (four per SIMD) share the
+// operand table and the parameters in LDS, and a block's wavefronts take
+// interleaved tiles of one contiguous run, meeting at a bare barrier at the
+// start of each round.
 // The centred features are not needed after the product, so they stream
 // through a ring of PF + 1 register groups: step s + PF is loaded while step
 // s is multiplied.  Lane (g, n) ends with components 16 kt + 4 g + v of pixel

@@ -251,10 +251,10 @@ __global__ __launch_bounds__(256) void k_proj_bf16_mfma_wide(MArgs a) {
 // ------------------------------------------------------------------------
 // BF16 kernel for the widest maps (CMAX = 512): every wavefront runs whole
 // 16-pixel tiles on its own, all channels in both products, so there are no
-// Z partials to add across wavefronts and no barrier in the tile loop.  The
-// eight wavefronts of a block (two per SIMD, which hide each other's memory
-// and LDS latency) share the operand tables and the per-channel parameters
-// in LDS; each walks its own contiguous run of tiles.  Lane (g, n) holds the
+// Z partials to add across wavefronts.  The NW wavefronts of a block (three
+// per SIMD, which hide each other's memory and LDS latency) share the
+// operand tables and the per-channel parameters in LDS and take interleaved
+// tiles of one contiguous run, meeting at bare barriers (see the loop).  Lane (g, n) holds the
 // channels 32 s + 8 g + t of pixel n in d[s][t] (the first product's B
 // operand), and the second product's outputs land on the same channels.
 // The bins of four consecutive channels of a pixel (one lane) are packed in
