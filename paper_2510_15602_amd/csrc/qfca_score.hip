@@ -319,6 +319,17 @@ __global__ __launch_bounds__(64) void k_score_t(KArgs a) {
                                smem + BLayout<T>::RCP_BYTES, rcp4);
 }
 
+// The block walk with a finite sigma_p (Gaussian association weights a.wgt).
+template <int T>
+__global__ __launch_bounds__(64) void k_score_tg(KArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* rcp4 = (float*)smem;
+    fill_rcp4<T>(rcp4, a.rcp, threadIdx.x, 64);
+    const int y0 = blockIdx.y * a.Hb;
+    score_tile<T, false, true, false, false, true>(a, blockIdx.x, y0, min(a.H, y0 + a.Hb), blockIdx.z, threadIdx.x,
+                                                   smem + BLayout<T>::RCP_BYTES, rcp4);
+}
+
 // Separable Gaussian, radius R, renormalised over in-image taps (the 2-D
 // renormalisation factorises because the in-image tap set is a rectangle).
 constexpr int BT = 16;
@@ -550,8 +561,10 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     a.r = L.T / 2;
     a.m = L.T * L.T;
     a.Hb = L.tile.Hb;
-    // a general reference or a finite sigma_p runs the column walk
-    const bool generic_only = L.tab.cRw != nullptr || L.tab.wgt != nullptr;
+    // a general reference runs the column walk; a finite sigma_p runs the
+    // block walk with Gaussian weights where the tile allows it
+    const bool generic_only = L.tab.cRw != nullptr;
+    const bool gauss = L.tab.wgt != nullptr;
     const int variant =
         (!generic_only && L.tile.variant == 1 && score_has_block_kernel(L.T) &&
          L.tile.S <= score_block_max_S(L.T) && L.tile.Ws >= L.T) ? 1 : 0;
@@ -563,7 +576,7 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     a.dbg_cp = L.dbg_cp; a.dbg_I = L.dbg_I;
     a.cRw = L.tab.cRw; a.wgt = L.tab.wgt;
     const bool dbg = L.dbg_cp != nullptr;
-    if (dbg && (!L.dbg_I || variant != 1)) return hipErrorInvalidValue;
+    if (dbg && (!L.dbg_I || variant != 1 || gauss)) return hipErrorInvalidValue;
     const bool w1o = L.w1only && variant == 1;
     if (L.w1only && !a.w1sum) return hipErrorInvalidValue;
     if (a.S < 1 || a.S * a.Bp > 64 || !a.asum) return hipErrorInvalidValue;
@@ -589,15 +602,19 @@ hipError_t launch_score(const ScoreLaunch& L, hipStream_t st) {
     switch (a.T) {
 #define QFCA_T_CASE(TT)                                                          \
         case TT: {                                                               \
+            const bool gs = gauss && !dbg && !w1o;                               \
             const void* kf = dbg ? (const void*)k_score_dbg<TT>                  \
-                                 : (w1o ? (const void*)k_score_w1<TT> : (const void*)k_score_t<TT>); \
-            hipError_t e = (dbg || w1o) ? no_static_lds_uncached(kf) : no_static_lds(kf, TT); \
+                                 : (w1o ? (const void*)k_score_w1<TT>            \
+                                        : (gs ? (const void*)k_score_tg<TT> : (const void*)k_score_t<TT>)); \
+            hipError_t e = (dbg || w1o || gs) ? no_static_lds_uncached(kf) : no_static_lds(kf, TT); \
             if (e == hipSuccess) e = allow(kf);                                  \
             if (e != hipSuccess) return e;                                       \
             if (dbg)                                                             \
                 hipLaunchKernelGGL(k_score_dbg<TT>, grid, dim3(64), lds, st, a); \
             else if (w1o)                                                        \
                 hipLaunchKernelGGL(k_score_w1<TT>, grid, dim3(64), lds, st, a);  \
+            else if (gs)                                                         \
+                hipLaunchKernelGGL(k_score_tg<TT>, grid, dim3(64), lds, st, a);  \
             else                                                                 \
                 hipLaunchKernelGGL(k_score_t<TT>, grid, dim3(64), lds, st, a);   \
         } break;

@@ -171,7 +171,12 @@ __device__ __forceinline__ void fill_rcp4(float* rcp4, const float* rcp, int tid
 //   windows, sum_j |cP_j m - cR_j n| / (n m) weighted by delta_c, added over
 //   the channel group into a.w1sum (fixed point); no per-bin errors, no
 //   association, no halo rows.
-template <int T, bool FASTG, bool RCP0, bool DBG = false, bool W1O = false>
+//   GS: finite sigma_p (Eq. 2 weights w(d) = a.wgt[d + r], separable): the
+//   horizontal sums are the w-weighted sums of the T steps around each
+//   output column (fixed order), the gather adds w(dy) times them, and an
+//   output is divided by the in-image weight sums along both axes instead of
+//   the window counts.
+template <int T, bool FASTG, bool RCP0, bool DBG = false, bool W1O = false, bool GS = false>
 __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int y0, int ye, int bz, int lane,
                                            unsigned char* smem, const float* rcp4) {
     using BL = BLayout<T>;
@@ -366,12 +371,21 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int y0, int y
     // complete, those below are never output (the accumulator ring of T rows
     // holds exactly the T pending rows).
     uint32_t g_w0[NIT], g_w1[NIT];
+    // GS: the weights w(d - r), d = 0 .. T - 1 (uniform), and the vertical
+    // weight of a gather item, w(r - t) = w(t - r) for pending row t
+    float gw[GS ? T : 1];
+    if constexpr (GS) {
+#pragma unroll
+        for (int d = 0; d < T; ++d) gw[d] = a.wgt[d];
+    }
+    float gwt[GS ? NIT : 1];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int idx = it * 64 + lane;
         const int ss = idx / (T * T);
         const int rem2 = idx - ss * (T * T);
         const int t = rem2 / T, k = rem2 - t * T;
+        if constexpr (GS) gwt[it] = a.wgt[t];
         const bool ok = (ss < S) && (cbase + ss < a.C);
         const int ssc = (ss < S) ? ss : 0;
         const int yo = ys - r + t;
@@ -394,13 +408,21 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int y0, int y
     constexpr int OSL = 4;
     constexpr int OSM = (T <= 9) ? 4 : 2;  // channels per wavefront (score_block_max_S)
     const bool ofast = (ws <= 64 * OSL) && (S <= OSM);
+    // in-image weight of the windows around position x along one axis: their
+    // count for the box, the sum of w(d) for a finite sigma_p (fixed order)
+    auto axis_weight = [&](int x, int len) -> double {
+        if constexpr (GS) {
+            double sw = 0.0;
+            for (int d = 0; d < T; ++d)
+                if (x - r + d >= 0 && x - r + d < len) sw += (double)a.wgt[d];
+            return sw > 0.0 ? sw : 1.0;
+        } else {
+            return (double)max(min(len - 1, x + r) - max(0, x - r) + 1, 1);
+        }
+    };
     double orx[OSL];
 #pragma unroll
-    for (int i = 0; i < OSL; ++i) {
-        const int xg = x0 + lane + 64 * i;
-        const int nxo = min(W - 1, xg + r) - max(0, xg - r) + 1;
-        orx[i] = 1.0 / (double)max(nxo, 1);
-    }
+    for (int i = 0; i < OSL; ++i) orx[i] = 1.0 / axis_weight(x0 + lane + 64 * i, W);
     const double inv_fxs = 1.0 / a.fxs;
 
     for (int yy = lo_add; yy < hi_add; ++yy) {
@@ -474,7 +496,9 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int y0, int y
             for (int i = 0; i < 2 * TPD; ++i) win[i] = vw[i];
         }
         int ent0 = 0;  // count that entered at step k = 0 of the previous block
-        float suf[T];  // suffix sums of the previous block's errors (suf[k] = sum over k' >= k)
+        // suffix sums of the previous block's errors (suf[k] = sum over
+        // k' >= k); with GS the previous block's errors themselves
+        float suf[T];
 #pragma unroll
         for (int k = 0; k < T; ++k) suf[k] = 0.f;
         for (int blk = 0; blk < nblk; ++blk) {
@@ -672,7 +696,22 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int y0, int y
             // 2. horizontal window sums: after step i0 + k the window holds
             //    steps [i0 + k - 2r, i0 + k] = previous block's k+1 .. T-1 and
             //    this block's 0 .. k; output column o = i0 + k - 2r
-            {
+            if constexpr (GS) {
+                // suf holds the previous block's errors; step i0 + k - 2r + d
+                // has weight w(d - r) for the output of step k
+#pragma unroll
+                for (int k = 0; k < T; ++k) {
+                    float h = 0.f;
+#pragma unroll
+                    for (int d = 0; d < T; ++d) {
+                        const int si = k - 2 * r + d;
+                        h = __builtin_fmaf(gw[d], si < 0 ? suf[si + T] : ev[si], h);
+                    }
+                    hrow[lane * HS + k] = h;
+                }
+#pragma unroll
+                for (int k = 0; k < T; ++k) suf[k] = ev[k];
+            } else {
                 float pre = 0.f;
 #pragma unroll
                 for (int k = 0; k < T; ++k) {
@@ -697,7 +736,8 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int y0, int y
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) hv[it] = hrow[(g_w0[it] & 0xFFFFu) + (gbin[it] & (Bp - 1)) * HS];
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) lds_store_f(gdst[it], gacc[it] + hv[it]);
+                for (int it = 0; it < NIT; ++it)
+                    lds_store_f(gdst[it], GS ? __builtin_fmaf(gwt[GS ? it : 0], hv[it], gacc[it]) : gacc[it] + hv[it]);
             } else if (gat) {
                 constexpr int CHK = 8;  // items per round of reads
                 auto gather_chunks = [&](auto inner) {
@@ -726,7 +766,8 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int y0, int y
                         }
 #pragma unroll
                         for (int q = 0; q < CHK; ++q)
-                            if (c0 + q < NIT) lds_store_f(da[q], av[q] + hv[q]);
+                            if (c0 + q < NIT)
+                                lds_store_f(da[q], GS ? __builtin_fmaf(gwt[GS ? c0 + q : 0], hv[q], av[q]) : av[q] + hv[q]);
                     }
                 };
                 if (FASTG && gin)
@@ -761,8 +802,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int y0, int y
         yo_lo = max(yo_lo, y0);
         yo_hi = min(yo_hi, ye - 1);
         for (int yo = yo_lo; yo <= yo_hi; ++yo) {
-            const int nyo = min(H - 1, yo + r) - max(0, yo - r) + 1;
-            const double rny = 1.0 / (double)nyo;
+            const double rny = 1.0 / axis_weight(yo, H);
             float* ar = acc + (yo % T) * S * Ws;
             if (ofast) {
                 // every read of the row before the stores that clear it
@@ -805,8 +845,7 @@ __device__ __forceinline__ void score_tile(const KArgs& a, int bx, int y0, int y
                 *ap = 0.f;
                 if (cc < a.C) {
                     const int xg = x0 + xo;
-                    const int nxo = min(W - 1, xg + r) - max(0, xg - r) + 1;
-                    const double v = (((double)av * (a.delta[cc] * a.fxs)) * (1.0 / (double)nxo)) * rny;
+                    const double v = (((double)av * (a.delta[cc] * a.fxs)) * (1.0 / axis_weight(xg, W))) * rny;
                     if (a.achan) a.achan[((size_t)cc * H + yo) * W + xg] = (float)(v * inv_fxs);
                     __hip_atomic_fetch_add(&a.asum[(size_t)yo * W + xg], __double2ll_rn(v), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);

@@ -50,7 +50,9 @@ def problem(seed, C, H, W, T, B):
                          ids=lambda c: "C%d_H%d_W%d_T%d_B%d_sp%g" % c)
 def test_gaussian_association(ctx, case):
     """Finite sigma_p against the oracle's direct weighted mean over the
-    windows holding each pixel; every map bitwise the same for every tile."""
+    windows holding each pixel, through the block walk (window sides up to
+    31) and the column walk; each walk's maps bitwise the same for every
+    tile."""
     C, H, W, T, B, sp = case
     say(f"[sigma_p] C={C} H={H} W={W} T={T} B={B} sigma_p={sp}")
     _, bins, delta, e = problem(50 + T, C, H, W, T, B)
@@ -65,13 +67,30 @@ def test_gaussian_association(ctx, case):
     close(out.amap.cpu().numpy(), ref.A, "channel mean")
     close(out.score.cpu().numpy(), ref.score, "score")
     close(out.w1.cpu().numpy(), ref.W1, "window W1")
+    block = T <= 31  # the automatic tile runs the block walk
     try:
+        if block:
+            for (Ws, Hb) in [(T, 8), (2 * T, 5), (3 * T, 64)]:
+                ctx.set_tile(Ws, Hb, 1, 1)
+                o2 = q.qfca_score_map(ctx, m, bd, amap=True, w1=True, achan=True)
+                torch.cuda.synchronize()
+                for f in ("score", "amap", "w1", "achan"):
+                    assert torch.equal(getattr(out, f), getattr(o2, f)), f"{f} differs with tile {(Ws, Hb)}"
+        col = None
         for (Ws, Hb) in [(16, 8), (40, 13), (7, 100)]:
             ctx.set_tile(Ws, Hb, 1, 0)
             o2 = q.qfca_score_map(ctx, m, bd, amap=True, w1=True, achan=True)
             torch.cuda.synchronize()
-            for f in ("score", "amap", "w1", "achan"):
-                assert torch.equal(getattr(out, f), getattr(o2, f)), f"{f} differs with tile {(Ws, Hb)}"
+            if col is None:
+                col = o2
+                close(o2.achan.cpu().numpy(), ref.Achan, "per-channel maps (column walk)")
+                close(o2.score.cpu().numpy(), ref.score, "score (column walk)")
+                if not block:
+                    for f in ("score", "amap", "w1", "achan"):
+                        assert torch.equal(getattr(out, f), getattr(o2, f)), f"{f} differs with tile {(Ws, Hb)}"
+            else:
+                for f in ("score", "amap", "w1", "achan"):
+                    assert torch.equal(getattr(col, f), getattr(o2, f)), f"{f} differs with tile {(Ws, Hb)}"
     finally:
         ctx.set_tile(0)
 
