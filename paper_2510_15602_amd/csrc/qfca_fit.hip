@@ -33,10 +33,16 @@ __global__ __launch_bounds__(256) void k_mean(const float* __restrict__ X, long 
 
 // Covariance partials: block (tile ta, tile tb >= ta, chunk) accumulates
 // sum_i (x_a - mu_a)(x_b - mu_b) over its pixel chunk for a 64 x 64 tile in
-// FP64 (each thread a 4 x 4 micro-tile).  Partials are reduced over chunks
-// in a fixed order by k_cov_reduce (deterministic).
+// FP64 on the matrix cores: the centred values of a stage are staged in LDS
+// as doubles, and wavefront w computes the 32 x 32 quadrant (w / 2, w % 2)
+// as 2 x 2 blocks of v_mfma_f64_16x16x4 (lane (g, n) gives row n of A and
+// column n of B at pixel g of each group of four; it ends with rows
+// 4 e + g, e = 0 .. 3, of column n: the FP64 form's output order, unlike
+// the FP32 16x16x4 form's 4 g + e).  Partials are reduced over chunks in a fixed order
+// by k_cov_reduce (deterministic).
 constexpr int CT = 64;   // tile side
-constexpr int CK = 16;   // pixels per LDS stage
+constexpr int CK = 16;   // pixels per LDS stage (a multiple of 4)
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_cov_partial(const float* __restrict__ X, int C, long N,
                                                      const double* __restrict__ mu, int ntile,
@@ -49,10 +55,12 @@ __global__ __launch_bounds__(256) void k_cov_partial(const float* __restrict__ X
     const int tb = ta + pair;
     const long i0 = (long)blockIdx.y * chunk;
     const long i1 = min(N, i0 + chunk);
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4];
-    for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    const int qa = (w >> 1) * 32, qb = (w & 1) * 32;
+    dbl4 acc[2][2];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) acc[u][v] = dbl4{0.0, 0.0, 0.0, 0.0};
     for (long ib = i0; ib < i1; ib += CK) {
         for (int t = threadIdx.x; t < CK * CT; t += 256) {
             const int kk = t % CK, row = t / CK;
@@ -62,18 +70,25 @@ __global__ __launch_bounds__(256) void k_cov_partial(const float* __restrict__ X
             Bs[kk][row] = (i < i1 && cb < C) ? (double)X[(size_t)cb * N + i] - mu[cb] : 0.0;
         }
         __syncthreads();
-        for (int kk = 0; kk < CK; ++kk) {
-            double av[4], bv[4];
-            for (int u = 0; u < 4; ++u) av[u] = As[kk][ty * 4 + u];
-            for (int v = 0; v < 4; ++v) bv[v] = Bs[kk][tx * 4 + v];
-            for (int u = 0; u < 4; ++u)
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+#pragma unroll
+        for (int k0 = 0; k0 < CK; k0 += 4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) av[u] = As[k0 + g][qa + 16 * u + n];
+#pragma unroll
+            for (int v = 0; v < 2; ++v) bv[v] = Bs[k0 + g][qb + 16 * v + n];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
         }
         __syncthreads();
     }
     double* out = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * CT * CT;
-    for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v) out[(ty * 4 + u) * CT + tx * 4 + v] = acc[u][v];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v)
+            for (int e = 0; e < 4; ++e) out[(qa + 16 * u + 4 * e + g) * CT + qb + 16 * v + n] = acc[u][v][e];
 }
 
 // One thread per entry of a tile pair (grid: pairs x entry blocks); the
