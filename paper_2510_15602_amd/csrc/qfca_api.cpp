@@ -248,12 +248,13 @@ qfca_status upload_quant(qfca_model m) {
     // device, three roundings: relative error below 3.1e-7 of |t|): with
     // dev = max_m |(e_m - lo) / delta - m| over the stored edges, a value
     // whose t lies farther than dev + (B + 2) * 2.4e-7 from every integer
-    // has bin floor(t) (clamped).  A margin of one half or more disables the
-    // shortcut for the channel.
-    std::vector<float> fastd(C, 1.f);
+    // has bin floor(t) (clamped).  The shortcut is off for a channel whose
+    // margin would be one half or more, or whose 1/delta is zero: its margin
+    // is +infinity, which no distance reaches.
+    std::vector<float> fastd(C, INFINITY);
     for (int c = 0; c < C; ++c) {
         const double dl = m->delta[c];
-        if (!(dl > 0.0) || B < 2) continue;
+        if (!(dl > 0.0) || B < 2 || invd[c] == 0.f) continue;
         double dev = 0.0;
         for (int mm = 1; mm < B; ++mm) {
             const double e = (double)m->edges[(size_t)c * (B - 1) + mm - 1];

@@ -72,7 +72,7 @@ __device__ __forceinline__ void batch_body(BatchHeader* hdr, const BatchJob* job
                 const float vm = ok ? J.pa.mu[i] : 0.f;
                 const float vl = ok ? J.pa.lo[i] : 0.f;
                 const float vi = ok ? J.pa.inv_delta[i] : 0.f;
-                const float vf = ok ? J.pa.fastd[i] : 1.f;
+                const float vf = ok ? J.pa.fastd[i] : INFINITY;
                 smu[i] = vm;
                 slo[i] = vl;
                 sid[i] = vi;

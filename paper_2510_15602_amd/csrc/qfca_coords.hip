@@ -86,7 +86,7 @@ __device__ __forceinline__ void coords_body(const MArgs& a) {
         const bool ok = i < a.k;
         const float vl = ok && a.lo ? a.lo[i] : 0.f;
         const float vi = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
-        const float vf = ok && a.fastd ? a.fastd[i] : 1.f;
+        const float vf = ok && a.fastd ? a.fastd[i] : INFINITY;
         slo[i] = vl;
         sid[i] = vi;
         sfd[i] = vf;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
         const bool ok = i < a.k;
         const float vl = ok && a.lo ? a.lo[i] : 0.f;
         const float vi = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
-        const float vf = ok && a.fastd ? a.fastd[i] : 1.f;
+        const float vf = ok && a.fastd ? a.fastd[i] : INFINITY;
         slo[i] = vl;
         sid[i] = vi;
         sfd[i] = vf;
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
             for (int v = 0; v < 4; ++v) {
                 const float tt = (z[kt][v] - lov[v]) * idv[v];
                 const float near = __builtin_amdgcn_fmed3f(rintf(tt), 1.f, top);
-                const bool dec = (fabsf(tt - near) >= dlv[v]) & (dlv[v] < 0.5f) & (idv[v] != 0.f);
+                const bool dec = fabsf(tt - near) >= dlv[v];  // +infinity: the shortcut is off
                 bq[v] = (uint32_t)__builtin_amdgcn_fmed3f(floorf(tt), 0.f, top);
                 need |= ((!dec) & pxok & (j0 + v < a.k) & (B > 1)) ? (1u << v) : 0u;
             }

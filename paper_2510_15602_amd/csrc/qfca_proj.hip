@@ -72,7 +72,7 @@ __device__ __forceinline__ void proj_prologue(const MArgs& a, int CMAX, float* s
         const float vm = ok ? a.mu[i] : 0.f;
         const float vl = ok && a.lo ? a.lo[i] : 0.f;
         const float vi = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
-        const float vf = ok && a.fastd ? a.fastd[i] : 1.f;
+        const float vf = ok && a.fastd ? a.fastd[i] : INFINITY;
         smu[i] = vm;
         slo[i] = vl;
         sid[i] = vi;
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
         const float vm = ok ? a.mu[i] : 0.f;
         const float vl = ok && a.lo ? a.lo[i] : 0.f;
         const float vi = ok && a.inv_delta ? a.inv_delta[i] : 0.f;
-        const float vf = ok && a.fastd ? a.fastd[i] : 1.f;
+        const float vf = ok && a.fastd ? a.fastd[i] : INFINITY;
         smu[i] = vm;
         slo[i] = vl;
         sid[i] = vi;
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
                 for (int v = 0; v < 4; ++v) {
                     const float tt = (rv[v] - lov[v]) * idv[v];
                     const float near = __builtin_amdgcn_fmed3f(rintf(tt), 1.f, top);
-                    const bool dec = (fabsf(tt - near) >= dlv[v]) & (dlv[v] < 0.5f) & (idv[v] != 0.f);
+                    const bool dec = fabsf(tt - near) >= dlv[v];  // +infinity: the shortcut is off
                     bq[v] = (uint32_t)__builtin_amdgcn_fmed3f(floorf(tt), 0.f, top);
                     need |= ((!dec) & pxok & (c0 + v < a.C)) ? (1u << v) : 0u;
                 }

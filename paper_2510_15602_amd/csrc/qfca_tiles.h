@@ -926,7 +926,7 @@ __device__ __forceinline__ void emit_values(const MArgs& a, int px, const int (&
             // t is decided when it lies at least dl from it, and its bin is
             // then floor(t) clamped to [0, B-1] (NaN is never decided)
             const float near = __builtin_amdgcn_fmed3f(rintf(t), 1.f, top);
-            const bool dec = (fabsf(t - near) >= dl) && (dl < 0.5f) && (idl != 0.f);
+            const bool dec = fabsf(t - near) >= dl;  // +infinity: the shortcut is off
             bq[e] = (int)__builtin_amdgcn_fmed3f(floorf(t), 0.f, top);
             need |= (!dec && valid[e]) ? (1u << e) : 0u;
         }
