@@ -363,33 +363,38 @@ int sym_eig_top(double* A, int n, int k, double* evals, double* vecs) {
             for (int i = 0; i < n; ++i) x[i] /= nr;
         }
     }
-    // back to the basis of A: y = H_0 H_1 ... H_{n-3} x, sign fixed so that the
+    // back to the basis of A: y = H_0 H_1 ... H_{n-3} x for all k vectors at
+    // once, reflector by reflector (each reflector read once, the k vectors
+    // held as rows of Y [n][k] so that the k dot products and updates of a
+    // row run along contiguous memory), then the sign fixed so that the
     // entry of largest magnitude is positive
-    std::vector<double> y(n);
-    for (int j = 0; j < k; ++j) {
-        const double* x = X.data() + (size_t)j * n;
-        for (int i = 0; i < n; ++i) y[i] = x[i];
-        for (int s = n - 3; s >= 0; --s) {
-            if (beta[s] == 0.0) continue;
-            const double* v = H.data() + (size_t)s * n;
-            double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;  // four partial sums
-            int i = s + 1;
-            for (; i + 4 <= n; i += 4) {
-                d0 += v[i] * y[i];
-                d1 += v[i + 1] * y[i + 1];
-                d2 += v[i + 2] * y[i + 2];
-                d3 += v[i + 3] * y[i + 3];
-            }
-            for (; i < n; ++i) d0 += v[i] * y[i];
-            double dot = (d0 + d1) + (d2 + d3);
-            dot *= beta[s];
-            for (int i = s + 1; i < n; ++i) y[i] -= dot * v[i];
+    std::vector<double> Y((size_t)n * k), dots(k);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < k; ++j) Y[(size_t)i * k + j] = X[(size_t)j * n + i];
+    for (int s = n - 3; s >= 0; --s) {
+        if (beta[s] == 0.0) continue;
+        const double* v = H.data() + (size_t)s * n;
+        std::fill(dots.begin(), dots.end(), 0.0);
+        for (int i = s + 1; i < n; ++i) {
+            const double vi = v[i];
+            const double* __restrict__ yi = Y.data() + (size_t)i * k;
+            double* __restrict__ dt = dots.data();
+            for (int j = 0; j < k; ++j) dt[j] += vi * yi[j];
         }
+        for (int j = 0; j < k; ++j) dots[j] *= beta[s];
+        for (int i = s + 1; i < n; ++i) {
+            const double vi = v[i];
+            double* __restrict__ yi = Y.data() + (size_t)i * k;
+            const double* __restrict__ dt = dots.data();
+            for (int j = 0; j < k; ++j) yi[j] -= dt[j] * vi;
+        }
+    }
+    for (int j = 0; j < k; ++j) {
         int arg = 0;
         for (int i = 1; i < n; ++i)
-            if (fabs(y[i]) > fabs(y[arg])) arg = i;
-        const double sg = y[arg] < 0.0 ? -1.0 : 1.0;
-        for (int i = 0; i < n; ++i) vecs[(size_t)i * k + j] = sg * y[i];
+            if (fabs(Y[(size_t)i * k + j]) > fabs(Y[(size_t)arg * k + j])) arg = i;
+        const double sg = Y[(size_t)arg * k + j] < 0.0 ? -1.0 : 1.0;
+        for (int i = 0; i < n; ++i) vecs[(size_t)i * k + j] = sg * Y[(size_t)i * k + j];
     }
     return 0;
 }
