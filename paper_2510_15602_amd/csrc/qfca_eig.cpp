@@ -252,6 +252,60 @@ int tridiag_ql(double* d, double* e, int n, double* ZT) {
     return 0;
 }
 
+// Eigenvalues only of the tridiagonal (d, e): the same shifted QL sweeps as
+// tridiag_ql, carried on the squares e_i^2 of the off-diagonal so that a
+// sweep takes no square root (the root-free form of Pal, Walker and Kahan,
+// as presented in Parlett, The Symmetric Eigenvalue Problem, 1980).  With
+// c and s the squared cosine and sine of a rotation, a sweep from the
+// bottom m of the unreduced block up to its top l carries gamma (the
+// rotated diagonal entry less the shift) and p = gamma^2 / c; the shift is
+// the eigenvalue of the leading 2 x 2 block nearer to d[l], as in
+// tridiag_ql.  e is destroyed; d receives the eigenvalues (unsorted).
+// Returns 0, or -1 if an eigenvalue fails to converge.
+int tridiag_eigvals(double* d, double* e, int n) {
+    const double eps = 2.220446049250313e-16, eps2 = eps * eps;
+    double tnorm = 0.0;
+    for (int i = 0; i < n; ++i) tnorm = std::max(tnorm, fabs(d[i]) + fabs(e[i]));
+    const double tn2 = eps2 * tnorm * tnorm;
+    std::vector<double> e2(n);
+    for (int i = 0; i < n; ++i) e2[i] = e[i] * e[i];
+    for (int l = 0; l < n; ++l) {
+        int iter = 0;
+        for (;;) {
+            // negligible off-diagonal below the block (next to its diagonal
+            // neighbours, or next to the matrix norm, as in tridiag_ql)
+            int m = l;
+            for (; m + 1 < n; ++m)
+                if (e2[m] <= eps2 * fabs(d[m]) * fabs(d[m + 1]) || e2[m] <= tn2) break;
+            if (m == l) break;
+            if (++iter > 100) return -1;
+            const double rte = sqrt(e2[l]);
+            double g = (d[l + 1] - d[l]) / (2.0 * rte);
+            const double rr = fast_hypot(g, 1.0);
+            const double sigma = d[l] - rte / (g + (g >= 0.0 ? rr : -rr));
+            double c = 1.0, sn = 0.0;
+            double gamma = d[m] - sigma;
+            double p = gamma * gamma;
+            for (int i = m - 1; i >= l; --i) {
+                const double bb = e2[i];
+                const double r = p + bb;
+                if (i != m - 1) e2[i + 1] = sn * r;
+                const double oldc = c;
+                c = p / r;
+                sn = bb / r;
+                const double oldgam = gamma;
+                const double alpha = d[i];
+                gamma = c * (alpha - sigma) - sn * oldgam;
+                d[i + 1] = oldgam + (alpha - gamma);
+                p = c != 0.0 ? (gamma * gamma) / c : oldc * bb;
+            }
+            e2[l] = sn * p;
+            d[l] = sigma + gamma;
+        }
+    }
+    return 0;
+}
+
 // One solve of (T - sigma I) x = b for the symmetric tridiagonal T = (d, e)
 // by Gaussian elimination with partial pivoting (the factor has up to two
 // superdiagonals); a zero pivot is replaced by `tiny`.  b is overwritten.
@@ -320,7 +374,7 @@ int sym_eig_top(double* A, int n, int k, double* evals, double* vecs) {
     std::vector<double> d(n), e(n), H((size_t)n * n, 0.0), beta(n, 0.0);
     householder_tridiag_lower(A, n, d.data(), e.data(), H.data(), beta.data());
     std::vector<double> dt(d), et(e);  // T, kept for the inverse iteration
-    if (tridiag_ql(d.data(), e.data(), n, nullptr) != 0) return -1;
+    if (tridiag_eigvals(d.data(), e.data(), n) != 0) return -1;
     std::sort(d.begin(), d.end(), [](double a, double b) { return a > b; });
     for (int j = 0; j < n; ++j) evals[j] = d[j];
     if (k == 0) return 0;
