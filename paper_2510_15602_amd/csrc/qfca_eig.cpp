@@ -4,7 +4,7 @@
 // implicit QL iteration with shifts (Bowdler, Martin, Reinsch and Wilkinson,
 // 1968).  sym_eig accumulates the whole orthogonal transform; sym_eig_top,
 // which the fit uses, keeps the reflectors instead, takes all eigenvalues
-// from QL without vectors, the k leading eigenvectors of the tridiagonal
+// from the root-free form of QL, the k leading eigenvectors of the tridiagonal
 // matrix by inverse iteration (Wilkinson; vectors of close eigenvalues
 // orthogonalised against each other, as in LAPACK's dstein), and applies the
 // reflectors to those k vectors only: O(C^3) for the reduction instead of
