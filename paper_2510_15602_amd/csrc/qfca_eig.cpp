@@ -106,7 +106,11 @@ void householder_tridiag(double* A, int n, double* d, double* e, double* Q, doub
 // the same row), and the rank-2 update A -= v q^T + q v^T touches the stored
 // half only, so a step costs about 4 len^2 operations instead of 6.  The
 // row loops are contiguous; the dot products keep four partial sums.
-void householder_tridiag_lower(double* A, int n, double* d, double* e, double* H, double* beta_out) {
+// Compiled twice, for AVX2 and for the baseline, the first taken at load time
+// where the processor has it (the row loops then run four doubles wide).
+__attribute__((target_clones("avx2", "default"))) void householder_tridiag_lower(double* A, int n, double* d,
+                                                                                 double* e, double* H,
+                                                                                 double* beta_out) {
     for (int i = 0; i < n; ++i) beta_out[i] = 0.0;
     for (int i = 0; i < n; ++i) e[i] = 0.0;
     std::vector<double> v(n), p(n), qv(n);
@@ -358,7 +362,9 @@ double norm2(const double* x, int n) {
 
 }  // namespace
 
-int sym_eig_top(double* A, int n, int k, double* evals, double* vecs) {
+// AVX2 and baseline builds, as householder_tridiag_lower.
+__attribute__((target_clones("avx2", "default"))) int sym_eig_top(double* A, int n, int k, double* evals,
+                                                                 double* vecs) {
     if (n <= 0 || k < 0 || k > n) return -1;
     std::vector<double> A0(A, A + (size_t)n * n);  // for the fallback below
     // When the inverse iteration cannot deliver (a large cluster of zero
