@@ -276,7 +276,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
     MArgs a) {
     constexpr int NS = CMAX / 32;        // first-product K steps (32 channels each)
     constexpr int QS = NS / 4;           // K steps of one quarter (one wavefront's share in k_proj_bf16_mfma)
-    constexpr int SB = 4;                // second-product steps between the block's barriers
+    constexpr int SB = 1;                // second-product steps between the block's barriers
     constexpr int NU = KT / 2;           // second-product K steps (32 components each)
     constexpr int VSZ = CMAX * KT * 16;  // bf16 elements per table
     extern __shared__ __align__(16) unsigned char lds_raw[];
