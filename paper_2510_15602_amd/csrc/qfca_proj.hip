@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void k_proj_bf16_mfma_wide(MArgs a) {
 // ------------------------------------------------------------------------
 // BF16 kernel for the widest maps (CMAX = 512): every wavefront runs whole
 // 16-pixel tiles on its own, all channels in both products, so there are no
-// Z partials to add across wavefronts.  The NW wavefronts of a block (three
+// Z partials to add across wavefronts.  The NW wavefronts of a block (two
 // per SIMD, which hide each other's memory and LDS latency) share the
 // operand tables and the per-channel parameters in LDS and take interleaved
 // tiles of one contiguous run, meeting at bare barriers (see the loop).  Lane (g, n) holds the
@@ -264,8 +264,12 @@ __global__ __launch_bounds__(256) void k_proj_bf16_mfma_wide(MArgs a) {
 //
 // LDS: mu, lo, 1/delta, bin margin [CMAX] each; the two operand tables.
 // Wavefronts per block of k_proj_bf16_solo (a multiple of 4: NW / 4 per SIMD).
+// Eight take 128 pixels a round, one whole 128-byte line of every channel's
+// bins, so with the per-step barriers no line is split between rounds
+// (1024x1024x512, k = 64: eight 0.86 ms, twelve 1.04 ms, sixteen, which
+// spill at 128 registers, 1.71 ms).
 #ifndef SOLO_WAVES
-#define SOLO_WAVES 12
+#define SOLO_WAVES 8
 #endif
 __host__ __device__ inline size_t solo_lds(int CMAX, int KT) {
     return (size_t)16 * CMAX + (size_t)2 * CMAX * KT * 16 * 2;
